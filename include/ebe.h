@@ -1,0 +1,209 @@
+/*
+ * ebe.h -- C ABI of the MI355X element-by-element (EBE) multi-case solver.
+ *
+ * The library computes, on one gfx950 GPU, the hot path of the implicit
+ * low-order unstructured finite-element crust-deformation solver of
+ * Yamaguchi et al. (WACCPD 2017): the EBE product f = sum_i Q_i K_i Q_i^T u
+ * (Section 2, Eq. (3)) on 10-node tetrahedra with isotropic linear
+ * elasticity (Eq. (1a-c)) and per-element moduli, applied to n load cases
+ * at once (Section 3.1), inside the adaptive conjugate-gradient solver of
+ * Algorithm 1 (FP64 outer loop, two-level FP32 multigrid inner loops).
+ * Element matrices are never stored: they are rebuilt from vertex
+ * coordinates and material at every product (Section 2, EBE method).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named *_dev are device pointers (hipMalloc / torch CUDA tensors);
+ *   all others are host pointers.  The caller owns every vector buffer; the
+ *   library only reads inputs and writes outputs during the call's stream work.
+ * - Multi-case vectors use the layout [node][component][rhs], rhs fastest
+ *   (Section 3.1: the case index is the innermost, contiguous loop), so a
+ *   vector of n cases on N nodes holds 3*N*n values.  Quadratic-level vectors
+ *   have N = n_nodes; linear-level (corner-only) vectors have N = n_vertices.
+ * - Buffers must not overlap unless stated.  Device buffers must be aligned
+ *   to their element size.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Calls marked
+ *   "asynchronous" only enqueue work on it; the others synchronise it.
+ * - A mesh handle must be used by one stream at a time.
+ * - No C++ exception crosses this interface.  Every call returns an
+ *   ebe_status; on failure a thread-local message is kept for ebe_last_error().
+ * - nrhs is 1..EBE_MAX_RHS.  Larger case sets are solved as several sets of at
+ *   most 16 cases, as the paper does (Section 5: 368 cases as 23 sets of 16).
+ */
+#ifndef EBE_H
+#define EBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EBE_MAX_RHS 16
+
+typedef int32_t ebe_status;
+#define EBE_OK 0
+#define EBE_NOT_CONVERGED 1      /* result valid but tolerance not reached; see stats */
+#define EBE_ERR_ARG (-1)         /* null pointer, size or enum out of range */
+#define EBE_ERR_INDEX (-2)       /* connectivity index out of range or inconsistent */
+#define EBE_ERR_INVERTED (-3)    /* element with det[x1-x0, x2-x0, x3-x0] <= 0 */
+#define EBE_ERR_CURVED (-4)      /* edge node not at its edge midpoint */
+#define EBE_ERR_MATERIAL (-5)    /* E <= 0, nu outside (-1, 0.5), or non-finite */
+#define EBE_ERR_OOM (-6)         /* device allocation failed */
+#define EBE_ERR_HIP (-7)         /* a HIP runtime call failed */
+#define EBE_ERR_BREAKDOWN (-8)   /* (p, Kp) <= 0 in the outer loop: K not SPD on the free DOFs */
+#define EBE_ERR_NONFINITE (-9)   /* NaN or Inf in an input or in the iteration */
+#define EBE_ERR_NUMBERING (-10)  /* numbering is not vertex-first */
+
+typedef int32_t ebe_dtype;
+#define EBE_F64 0
+#define EBE_F32 1
+
+/* Preconditioner of the outer loop (Algorithm 1(a)). */
+#define EBE_PREC_PCGE 0  /* plain CG with 3x3 block Jacobi ("PCGE", Section 4) */
+#define EBE_PREC_MG2 1   /* adaptive CG: inner CG on the linear mesh, then on the quadratic mesh */
+
+/* Arithmetic of the preconditioner; the outer loop is always FP64. */
+#define EBE_MODE_FP64 0
+#define EBE_MODE_MIXED 1 /* preconditioner (inner loops, EBE products) in FP32 */
+
+typedef struct ebe_mesh ebe_mesh;   /* opaque; owns device copies of the mesh and workspace */
+typedef struct ebe_batch ebe_batch; /* opaque; a set of meshes solved together */
+
+/* Solver options.  ebe_pcg_default_opts() fills the paper's settings:
+ * MG2, MIXED, tol 1e-8, inner tolerances {0.1, 0.05} and maxima {30, 300}
+ * (Section 4, Table 2). */
+typedef struct {
+  int32_t precond;      /* EBE_PREC_* */
+  int32_t mode;         /* EBE_MODE_* */
+  double tol;           /* stop when max_j ||f_j - K u_j|| / ||f_j|| <= tol (unsquared) */
+  int32_t max_outer;    /* outer iteration cap */
+  int32_t check_every;  /* host reads the device convergence flag every k outer iterations */
+  double inner_eps[2];  /* squared relative-residual tolerance of inner level 0 and level 1 */
+  int32_t inner_max[2]; /* inner loops run while i < N, i from 1: at most N-1 steps */
+  int32_t use_x0;       /* 1: u_dev holds the initial guess on entry; 0: start from zero */
+  int32_t coarse_guess; /* 0: u1 = P1^T u as printed; 1: u1 = corner values of u */
+} ebe_pcg_opts;
+
+typedef struct {
+  int32_t outer_iters;
+  int32_t status;          /* same as the return value of the solve */
+  int64_t inner_iters[2];  /* total inner steps on level 0 and level 1 */
+  double max_rel_res;      /* max_j ||r_j|| / ||f_j|| of the recursive residual at exit */
+  double seconds;          /* wall time of the solve, host clock */
+} ebe_pcg_stats;
+
+/* ---- mesh ------------------------------------------------------------- */
+
+/* Create a mesh handle from host arrays (copied; synchronous).
+ * Defines Q_i (connectivity), the coordinates and the per-element material
+ * from which every K_i is rebuilt (Section 2, Eq. (3) and the EBE method).
+ *   xyz       [n_nodes][3] coordinates.
+ *   conn10    [n_elem][10] node ids: corners 0..3, then edge nodes of
+ *             edges (0,1),(1,2),(0,2),(0,3),(1,3),(2,3).
+ *   n_vertices  nodes 0..n_vertices-1 must be exactly the corners
+ *             (vertex-first numbering; checked, never reordered).
+ *   young, poisson  [n_elem] isotropic moduli E_e, nu_e.
+ *   dof_fixed [n_nodes][3] 1 = homogeneous Dirichlet DOF, or NULL (none).
+ * Checks: index range and numbering, det > 0, edge nodes at midpoints
+ * (|x_edge - midpoint| <= 1e-10 * longest edge), material range, finiteness.
+ * n_nodes must be below 2^28.  On error *out is set to NULL. */
+ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertices,
+                           const int32_t* conn10, int64_t n_elem,
+                           const double* young, const double* poisson,
+                           const uint8_t* dof_fixed, void* stream, ebe_mesh** out);
+
+/* Replace the per-element moduli from device arrays [n_elem] (asynchronous
+ * apart from a range check that synchronises the stream). */
+ebe_status ebe_mesh_set_material(ebe_mesh* mesh, const double* young_dev,
+                                 const double* poisson_dev, void* stream);
+
+/* Sizes of a mesh; any out pointer may be NULL. */
+ebe_status ebe_mesh_info(const ebe_mesh* mesh, int64_t* n_nodes, int64_t* n_vertices,
+                         int64_t* n_elem);
+
+void ebe_mesh_destroy(ebe_mesh* mesh);
+
+/* ---- operators (asynchronous) ---------------------------------------- */
+
+/* y = K x for nrhs cases (Section 2, Eq. (3)), K rebuilt element by element.
+ * x_dev, y_dev: [n_nodes][3][nrhs] of dtype (double or float).  y is
+ * overwritten.  apply_bc = 1 computes y = P K P x, P zeroing fixed DOFs.
+ * FP32 sums in FP32 (element geometry is formed from FP64 coordinates). */
+ebe_status ebe_matvec(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* x_dev,
+                      void* y_dev, int32_t apply_bc, void* stream);
+
+/* y += K x: the same product accumulated into y (no clearing pass), e.g. for
+ * residuals r = K u - f with y holding -f on entry.  Same arguments. */
+ebe_status ebe_matvec_add(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* x_dev,
+                          void* y_dev, int32_t apply_bc, void* stream);
+
+/* y = K1 x on the linear (4-node) mesh made of the corners, the coarse
+ * operator of inner loop level 1 (Section 2, multigrid; Table 4 "1st order EBE").
+ * x_dev, y_dev: [n_vertices][3][nrhs]. */
+ebe_status ebe_matvec_p1(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* x_dev,
+                         void* y_dev, int32_t apply_bc, void* stream);
+
+/* Grid transfers between the quadratic mesh and the corner-only linear mesh
+ * (Algorithm 1(a), P1 and its transpose).  prolong: y[n_nodes] = P1 x[n_vertices]
+ * (corner copied, edge node = mean of its two corners); restrict:
+ * y[n_vertices] = P1^T x[n_nodes].  Fixed DOFs of y are zeroed when apply_bc = 1. */
+ebe_status ebe_prolong_p1(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* x_dev,
+                          void* y_dev, int32_t apply_bc, void* stream);
+ebe_status ebe_restrict_p1(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* x_dev,
+                           void* y_dev, int32_t apply_bc, void* stream);
+
+/* 3x3 block Jacobi of Algorithm 1 ("diag[ ]"): level 0 = quadratic K, level 1
+ * = linear K1.  Blocks are the nodal 3x3 diagonal blocks of P K P with fixed
+ * rows/columns set to identity, formed and inverted in FP64.
+ *   ebe_diag_blocks: writes the (uninverted) blocks, row-major [N][9] double.
+ *   ebe_block_jacobi: y = M^-1 x, x/y [N][3][nrhs] of dtype. */
+ebe_status ebe_diag_blocks(ebe_mesh* mesh, int32_t level, double* blocks_dev, void* stream);
+ebe_status ebe_block_jacobi(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs,
+                            const void* x_dev, void* y_dev, void* stream);
+
+/* ---- solver ----------------------------------------------------------- */
+
+void ebe_pcg_default_opts(ebe_pcg_opts* opts);
+
+/* Solve P K P u_j = P f_j for nrhs cases (Eq. (2)) with the adaptive CG of
+ * Algorithm 1 (or PCGE).  f_dev, u_dev: [n_nodes][3][nrhs] double; u is
+ * written (fixed DOFs set to 0).  opts NULL = defaults; stats may be NULL.
+ * Synchronises the stream at every convergence check and at exit.
+ * Returns EBE_OK, EBE_NOT_CONVERGED (u holds the last iterate),
+ * EBE_ERR_BREAKDOWN or EBE_ERR_NONFINITE. */
+ebe_status ebe_pcg_solve(ebe_mesh* mesh, int32_t nrhs, const double* f_dev, double* u_dev,
+                         const ebe_pcg_opts* opts, ebe_pcg_stats* stats, void* stream);
+
+/* ---- adjoint (extension: inverse analysis, Section 5) ------------------ */
+
+/* Per-element gradient of a misfit with respect to E_e, given the forward
+ * states u_c and adjoint states lambda_c (K lambda_c = dL/du_c):
+ *   g_e = - sum_c lambda_{c,e}^T (K_e / E_e) u_{c,e}      (K_e is linear in E_e).
+ * u_dev, lam_dev: [n_nodes][3][nrhs] of dtype; g_dev: [n_elem] of dtype,
+ * overwritten.  No scatter: each element writes its own entry (asynchronous). */
+ebe_status ebe_adjoint_grad(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* u_dev,
+                            const void* lam_dev, void* g_dev, void* stream);
+
+/* ---- batches: many meshes / case sets solved together ------------------ */
+
+/* A batch runs the solves of several meshes, each with its own nrhs, on one
+ * stream, interleaving their iterations so that small meshes share the GPU
+ * (Section 5 solves case sets one after another; here they overlap). */
+ebe_status ebe_batch_create(ebe_mesh* const* meshes, int32_t n_mesh, const int32_t* nrhs,
+                            ebe_batch** out);
+ebe_status ebe_batch_solve(ebe_batch* batch, const double* const* f_dev, double* const* u_dev,
+                           const ebe_pcg_opts* opts, ebe_pcg_stats* stats, void* stream);
+void ebe_batch_destroy(ebe_batch* batch);
+
+/* ---- diagnostics ------------------------------------------------------- */
+
+const char* ebe_status_string(ebe_status status);
+const char* ebe_last_error(void);   /* thread-local detail of the last failure */
+const char* ebe_build_info(void);   /* target architecture and build flags */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBE_H */

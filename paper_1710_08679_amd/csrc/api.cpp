@@ -1,0 +1,147 @@
+// C-ABI entry points of the operators: EBE products, grid transfers, block
+// Jacobi and the adjoint element gradient.  Argument checking lives here;
+// the kernels assume checked arguments.
+#include <hip/hip_runtime.h>
+
+#include "ebe_internal.h"
+
+using namespace ebe;
+
+namespace {
+
+ebe_status check_common(const char* fn, const ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x,
+                        const void* y) {
+  if (!m || !x || !y) {
+    set_error("%s: null argument", fn);
+    return EBE_ERR_ARG;
+  }
+  if (dt != EBE_F64 && dt != EBE_F32) {
+    set_error("%s: dtype %d is not EBE_F64 or EBE_F32", fn, dt);
+    return EBE_ERR_ARG;
+  }
+  if (nrhs < 1 || nrhs > EBE_MAX_RHS) {
+    set_error("%s: nrhs %d outside 1..%d", fn, nrhs, EBE_MAX_RHS);
+    return EBE_ERR_ARG;
+  }
+  if (x == y) {
+    set_error("%s: input and output must not alias", fn);
+    return EBE_ERR_ARG;
+  }
+  return EBE_OK;
+}
+
+ebe_status hip_status(const char* fn, hipError_t e) {
+  if (e == hipSuccess) return EBE_OK;
+  set_error("%s: %s", fn, hipGetErrorString(e));
+  return EBE_ERR_HIP;
+}
+
+}  // namespace
+
+namespace ebe {
+
+// Form and invert the 3x3 block-Jacobi blocks of both levels (once per material).
+ebe_status ensure_blocks(ebe_mesh* m, hipStream_t s) {
+  if (m->minv_ready) return EBE_OK;
+  DBuf tmp;
+  ebe_status st = tmp.alloc(size_t(m->n_nodes) * 6 * sizeof(double));
+  if (st != EBE_OK) return st;
+  for (int level = 0; level < 2; ++level) {
+    const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+    if ((st = m->minv64[level].alloc(size_t(n) * 6 * sizeof(double))) != EBE_OK) return st;
+    if ((st = m->minv32[level].alloc(size_t(n) * 6 * sizeof(float))) != EBE_OK) return st;
+    EBE_TRY_HIP(launch_diag_blocks(m, level, tmp.as<double>(), s));
+    EBE_TRY_HIP(launch_invert_blocks(m, level, tmp.as<double>(), m->minv64[level].as<double>(),
+                                     m->minv32[level].as<float>(), s));
+  }
+  // tmp is freed at scope exit; make sure the kernels that read it are done
+  EBE_TRY_HIP(hipStreamSynchronize(s));
+  m->minv_ready = true;
+  return EBE_OK;
+}
+
+}  // namespace ebe
+
+extern "C" {
+
+ebe_status ebe_matvec(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, int32_t apply_bc,
+                      void* stream) {
+  ebe_status st = check_common("ebe_matvec", m, dt, nrhs, x, y);
+  if (st != EBE_OK) return st;
+  return hip_status("ebe_matvec", launch_ebe_p2(m, dt, nrhs, x, y, apply_bc && m->has_bc,
+                                                static_cast<hipStream_t>(stream)));
+}
+
+ebe_status ebe_matvec_add(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, int32_t apply_bc,
+                          void* stream) {
+  ebe_status st = check_common("ebe_matvec_add", m, dt, nrhs, x, y);
+  if (st != EBE_OK) return st;
+  return hip_status("ebe_matvec_add", launch_ebe(m, 2, dt, nrhs, x, y, apply_bc && m->has_bc, false, nullptr,
+                                                 static_cast<hipStream_t>(stream)));
+}
+
+ebe_status ebe_matvec_p1(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, int32_t apply_bc,
+                         void* stream) {
+  ebe_status st = check_common("ebe_matvec_p1", m, dt, nrhs, x, y);
+  if (st != EBE_OK) return st;
+  return hip_status("ebe_matvec_p1", launch_ebe_p1(m, dt, nrhs, x, y, apply_bc && m->has_bc,
+                                                   static_cast<hipStream_t>(stream)));
+}
+
+ebe_status ebe_prolong_p1(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, int32_t apply_bc,
+                          void* stream) {
+  ebe_status st = check_common("ebe_prolong_p1", m, dt, nrhs, x, y);
+  if (st != EBE_OK) return st;
+  return hip_status("ebe_prolong_p1", launch_prolong(m, dt, nrhs, x, y, apply_bc && m->has_bc,
+                                                     static_cast<hipStream_t>(stream)));
+}
+
+ebe_status ebe_restrict_p1(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, int32_t apply_bc,
+                           void* stream) {
+  ebe_status st = check_common("ebe_restrict_p1", m, dt, nrhs, x, y);
+  if (st != EBE_OK) return st;
+  return hip_status("ebe_restrict_p1", launch_restrict(m, dt, nrhs, x, y, apply_bc && m->has_bc,
+                                                       static_cast<hipStream_t>(stream)));
+}
+
+ebe_status ebe_diag_blocks(ebe_mesh* m, int32_t level, double* blocks, void* stream) {
+  if (!m || !blocks || (level != 0 && level != 1)) {
+    set_error("ebe_diag_blocks: null argument or level not 0/1");
+    return EBE_ERR_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  DBuf tmp;
+  ebe_status st = tmp.alloc(size_t(n) * 6 * sizeof(double));
+  if (st != EBE_OK) return st;
+  EBE_TRY_HIP(launch_diag_blocks(m, level, tmp.as<double>(), s));
+  EBE_TRY_HIP(launch_expand_blocks(n, tmp.as<double>(), blocks, s));
+  EBE_TRY_HIP(hipStreamSynchronize(s));
+  return EBE_OK;
+}
+
+ebe_status ebe_block_jacobi(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, const void* x, void* y,
+                            void* stream) {
+  ebe_status st = check_common("ebe_block_jacobi", m, dt, nrhs, x, y);
+  if (st != EBE_OK) return st;
+  if (level != 0 && level != 1) {
+    set_error("ebe_block_jacobi: level %d not 0/1", level);
+    return EBE_ERR_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = ensure_blocks(m, s)) != EBE_OK) return st;
+  return hip_status("ebe_block_jacobi", launch_bjacobi(m, level, dt, nrhs, x, y, s));
+}
+
+ebe_status ebe_adjoint_grad(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* u, const void* lam, void* g,
+                            void* stream) {
+  ebe_status st = check_common("ebe_adjoint_grad", m, dt, nrhs, u, g);
+  if (st != EBE_OK) return st;
+  if (!lam || lam == g) {
+    set_error("ebe_adjoint_grad: lam is NULL or aliases g");
+    return EBE_ERR_ARG;
+  }
+  return hip_status("ebe_adjoint_grad", launch_adjoint(m, dt, nrhs, u, lam, g, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

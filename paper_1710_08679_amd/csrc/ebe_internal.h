@@ -1,0 +1,122 @@
+// Internal declarations of the EBE library: the mesh handle, device buffers,
+// error reporting and the kernel launchers shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ebe.h"
+
+namespace ebe {
+
+// Connectivity words carry the node id in the low 28 bits and the node's
+// Dirichlet flags (x, y, z) in bits 28..30, so that a kernel that gathers a
+// node also knows which of its DOFs are fixed without a second load.
+constexpr int32_t kIdxBits = 28;
+constexpr int32_t kIdxMask = (1 << kIdxBits) - 1;
+
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
+#define EBE_TRY_HIP(call)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      ::ebe::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),    \
+                       __FILE__, __LINE__);                                      \
+      return EBE_ERR_HIP;                                                        \
+    }                                                                            \
+  } while (0)
+
+// Owned device allocation.
+class DBuf {
+ public:
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  ebe_status alloc(size_t bytes);        // no-op when already at least this large
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p_); }
+  size_t bytes() const { return n_; }
+ private:
+  void* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+// Solver workspace; grown to the largest nrhs seen.
+struct Workspace {
+  int nrhs_cap = 0;
+  // FP64 outer vectors [N][3][nrhs]
+  DBuf r, p, q, z;
+  // preconditioner vectors (FP32 or FP64) on level 0 and level 1
+  DBuf rb, ub, e0, p0, q0;
+  DBuf r1, u1, e1, p1, q1;
+  // per-column scalars and reduction partials
+  DBuf scal;      // double scalars (see solver.cpp for the slots)
+  DBuf partials;  // block partial sums
+  DBuf flags;     // int32 device flags
+  DBuf counter;   // int32/uint32 arrival counters for last-block reductions
+  int* host_flags = nullptr;  // pinned host mirror
+};
+
+}  // namespace ebe
+
+struct ebe_mesh {
+  int64_t n_nodes = 0, n_vertices = 0, n_elem = 0;
+  bool has_bc = false;
+  int device = 0;
+  ebe::DBuf conn;       // int32 [E][10], packed (see kIdxBits)
+  ebe::DBuf xv;         // double4 [Nv] corner coordinates (w unused)
+  ebe::DBuf lame64;     // double2 [E] (lambda, mu)
+  ebe::DBuf lame32;     // float2  [E]
+  ebe::DBuf young;      // double [E]
+  ebe::DBuf poisson;    // double [E]
+  ebe::DBuf fix;        // uint8  [N] bit c = DOF c fixed
+  ebe::DBuf edge_ends;  // int32 [N-Nv][2]
+  ebe::DBuf v2e_off;    // int32 [Nv+1] corner -> incident edge nodes (CSR)
+  ebe::DBuf v2e_idx;    // int32 [2 (N-Nv)]
+  // 3x3 block Jacobi: inverted symmetric blocks (xx yy zz yz zx xy), per level
+  ebe::DBuf minv64[2], minv32[2];
+  bool minv_ready = false;
+  ebe::Workspace ws;
+};
+
+namespace ebe {
+
+// ---- kernel launchers (ebe_kernels.hip) -----------------------------------
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_ebe_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y,
+                         bool bc, hipStream_t s);
+hipError_t launch_ebe_p1(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y,
+                         bool bc, hipStream_t s);
+// general form: order 2 (quadratic) or 1 (linear); zero_first clears y; the
+// kernel does nothing when gate is non-null and *gate == 0 on the device.
+hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,
+                      bool zero_first, const int* gate, hipStream_t s);
+hipError_t launch_diag_blocks(const ebe_mesh* m, int level, double* blk6, hipStream_t s);
+hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6, double* inv64,
+                                float* inv32, hipStream_t s);
+hipError_t launch_expand_blocks(int64_t n, const double* blk6, double* out9, hipStream_t s);
+hipError_t launch_lame(const ebe_mesh* m, hipStream_t s);
+hipError_t launch_check_material(const double* young, const double* poisson, int64_t n, int* bad,
+                                 hipStream_t s);
+
+// ---- vector kernels (ebe_vec.hip) -----------------------------------------
+hipError_t launch_prolong(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y,
+                          bool bc, hipStream_t s);
+hipError_t launch_restrict(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y,
+                           bool bc, hipStream_t s);
+hipError_t launch_bjacobi(const ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const void* x,
+                          void* y, hipStream_t s);
+
+// ---- adjoint (ebe_adjoint.hip) ---------------------------------------------
+hipError_t launch_adjoint(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* u,
+                          const void* lam, void* g, hipStream_t s);
+
+ebe_status ensure_blocks(ebe_mesh* m, hipStream_t s);
+
+}  // namespace ebe

@@ -1,0 +1,161 @@
+// Element operators of straight-sided tetrahedra, applied without forming
+// the element matrix (Section 2, EBE method: K_i is rebuilt from the corner
+// coordinates and the material at every product).
+//
+// Quadratic (10-node) element.  With barycentric coordinates L_k and their
+// constant gradients G_k, the displacement gradient of a quadratic field is
+// linear in L:  grad u = sum_k L_k H_k  with
+//     H_k = 4 sum_{m != k} (u_{km} - u_k) (x) G_m  -  sum_{i>=1} (u_i - u_0) (x) G_i,
+// where u_{km} is the edge node between corners k and m.  The stress is
+// sigma = sum_k L_k S_k with S_k = lambda tr(H_k) I + 2 mu sym(H_k), and
+// int L_k L_l dV = V (1 + delta_kl) / 20 turns the nodal forces
+// f_a = int sigma grad N_a dV into
+//     corner i:        f_i  = (4 S'_i - S') G_i
+//     edge (k, m):     f_km = 4 [(S'_m + S') G_k + (S'_k + S') G_m]
+// with S'_k = (V/20) S_k and S' = sum_k S'_k.  This equals K_e u_e of the
+// isoparametric B^T D B integral exactly (to rounding) for straight elements.
+//
+// Symmetric tensors are stored as (xx, yy, zz, yz, zx, xy); strains carry
+// engineering shears (yz = du_y/dz + du_z/dy).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ebe {
+
+#define EBE_HD __host__ __device__ __forceinline__
+
+// local node of the edge between corners k != m (VTK quadratic-tetra order:
+// edges (0,1), (1,2), (0,2), (0,3), (1,3), (2,3) are local nodes 4..9)
+EBE_HD constexpr int edge_node(int k, int m) {
+  return (k > m) ? edge_node(m, k) : (k == 0 ? (m == 1 ? 4 : (m == 2 ? 6 : 7)) : (k == 1 ? (m == 2 ? 5 : 8) : 9));
+}
+EBE_HD constexpr int edge_end(int q, int side) {
+  return side == 0 ? (q == 0 ? 0 : q == 1 ? 1 : q == 2 ? 0 : q == 3 ? 0 : q == 4 ? 1 : 2)
+                   : (q == 0 ? 1 : q == 1 ? 2 : q == 2 ? 2 : 3);
+}
+
+// Barycentric gradients G[4][3] and volume of the corner tetrahedron.  Edge
+// vectors are formed in FP64 (coordinates are FP64), the rest in T.
+template <typename T>
+EBE_HD T tet_geometry(const double4& p0, const double4& p1, const double4& p2,
+                                          const double4& p3, T G[4][3]) {
+  const T a0 = T(p1.x - p0.x), a1 = T(p1.y - p0.y), a2 = T(p1.z - p0.z);
+  const T b0 = T(p2.x - p0.x), b1 = T(p2.y - p0.y), b2 = T(p2.z - p0.z);
+  const T c0 = T(p3.x - p0.x), c1 = T(p3.y - p0.y), c2 = T(p3.z - p0.z);
+  // rows of the inverse Jacobian: (b x c, c x a, a x b) / det
+  const T bc0 = b1 * c2 - b2 * c1, bc1 = b2 * c0 - b0 * c2, bc2 = b0 * c1 - b1 * c0;
+  const T ca0 = c1 * a2 - c2 * a1, ca1 = c2 * a0 - c0 * a2, ca2 = c0 * a1 - c1 * a0;
+  const T ab0 = a1 * b2 - a2 * b1, ab1 = a2 * b0 - a0 * b2, ab2 = a0 * b1 - a1 * b0;
+  const T det = a0 * bc0 + a1 * bc1 + a2 * bc2;
+  const T inv = T(1) / det;
+  G[1][0] = bc0 * inv; G[1][1] = bc1 * inv; G[1][2] = bc2 * inv;
+  G[2][0] = ca0 * inv; G[2][1] = ca1 * inv; G[2][2] = ca2 * inv;
+  G[3][0] = ab0 * inv; G[3][1] = ab1 * inv; G[3][2] = ab2 * inv;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) G[0][d] = -(G[1][d] + G[2][d] + G[3][d]);
+  return det * T(1.0 / 6.0);
+}
+
+// w += engineering strain of the outer product d (x) g
+template <typename T>
+EBE_HD void acc_eng(T w[6], const T d[3], const T g[3]) {
+  w[0] += d[0] * g[0];
+  w[1] += d[1] * g[1];
+  w[2] += d[2] * g[2];
+  w[3] += d[1] * g[2] + d[2] * g[1];
+  w[4] += d[2] * g[0] + d[0] * g[2];
+  w[5] += d[0] * g[1] + d[1] * g[0];
+}
+
+// out = P g for symmetric P
+template <typename T>
+EBE_HD void sym_mv(const T P[6], const T g[3], T out[3]) {
+  out[0] = P[0] * g[0] + P[5] * g[1] + P[4] * g[2];
+  out[1] = P[5] * g[0] + P[1] * g[1] + P[3] * g[2];
+  out[2] = P[4] * g[0] + P[3] * g[1] + P[2] * g[2];
+}
+
+// stress (scaled) from engineering strain: cl = lambda * s, cm = mu * s
+template <typename T>
+EBE_HD void stress(const T e[6], T cl, T cm, T S[6]) {
+  const T tr = e[0] + e[1] + e[2];
+  const T cm2 = cm + cm;
+  S[0] = cl * tr + cm2 * e[0];
+  S[1] = cl * tr + cm2 * e[1];
+  S[2] = cl * tr + cm2 * e[2];
+  S[3] = cm * e[3];
+  S[4] = cm * e[4];
+  S[5] = cm * e[5];
+}
+
+// f = K_e u for a straight 10-node tetrahedron; cl = lambda V / 20, cm = mu V / 20.
+template <typename T>
+EBE_HD void p2_forces(const T G[4][3], T cl, T cm, const T u[10][3], T f[10][3]) {
+  T a6[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int i = 1; i < 4; ++i) {
+    const T d[3] = {u[i][0] - u[0][0], u[i][1] - u[0][1], u[i][2] - u[0][2]};
+    acc_eng(a6, d, G[i]);
+  }
+  T S[4][6];
+  T Ssum[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    T w6[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if (m == k) continue;
+      const int j = edge_node(k, m);
+      const T d[3] = {u[j][0] - u[k][0], u[j][1] - u[k][1], u[j][2] - u[k][2]};
+      acc_eng(w6, d, G[m]);
+    }
+    T e6[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e6[c] = T(4) * w6[c] - a6[c];
+    stress(e6, cl, cm, S[k]);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Ssum[c] += S[k][c];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    T P[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) P[c] = T(4) * S[i][c] - Ssum[c];
+    sym_mv(P, G[i], f[i]);
+  }
+  // T'_k = 4 (S'_k + S'), reusing S
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) S[k][c] = T(4) * (S[k][c] + Ssum[c]);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int k = edge_end(q, 0), m = edge_end(q, 1);
+    T t1[3], t2[3];
+    sym_mv(S[m], G[k], t1);
+    sym_mv(S[k], G[m], t2);
+    f[4 + q][0] = t1[0] + t2[0];
+    f[4 + q][1] = t1[1] + t2[1];
+    f[4 + q][2] = t1[2] + t2[2];
+  }
+}
+
+// f = K1_e u for a 4-node tetrahedron (constant strain); cl = lambda V, cm = mu V.
+template <typename T>
+EBE_HD void p1_forces(const T G[4][3], T cl, T cm, const T u[4][3], T f[4][3]) {
+  T e6[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int i = 1; i < 4; ++i) {
+    const T d[3] = {u[i][0] - u[0][0], u[i][1] - u[0][1], u[i][2] - u[0][2]};
+    acc_eng(e6, d, G[i]);
+  }
+  T S[6];
+  stress(e6, cl, cm, S);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) sym_mv(S, G[i], f[i]);
+}
+
+}  // namespace ebe

@@ -1,0 +1,248 @@
+// Host side of the multi-case solver: Algorithm 1 of the paper.
+//
+//  (a) outer loop, FP64: flexible CG whose preconditioner is a rough inner
+//      solve, stopped when max_j ||r_j|| / ||f_j|| <= tol;
+//  (b) inner loops: block-Jacobi CG to a squared relative residual eps or N
+//      steps, first on the linear mesh made of the corners (level 1), then on
+//      the quadratic mesh (level 0), in FP32 (MIXED) or FP64.
+//  PCGE (Section 4) is the outer loop with z = M^-1 r instead of lines 8-17.
+//
+// All per-case scalars live on the device (solver_kernels.hip).  The host
+// enqueues iterations and reads the loop flags after a few of them; kernels
+// enqueued past convergence see the cleared flag and return at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "ebe_internal.h"
+#include "solver_state.h"
+
+using namespace ebe;
+
+namespace {
+
+constexpr int kMaxBlocks = 1024;
+
+struct Bufs {
+  double *r, *p, *q, *z;  // outer, [N][3][n] FP64
+  void *rb, *ub, *e0, *p0, *q0;  // level 0
+  void *r1, *u1, *e1, *p1, *q1;  // level 1
+};
+
+ebe_status ensure_workspace(ebe_mesh* m, int nr) {
+  Workspace& w = m->ws;
+  const size_t v0 = size_t(m->n_nodes) * 3 * nr * sizeof(double);
+  const size_t v1 = size_t(m->n_vertices) * 3 * nr * sizeof(double);
+  ebe_status st = EBE_OK;
+  DBuf* outer[] = {&w.r, &w.p, &w.q, &w.z, &w.rb, &w.ub, &w.e0, &w.p0, &w.q0};
+  for (DBuf* b : outer)
+    if ((st = b->alloc(v0)) != EBE_OK) return st;
+  DBuf* coarse[] = {&w.r1, &w.u1, &w.e1, &w.p1, &w.q1};
+  for (DBuf* b : coarse)
+    if ((st = b->alloc(v1)) != EBE_OK) return st;
+  if ((st = w.scal.alloc(sizeof(SolverScalars))) != EBE_OK) return st;
+  if ((st = w.partials.alloc(size_t(kMaxBlocks) * 3 * EBE_MAX_RHS * sizeof(double))) != EBE_OK) return st;
+  if ((st = w.counter.alloc(64)) != EBE_OK) return st;
+  if (!w.host_flags) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&w.host_flags), sizeof(SolverScalars), 0);
+    if (e != hipSuccess) {
+      w.host_flags = nullptr;
+      set_error("hipHostMalloc failed: %s", hipGetErrorString(e));
+      return EBE_ERR_OOM;
+    }
+  }
+  w.nrhs_cap = std::max(w.nrhs_cap, nr);
+  return EBE_OK;
+}
+
+// Copy the scalar block to pinned host memory and wait for the stream.
+ebe_status read_scalars(ebe_mesh* m, hipStream_t s, SolverScalars** out) {
+  SolverScalars* h = reinterpret_cast<SolverScalars*>(m->ws.host_flags);
+  EBE_TRY_HIP(hipMemcpyAsync(h, m->ws.scal.as<void>(), sizeof(SolverScalars), hipMemcpyDeviceToHost, s));
+  EBE_TRY_HIP(hipStreamSynchronize(s));
+  *out = h;
+  return EBE_OK;
+}
+
+#define EBE_K(call)                                        \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) {                                \
+      set_error("%s: %s", #call, hipGetErrorString(e_));   \
+      return EBE_ERR_HIP;                                  \
+    }                                                      \
+  } while (0)
+
+template <typename T>
+constexpr ebe_dtype dtype_of() {
+  return sizeof(T) == 8 ? EBE_F64 : EBE_F32;
+}
+
+// Algorithm 1(b) on one level: approximately solve A u = r starting from u.
+template <typename T>
+ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int nr, double eps, int nmax,
+                       SolverState& st, hipStream_t s) {
+  const int order = level == 0 ? 2 : 1;
+  InnerScalars* din = &st.sc->inner[level];
+  EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, u, q, true, true, &st.sc->outer_active, s));
+  EBE_K(sk_inner_init<T>(m, level, r, q, e, nr, eps, nmax, st, s));
+  int enq = 0;
+  int chunk = level == 0 ? 3 : 4;
+  while (enq < nmax - 1) {
+    const int k = std::min(chunk, nmax - 1 - enq);
+    for (int c = 0; c < k; ++c) {
+      EBE_K(sk_inner_p<T>(m, level, e, p, q, nr, st, s));
+      EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, p, q, true, false, &din->active, s));
+      EBE_K(sk_inner_alpha<T>(m, level, p, q, nr, st, s));
+      EBE_K(sk_inner_update<T>(m, level, e, u, q, p, nr, eps, nmax, st, s));
+    }
+    enq += k;
+    SolverScalars* h = nullptr;
+    ebe_status rs = read_scalars(m, s, &h);
+    if (rs != EBE_OK) return rs;
+    if (!h->inner[level].active) break;
+    chunk = std::min(chunk * 2, 32);
+  }
+  return EBE_OK;
+}
+
+// Lines 9-18 of Algorithm 1(a): z from r through both inner levels.
+template <typename T>
+ebe_status mg2_precondition(ebe_mesh* m, int nr, const ebe_pcg_opts& o, const Bufs& b, SolverState& st,
+                            hipStream_t s) {
+  T* rb = static_cast<T*>(b.rb);
+  T* ub = static_cast<T*>(b.ub);
+  T* r1 = static_cast<T*>(b.r1);
+  T* u1 = static_cast<T*>(b.u1);
+  const ebe_dtype dt = dtype_of<T>();
+  EBE_K(sk_cast_bj<T>(m, b.r, rb, ub, nr, st, s));            // r_bar <= r ; u_bar <= M0^-1 r_bar
+  EBE_K(launch_restrict(m, dt, nr, rb, r1, true, s));          // r1 <= P1^T r_bar
+  if (o.coarse_guess == 1) {
+    EBE_K(hipMemcpyAsync(u1, ub, size_t(m->n_vertices) * 3 * nr * sizeof(T), hipMemcpyDeviceToDevice, s));
+  } else {
+    EBE_K(launch_restrict(m, dt, nr, ub, u1, true, s));        // u1 <= P1^T u_bar
+  }
+  ebe_status rs = inner_solve<T>(m, 1, r1, u1, static_cast<T*>(b.e1), static_cast<T*>(b.p1),
+                                 static_cast<T*>(b.q1), nr, o.inner_eps[1], o.inner_max[1], st, s);
+  if (rs != EBE_OK) return rs;
+  EBE_K(launch_prolong(m, dt, nr, u1, ub, true, s));           // u_bar <= P1 u1
+  rs = inner_solve<T>(m, 0, rb, ub, static_cast<T*>(b.e0), static_cast<T*>(b.p0), static_cast<T*>(b.q0), nr,
+                      o.inner_eps[0], o.inner_max[0], st, s);
+  if (rs != EBE_OK) return rs;
+  EBE_K(sk_outer_z_cast<T>(m, ub, b.r, b.q, b.z, nr, st, s));  // z <= u_bar ; (z,q), (z,r)
+  return EBE_OK;
+}
+
+ebe_status check_opts(const ebe_pcg_opts& o) {
+  if ((o.precond != EBE_PREC_PCGE && o.precond != EBE_PREC_MG2) ||
+      (o.mode != EBE_MODE_FP64 && o.mode != EBE_MODE_MIXED) || !(o.tol > 0.0) || o.max_outer < 1 ||
+      o.check_every < 1 || o.inner_max[0] < 1 || o.inner_max[1] < 1 || !(o.inner_eps[0] >= 0.0) ||
+      !(o.inner_eps[1] >= 0.0) || (o.coarse_guess != 0 && o.coarse_guess != 1)) {
+    set_error("ebe_pcg_solve: invalid options");
+    return EBE_ERR_ARG;
+  }
+  return EBE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ebe_pcg_default_opts(ebe_pcg_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precond = EBE_PREC_MG2;
+  o->mode = EBE_MODE_MIXED;
+  o->tol = 1e-8;
+  o->max_outer = 10000;
+  o->check_every = 8;
+  o->inner_eps[0] = 0.1;   // Table 2, level 0
+  o->inner_eps[1] = 0.05;  // Table 2, level 1
+  o->inner_max[0] = 30;
+  o->inner_max[1] = 300;
+  o->use_x0 = 0;
+  o->coarse_guess = 0;
+}
+
+ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, const ebe_pcg_opts* opts,
+                         ebe_pcg_stats* stats, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (!m || !f || !u || f == u) {
+    set_error("ebe_pcg_solve: null or aliasing argument");
+    return EBE_ERR_ARG;
+  }
+  if (nr < 1 || nr > EBE_MAX_RHS) {
+    set_error("ebe_pcg_solve: nrhs %d outside 1..%d", nr, EBE_MAX_RHS);
+    return EBE_ERR_ARG;
+  }
+  ebe_pcg_opts o;
+  if (opts) o = *opts;
+  else ebe_pcg_default_opts(&o);
+  ebe_status st_ = check_opts(o);
+  if (st_ != EBE_OK) return st_;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st_ = ensure_blocks(m, s)) != EBE_OK) return st_;
+  if ((st_ = ensure_workspace(m, nr)) != EBE_OK) return st_;
+
+  Workspace& w = m->ws;
+  SolverState st;
+  st.sc = w.scal.as<SolverScalars>();
+  st.partials = w.partials.as<void>();
+  st.counter = w.counter.as<unsigned>();
+  Bufs b{w.r.as<double>(), w.p.as<double>(), w.q.as<double>(), w.z.as<double>(), w.rb.as<void>(),
+         w.ub.as<void>(), w.e0.as<void>(), w.p0.as<void>(), w.q0.as<void>(), w.r1.as<void>(),
+         w.u1.as<void>(), w.e1.as<void>(), w.p1.as<void>(), w.q1.as<void>()};
+  const size_t vbytes = size_t(m->n_nodes) * 3 * nr * sizeof(double);
+
+  EBE_K(launch_fill_zero(st.sc, sizeof(SolverScalars), s));
+  EBE_K(launch_fill_zero(st.counter, 64, s));
+  EBE_K(launch_fill_zero(b.p, vbytes, s));
+  if (o.use_x0) EBE_K(sk_mask_u(m, u, nr, st, s));
+  else EBE_K(launch_fill_zero(u, vbytes, s));
+  // lines 4-5: r <= f - sum_i K_i u_i
+  EBE_K(launch_ebe(m, 2, EBE_F64, nr, u, b.q, true, true, nullptr, s));
+  EBE_K(sk_outer_init(m, f, b.q, b.r, nr, o.tol, st, s));
+
+  SolverScalars* h = nullptr;
+  ebe_status rs = read_scalars(m, s, &h);
+  if (rs != EBE_OK) return rs;
+  const bool mg = o.precond == EBE_PREC_MG2;
+  const int per_check = mg ? 1 : o.check_every;
+  int enq = 0;
+  while (h->outer_active && !h->err && enq < o.max_outer) {
+    const int k = std::min(per_check, o.max_outer - enq);
+    for (int c = 0; c < k; ++c) {
+      if (mg) {
+        rs = (o.mode == EBE_MODE_MIXED) ? mg2_precondition<float>(m, nr, o, b, st, s)
+                                        : mg2_precondition<double>(m, nr, o, b, st, s);
+        if (rs != EBE_OK) return rs;
+      } else {
+        EBE_K(sk_outer_z_bj(m, b.r, b.q, b.z, nr, st, s));   // z <= M^-1 r ; (z,q), (z,r)
+      }
+      EBE_K(sk_outer_p(m, b.z, b.p, b.q, nr, st, s));        // p <= z + beta p ; q <= 0
+      EBE_K(launch_ebe(m, 2, EBE_F64, nr, b.p, b.q, true, false, &st.sc->outer_active, s));  // q <= K p
+      EBE_K(sk_outer_alpha(m, b.p, b.q, nr, st, s));         // alpha <= rho / (p, q)
+      EBE_K(sk_outer_update(m, b.r, u, b.q, b.p, nr, o.tol, o.max_outer, st, s));  // r, u updates
+    }
+    enq += k;
+    if ((rs = read_scalars(m, s, &h)) != EBE_OK) return rs;
+  }
+  ebe_status result = EBE_OK;
+  if (h->err) result = h->err;
+  else if (!(h->max_rel <= o.tol)) result = EBE_NOT_CONVERGED;
+  if (stats) {
+    stats->outer_iters = h->outer_iter;
+    stats->inner_iters[0] = h->inner[0].steps;
+    stats->inner_iters[1] = h->inner[1].steps;
+    stats->max_rel_res = h->max_rel;
+    stats->status = result;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (result < 0) set_error("ebe_pcg_solve: %s", ebe_status_string(result));
+  return result;
+}
+
+}  // extern "C"

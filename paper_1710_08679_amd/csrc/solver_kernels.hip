@@ -1,0 +1,583 @@
+// Fused vector kernels of Algorithm 1 and their device-side scalar steps.
+//
+// Every CG loop in Algorithm 1 carries n cases with per-case scalars and
+// stops when the worst case meets its test (Section 3.1).  Here those scalars
+// never leave the GPU: a kernel that needs an inner product accumulates
+// per-case partial sums, the last workgroup to finish (arrival counter) adds
+// the partials in a fixed order and runs the scalar step (alpha, beta, rho,
+// the stopping test) for all cases.  Loop control is a device flag that
+// every later kernel of the loop reads first, so the host can enqueue
+// iterations ahead and only reads the flag now and then.
+//
+// Work unit = (node, case): a work-item reads the three components of one
+// case of one node (stride n in the [node][component][case] layout), which
+// the 3x3 block Jacobi needs; a workgroup holds a multiple of n work-items so
+// each work-item keeps one case for the whole grid-stride loop.
+#include <hip/hip_runtime.h>
+
+#include "ebe_internal.h"
+#include "solver_state.h"
+
+namespace ebe {
+namespace {
+
+constexpr int kMaxBlocks = 1024;
+
+inline int block_for(int nr) { return (256 / nr) * nr; }
+
+template <typename T>
+__device__ __forceinline__ void bj_apply(const T* __restrict__ m, T x0, T x1, T x2, T& y0, T& y1, T& y2) {
+  y0 = m[0] * x0 + m[5] * x1 + m[4] * x2;
+  y1 = m[5] * x0 + m[1] * x1 + m[3] * x2;
+  y2 = m[4] * x0 + m[3] * x1 + m[2] * x2;
+}
+
+__device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
+
+// ---------------------------------------------------------------------------
+// generic node-case kernel with NDOT per-case inner products and an epilogue
+// ---------------------------------------------------------------------------
+template <typename Acc, int NDOT, class Body, class Epi>
+__global__ __launch_bounds__(256) void k_nodecase(Body body, Epi epi, int64_t n_nodes, int nr,
+                                                  Acc* __restrict__ partials, unsigned* __restrict__ counter,
+                                                  const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int bd = blockDim.x;
+  const int col = threadIdx.x % nr;
+  Acc acc[NDOT > 0 ? NDOT : 1];
+#pragma unroll
+  for (int d = 0; d < (NDOT > 0 ? NDOT : 1); ++d) acc[d] = Acc(0);
+  const int64_t units = n_nodes * nr;
+  for (int64_t u = int64_t(blockIdx.x) * bd + threadIdx.x; u < units; u += int64_t(gridDim.x) * bd)
+    body(u / nr, col, acc);
+  if constexpr (NDOT > 0) {
+    __shared__ Acc sh[256 * NDOT];
+    __shared__ bool last;
+#pragma unroll
+    for (int d = 0; d < NDOT; ++d) sh[d * 256 + threadIdx.x] = acc[d];
+    __syncthreads();
+    const int nsum = NDOT * nr;
+    if (threadIdx.x < nsum) {
+      const int d = threadIdx.x / nr, c = threadIdx.x % nr;
+      Acc s = Acc(0);
+      for (int k = c; k < bd; k += nr) s += sh[d * 256 + k];
+      partials[size_t(blockIdx.x) * nsum + threadIdx.x] = s;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    __shared__ double tot[3 * EBE_MAX_RHS];
+    if (threadIdx.x < nsum) {
+      double s = 0.0;
+      for (unsigned b = 0; b < gridDim.x; ++b)
+        s += double(__builtin_nontemporal_load(&partials[size_t(b) * nsum + threadIdx.x]));
+      tot[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      *counter = 0u;
+      epi(tot, nr);
+    }
+  }
+}
+
+template <typename Acc, int NDOT, class Body, class Epi>
+hipError_t run_nodecase(Body body, Epi epi, int64_t n_nodes, int nr, SolverState& st, const int* gate,
+                        hipStream_t s) {
+  const int bd = block_for(nr);
+  int64_t g = (n_nodes * nr + bd - 1) / bd;
+  if (g > kMaxBlocks) g = kMaxBlocks;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL((k_nodecase<Acc, NDOT, Body, Epi>), dim3(unsigned(g)), dim3(bd), 0, s, body, epi, n_nodes,
+                     nr, reinterpret_cast<Acc*>(st.partials), st.counter, gate);
+  return hipGetLastError();
+}
+
+struct NoEpi {
+  __device__ void operator()(const double*, int) const {}
+};
+
+// ---------------------------------------------------------------------------
+// bodies
+// ---------------------------------------------------------------------------
+#define NC_IDX(node, c, col) ((node) * 3 * int64_t(nr) + (c) * nr + (col))
+
+// u <- P u (fixed DOFs to zero); f is only read
+struct BodyMaskU {
+  double* u;
+  const uint8_t* fix;
+  int nr;
+  __device__ void operator()(int64_t node, int col, double*) const {
+    const unsigned fx = fix[node];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if ((fx >> c) & 1) u[NC_IDX(node, c, col)] = 0.0;
+  }
+};
+
+// r = P f - q ; sums: ||Pf||^2, ||r||^2
+struct BodyOuterInit {
+  const double* f;
+  const double* q;
+  double* r;
+  const uint8_t* fix;
+  int nr;
+  __device__ void operator()(int64_t node, int col, double* acc) const {
+    const unsigned fx = fix[node];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = NC_IDX(node, c, col);
+      const double fv = ((fx >> c) & 1) ? 0.0 : f[i];
+      const double rv = ((fx >> c) & 1) ? 0.0 : fv - q[i];
+      r[i] = rv;
+      acc[0] += fv * fv;
+      acc[1] += rv * rv;
+    }
+  }
+};
+
+// z = M^-1 r (PCGE) or z = (double) ub (MG2); sums: (z, q), (z, r)
+template <int MODE, typename TU>
+struct BodyOuterZ {
+  const double* minv;  // MODE 0
+  const TU* ub;        // MODE 1
+  const double* r;
+  const double* q;
+  double* z;
+  int nr;
+  __device__ void operator()(int64_t node, int col, double* acc) const {
+    const int64_t i0 = NC_IDX(node, 0, col);
+    const double r0 = r[i0], r1 = r[i0 + nr], r2 = r[i0 + 2 * nr];
+    double z0, z1, z2;
+    if (MODE == 0) {
+      bj_apply(minv + 6 * node, r0, r1, r2, z0, z1, z2);
+    } else {
+      z0 = double(ub[i0]);
+      z1 = double(ub[i0 + nr]);
+      z2 = double(ub[i0 + 2 * nr]);
+    }
+    z[i0] = z0;
+    z[i0 + nr] = z1;
+    z[i0 + 2 * nr] = z2;
+    acc[0] += z0 * q[i0] + z1 * q[i0 + nr] + z2 * q[i0 + 2 * nr];
+    acc[1] += z0 * r0 + z1 * r1 + z2 * r2;
+  }
+};
+
+// p = z + beta p ; q = 0
+template <typename T>
+struct BodyPUpdate {
+  const T* z;
+  T* p;
+  T* q;
+  const double* beta;
+  int nr;
+  __device__ void operator()(int64_t node, int col, double*) const {
+    const T b = T(beta[col]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = NC_IDX(node, c, col);
+      // beta = 0 starts a new direction: do not read p (it may hold stale bits)
+      p[i] = (b == T(0)) ? z[i] : z[i] + b * p[i];
+      q[i] = T(0);
+    }
+  }
+};
+
+// sums: (p, q)
+template <typename T>
+struct BodyDot {
+  const T* a;
+  const T* b;
+  int nr;
+  template <typename Acc>
+  __device__ void operator()(int64_t node, int col, Acc* acc) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = NC_IDX(node, c, col);
+      acc[0] += Acc(a[i]) * Acc(b[i]);
+    }
+  }
+};
+
+// r -= alpha q ; u += alpha p ; sums: ||r||^2
+struct BodyOuterUpdate {
+  double* r;
+  double* u;
+  const double* q;
+  const double* p;
+  const double* alpha;
+  int nr;
+  __device__ void operator()(int64_t node, int col, double* acc) const {
+    const double a = alpha[col];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = NC_IDX(node, c, col);
+      const double rv = r[i] - a * q[i];
+      r[i] = rv;
+      u[i] += a * p[i];
+      acc[0] += rv * rv;
+    }
+  }
+};
+
+// rb = (T) r ; ub = M0^-1 rb
+template <typename T>
+struct BodyCastBJ {
+  const double* r;
+  const T* minv;
+  T* rb;
+  T* ub;
+  int nr;
+  __device__ void operator()(int64_t node, int col, double*) const {
+    const int64_t i0 = NC_IDX(node, 0, col);
+    const T r0 = T(r[i0]), r1 = T(r[i0 + nr]), r2 = T(r[i0 + 2 * nr]);
+    rb[i0] = r0;
+    rb[i0 + nr] = r1;
+    rb[i0 + 2 * nr] = r2;
+    T y0, y1, y2;
+    bj_apply(minv + 6 * node, r0, r1, r2, y0, y1, y2);
+    ub[i0] = y0;
+    ub[i0 + nr] = y1;
+    ub[i0 + 2 * nr] = y2;
+  }
+};
+
+// inner start: e = r - q ; sums ||e||^2, (M^-1 e, e), ||r||^2
+template <typename T>
+struct BodyInnerInit {
+  const T* r;
+  const T* q;
+  T* e;
+  const T* minv;
+  int nr;
+  __device__ void operator()(int64_t node, int col, T* acc) const {
+    const int64_t i0 = NC_IDX(node, 0, col);
+    const T r0 = r[i0], r1 = r[i0 + nr], r2 = r[i0 + 2 * nr];
+    const T e0 = r0 - q[i0], e1 = r1 - q[i0 + nr], e2 = r2 - q[i0 + 2 * nr];
+    e[i0] = e0;
+    e[i0 + nr] = e1;
+    e[i0 + 2 * nr] = e2;
+    T z0, z1, z2;
+    bj_apply(minv + 6 * node, e0, e1, e2, z0, z1, z2);
+    acc[0] += e0 * e0 + e1 * e1 + e2 * e2;
+    acc[1] += z0 * e0 + z1 * e1 + z2 * e2;
+    acc[2] += r0 * r0 + r1 * r1 + r2 * r2;
+  }
+};
+
+// p = M^-1 e + beta p ; q = 0
+template <typename T>
+struct BodyInnerP {
+  const T* e;
+  T* p;
+  T* q;
+  const T* minv;
+  const double* beta;
+  int nr;
+  __device__ void operator()(int64_t node, int col, T*) const {
+    const int64_t i0 = NC_IDX(node, 0, col);
+    T z0, z1, z2;
+    bj_apply(minv + 6 * node, e[i0], e[i0 + nr], e[i0 + 2 * nr], z0, z1, z2);
+    const T b = T(beta[col]);
+    if (b == T(0)) {  // first step of the loop: p may hold stale bits
+      p[i0] = z0;
+      p[i0 + nr] = z1;
+      p[i0 + 2 * nr] = z2;
+    } else {
+      p[i0] = z0 + b * p[i0];
+      p[i0 + nr] = z1 + b * p[i0 + nr];
+      p[i0 + 2 * nr] = z2 + b * p[i0 + 2 * nr];
+    }
+    q[i0] = T(0);
+    q[i0 + nr] = T(0);
+    q[i0 + 2 * nr] = T(0);
+  }
+};
+
+// e -= alpha q ; u += alpha p ; sums ||e||^2, (M^-1 e, e)
+template <typename T>
+struct BodyInnerUpdate {
+  T* e;
+  T* u;
+  const T* q;
+  const T* p;
+  const T* minv;
+  const double* alpha;
+  int nr;
+  __device__ void operator()(int64_t node, int col, T* acc) const {
+    const int64_t i0 = NC_IDX(node, 0, col);
+    const T a = T(alpha[col]);
+    T ev[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = i0 + c * nr;
+      ev[c] = e[i] - a * q[i];
+      e[i] = ev[c];
+      u[i] += a * p[i];
+    }
+    T z0, z1, z2;
+    bj_apply(minv + 6 * node, ev[0], ev[1], ev[2], z0, z1, z2);
+    acc[0] += ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2];
+    acc[1] += z0 * ev[0] + z1 * ev[1] + z2 * ev[2];
+  }
+};
+
+#undef NC_IDX
+
+// ---------------------------------------------------------------------------
+// epilogues (run by one thread of the last workgroup); see solver_state.h
+// ---------------------------------------------------------------------------
+struct EpiOuterInit {
+  SolverScalars* sc;
+  double tol;
+  __device__ void operator()(const double* tot, int nr) const {
+    double worst = 0.0;
+    bool bad = false;
+    for (int j = 0; j < nr; ++j) {
+      const double ff = tot[j], rr = tot[nr + j];
+      sc->nf2[j] = ff;
+      sc->rr[j] = rr;
+      const double rel = ff > 0.0 ? sqrt(rr / ff) : 0.0;
+      sc->rel[j] = rel;
+      bad |= !finite_d(rel) || !finite_d(ff) || !finite_d(rr);
+      worst = fmax(worst, rel);
+      sc->alpha[j] = 0.0;
+      sc->beta[j] = 0.0;
+      sc->rho[j] = 0.0;
+    }
+    sc->max_rel = worst;
+    sc->outer_iter = 0;
+    if (bad) sc->err = EBE_ERR_NONFINITE;
+    sc->outer_active = (!bad && worst > tol) ? 1 : 0;
+  }
+};
+
+struct EpiOuterBeta {
+  SolverScalars* sc;
+  __device__ void operator()(const double* tot, int nr) const {
+    const bool first = sc->outer_iter == 0;
+    for (int j = 0; j < nr; ++j) {
+      const double zq = tot[j], zr = tot[nr + j];
+      // flexible CG: beta_i = -alpha_{i-1} (z_i, q_{i-1}) / rho_{i-1}
+      double b = 0.0;
+      if (!first && sc->rho[j] != 0.0) b = -sc->alpha[j] * zq / sc->rho[j];
+      if (!finite_d(b)) b = 0.0;
+      sc->beta[j] = b;
+      sc->rho[j] = zr;
+    }
+  }
+};
+
+struct EpiOuterAlpha {
+  SolverScalars* sc;
+  __device__ void operator()(const double* tot, int nr) const {
+    for (int j = 0; j < nr; ++j) {
+      const double g = tot[j];
+      double a = 0.0;
+      if (g > 0.0) a = sc->rho[j] / g;
+      else if (g < 0.0 || (g == 0.0 && sc->rr[j] > 0.0 && sc->rho[j] != 0.0)) sc->err = EBE_ERR_BREAKDOWN;
+      if (!finite_d(g) || !finite_d(a)) {
+        sc->err = EBE_ERR_NONFINITE;
+        a = 0.0;
+      }
+      sc->alpha[j] = a;
+    }
+    if (sc->err) sc->outer_active = 0;
+  }
+};
+
+struct EpiOuterConv {
+  SolverScalars* sc;
+  double tol;
+  int max_outer;
+  __device__ void operator()(const double* tot, int nr) const {
+    double worst = 0.0;
+    bool bad = false;
+    for (int j = 0; j < nr; ++j) {
+      const double rr = tot[j];
+      sc->rr[j] = rr;
+      const double rel = sc->nf2[j] > 0.0 ? sqrt(rr / sc->nf2[j]) : 0.0;
+      sc->rel[j] = rel;
+      bad |= !finite_d(rel);
+      worst = fmax(worst, rel);
+    }
+    sc->max_rel = worst;
+    sc->outer_iter += 1;
+    if (bad) sc->err = EBE_ERR_NONFINITE;
+    sc->outer_active = (!bad && !sc->err && worst > tol && sc->outer_iter < max_outer) ? 1 : 0;
+  }
+};
+
+template <typename T>
+struct EpiInnerStart {
+  InnerScalars* in;
+  double eps;
+  int nmax;
+  __device__ void operator()(const double* tot, int nr) const {
+    double worst = 0.0;
+    for (int j = 0; j < nr; ++j) {
+      const double ee = tot[j], ze = tot[nr + j], rr = tot[2 * nr + j];
+      in->nr2[j] = rr;
+      const double ratio = rr > 0.0 ? ee / rr : 0.0;
+      if (isfinite(ratio)) worst = fmax(worst, ratio);
+      in->rho_a[j] = ze;
+      in->beta[j] = 0.0;
+      in->alpha[j] = 0.0;
+    }
+    in->i = 1;
+    in->active = (worst > eps && in->i < nmax) ? 1 : 0;
+  }
+};
+
+template <typename T>
+struct EpiInnerAlpha {
+  InnerScalars* in;
+  __device__ void operator()(const double* tot, int nr) const {
+    for (int j = 0; j < nr; ++j) {
+      const double g = tot[j];
+      double a = (g != 0.0) ? in->rho_a[j] / g : 0.0;
+      if (!isfinite(a)) a = 0.0;  // a column whose step vanished is frozen
+      in->alpha[j] = a;
+      in->rho_b[j] = in->rho_a[j];
+    }
+  }
+};
+
+template <typename T>
+struct EpiInnerStep {
+  InnerScalars* in;
+  double eps;
+  int nmax;
+  __device__ void operator()(const double* tot, int nr) const {
+    double worst = 0.0;
+    for (int j = 0; j < nr; ++j) {
+      const double ee = tot[j], ze = tot[nr + j];
+      const double ratio = in->nr2[j] > 0.0 ? ee / in->nr2[j] : 0.0;
+      if (isfinite(ratio)) worst = fmax(worst, ratio);
+      in->rho_a[j] = ze;
+      double b = (in->rho_b[j] != 0.0) ? ze / in->rho_b[j] : 0.0;
+      if (!isfinite(b)) b = 0.0;
+      in->beta[j] = b;
+    }
+    in->i += 1;
+    in->steps += 1;
+    in->active = (worst > eps && in->i < nmax) ? 1 : 0;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers used by solver.cpp
+// ---------------------------------------------------------------------------
+hipError_t sk_mask_u(const ebe_mesh* m, double* u, int nr, SolverState& st, hipStream_t s) {
+  return run_nodecase<double, 0>(BodyMaskU{u, m->fix.as<uint8_t>(), nr}, NoEpi{}, m->n_nodes, nr, st, nullptr, s);
+}
+
+hipError_t sk_outer_init(const ebe_mesh* m, const double* f, const double* q, double* r, int nr, double tol,
+                         SolverState& st, hipStream_t s) {
+  return run_nodecase<double, 2>(BodyOuterInit{f, q, r, m->fix.as<uint8_t>(), nr}, EpiOuterInit{st.sc, tol},
+                                 m->n_nodes, nr, st, nullptr, s);
+}
+
+hipError_t sk_outer_z_bj(const ebe_mesh* m, const double* r, const double* q, double* z, int nr, SolverState& st,
+                         hipStream_t s) {
+  BodyOuterZ<0, double> b{m->minv64[0].as<double>(), nullptr, r, q, z, nr};
+  return run_nodecase<double, 2>(b, EpiOuterBeta{st.sc}, m->n_nodes, nr, st, &st.sc->outer_active, s);
+}
+
+template <typename T>
+hipError_t sk_outer_z_cast(const ebe_mesh* m, const T* ub, const double* r, const double* q, double* z, int nr,
+                           SolverState& st, hipStream_t s) {
+  BodyOuterZ<1, T> b{nullptr, ub, r, q, z, nr};
+  return run_nodecase<double, 2>(b, EpiOuterBeta{st.sc}, m->n_nodes, nr, st, &st.sc->outer_active, s);
+}
+template hipError_t sk_outer_z_cast<float>(const ebe_mesh*, const float*, const double*, const double*, double*,
+                                           int, SolverState&, hipStream_t);
+template hipError_t sk_outer_z_cast<double>(const ebe_mesh*, const double*, const double*, const double*, double*,
+                                            int, SolverState&, hipStream_t);
+
+hipError_t sk_outer_p(const ebe_mesh* m, const double* z, double* p, double* q, int nr, SolverState& st,
+                      hipStream_t s) {
+  return run_nodecase<double, 0>(BodyPUpdate<double>{z, p, q, st.sc->beta, nr}, NoEpi{}, m->n_nodes, nr, st,
+                                 &st.sc->outer_active, s);
+}
+
+hipError_t sk_outer_alpha(const ebe_mesh* m, const double* p, const double* q, int nr, SolverState& st,
+                          hipStream_t s) {
+  return run_nodecase<double, 1>(BodyDot<double>{p, q, nr}, EpiOuterAlpha{st.sc}, m->n_nodes, nr, st,
+                                 &st.sc->outer_active, s);
+}
+
+hipError_t sk_outer_update(const ebe_mesh* m, double* r, double* u, const double* q, const double* p, int nr,
+                           double tol, int max_outer, SolverState& st, hipStream_t s) {
+  return run_nodecase<double, 1>(BodyOuterUpdate{r, u, q, p, st.sc->alpha, nr}, EpiOuterConv{st.sc, tol, max_outer},
+                                 m->n_nodes, nr, st, &st.sc->outer_active, s);
+}
+
+template <typename T>
+hipError_t sk_cast_bj(const ebe_mesh* m, const double* r, T* rb, T* ub, int nr, SolverState& st, hipStream_t s) {
+  const T* minv = sizeof(T) == 8 ? reinterpret_cast<const T*>(m->minv64[0].as<void>())
+                                 : reinterpret_cast<const T*>(m->minv32[0].as<void>());
+  return run_nodecase<double, 0>(BodyCastBJ<T>{r, minv, rb, ub, nr}, NoEpi{}, m->n_nodes, nr, st,
+                                 &st.sc->outer_active, s);
+}
+template hipError_t sk_cast_bj<float>(const ebe_mesh*, const double*, float*, float*, int, SolverState&, hipStream_t);
+template hipError_t sk_cast_bj<double>(const ebe_mesh*, const double*, double*, double*, int, SolverState&,
+                                       hipStream_t);
+
+template <typename T>
+static const T* minv_of(const ebe_mesh* m, int level) {
+  return sizeof(T) == 8 ? reinterpret_cast<const T*>(m->minv64[level].as<void>())
+                        : reinterpret_cast<const T*>(m->minv32[level].as<void>());
+}
+
+template <typename T>
+hipError_t sk_inner_init(const ebe_mesh* m, int level, const T* r, const T* q, T* e, int nr, double eps, int nmax,
+                         SolverState& st, hipStream_t s) {
+  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  return run_nodecase<T, 3>(BodyInnerInit<T>{r, q, e, minv_of<T>(m, level), nr},
+                            EpiInnerStart<T>{&st.sc->inner[level], eps, nmax}, n, nr, st, &st.sc->outer_active, s);
+}
+
+template <typename T>
+hipError_t sk_inner_p(const ebe_mesh* m, int level, const T* e, T* p, T* q, int nr, SolverState& st,
+                      hipStream_t s) {
+  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  return run_nodecase<T, 0>(BodyInnerP<T>{e, p, q, minv_of<T>(m, level), st.sc->inner[level].beta, nr}, NoEpi{},
+                            n, nr, st, &st.sc->inner[level].active, s);
+}
+
+template <typename T>
+hipError_t sk_inner_alpha(const ebe_mesh* m, int level, const T* p, const T* q, int nr, SolverState& st,
+                          hipStream_t s) {
+  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  return run_nodecase<T, 1>(BodyDot<T>{p, q, nr}, EpiInnerAlpha<T>{&st.sc->inner[level]}, n, nr, st,
+                            &st.sc->inner[level].active, s);
+}
+
+template <typename T>
+hipError_t sk_inner_update(const ebe_mesh* m, int level, T* e, T* u, const T* q, const T* p, int nr, double eps,
+                           int nmax, SolverState& st, hipStream_t s) {
+  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  return run_nodecase<T, 2>(BodyInnerUpdate<T>{e, u, q, p, minv_of<T>(m, level), st.sc->inner[level].alpha, nr},
+                            EpiInnerStep<T>{&st.sc->inner[level], eps, nmax}, n, nr, st,
+                            &st.sc->inner[level].active, s);
+}
+
+#define EBE_INST(T)                                                                                              \
+  template hipError_t sk_inner_init<T>(const ebe_mesh*, int, const T*, const T*, T*, int, double, int,            \
+                                       SolverState&, hipStream_t);                                               \
+  template hipError_t sk_inner_p<T>(const ebe_mesh*, int, const T*, T*, T*, int, SolverState&, hipStream_t);      \
+  template hipError_t sk_inner_alpha<T>(const ebe_mesh*, int, const T*, const T*, int, SolverState&, hipStream_t); \
+  template hipError_t sk_inner_update<T>(const ebe_mesh*, int, T*, T*, const T*, const T*, int, double, int,       \
+                                         SolverState&, hipStream_t);
+EBE_INST(float)
+EBE_INST(double)
+#undef EBE_INST
+
+}  // namespace ebe

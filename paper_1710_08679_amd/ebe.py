@@ -1,0 +1,317 @@
+"""Thin Python binding of the C ABI in ``include/ebe.h`` (``lib/libebe.so``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device buffers are torch CUDA tensors (PyTorch provides memory and
+streams); vectors use the (nodes, 3, nrhs) layout, case index fastest.  The
+library must be built (``python -m paper_1710_08679_amd.build``); nothing here
+falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libebe.so")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_ARG, ERR_INDEX, ERR_INVERTED, ERR_CURVED, ERR_MATERIAL = -1, -2, -3, -4, -5
+ERR_OOM, ERR_HIP, ERR_BREAKDOWN, ERR_NONFINITE, ERR_NUMBERING = -6, -7, -8, -9, -10
+F64, F32 = 0, 1
+PREC_PCGE, PREC_MG2 = 0, 1
+MODE_FP64, MODE_MIXED = 0, 1
+MAX_RHS = 16
+
+EXPORTED = (
+    "ebe_mesh_create", "ebe_mesh_set_material", "ebe_mesh_info", "ebe_mesh_destroy", "ebe_matvec",
+    "ebe_matvec_add",
+    "ebe_matvec_p1", "ebe_prolong_p1", "ebe_restrict_p1", "ebe_diag_blocks", "ebe_block_jacobi",
+    "ebe_pcg_default_opts", "ebe_pcg_solve", "ebe_adjoint_grad", "ebe_batch_create", "ebe_batch_solve",
+    "ebe_batch_destroy", "ebe_status_string", "ebe_last_error", "ebe_build_info",
+)
+
+
+class PcgOpts(ctypes.Structure):
+    _fields_ = [("precond", ctypes.c_int32), ("mode", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("inner_eps", ctypes.c_double * 2), ("inner_max", ctypes.c_int32 * 2),
+                ("use_x0", ctypes.c_int32), ("coarse_guess", ctypes.c_int32)]
+
+
+class PcgStats(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int64 * 2), ("max_rel_res", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"outer_iters": self.outer_iters, "status": self.status,
+                "inner_iters": [int(self.inner_iters[0]), int(self.inner_iters[1])],
+                "max_rel_res": self.max_rel_res, "seconds": self.seconds}
+
+
+class EbeError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+_LIB = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+def load():
+    """Load ``libebe.so``; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1710_08679_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "ebe_mesh_create": ([_vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)], _i32),
+        "ebe_mesh_set_material": ([_vp, _vp, _vp, _vp], _i32),
+        "ebe_mesh_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _i32),
+        "ebe_mesh_destroy": ([_vp], None),
+        "ebe_matvec": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
+        "ebe_matvec_add": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
+        "ebe_matvec_p1": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
+        "ebe_prolong_p1": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
+        "ebe_restrict_p1": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
+        "ebe_diag_blocks": ([_vp, _i32, _vp, _vp], _i32),
+        "ebe_block_jacobi": ([_vp, _i32, _i32, _i32, _vp, _vp, _vp], _i32),
+        "ebe_pcg_default_opts": ([ctypes.POINTER(PcgOpts)], None),
+        "ebe_pcg_solve": ([_vp, _i32, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgStats), _vp], _i32),
+        "ebe_adjoint_grad": ([_vp, _i32, _i32, _vp, _vp, _vp, _vp], _i32),
+        "ebe_batch_create": ([ctypes.POINTER(_vp), _i32, ctypes.POINTER(_i32), ctypes.POINTER(_vp)], _i32),
+        "ebe_batch_solve": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(PcgOpts),
+                             ctypes.POINTER(PcgStats), _vp], _i32),
+        "ebe_batch_destroy": ([_vp], None),
+        "ebe_status_string": ([_i32], ctypes.c_char_p),
+        "ebe_last_error": ([], ctypes.c_char_p),
+        "ebe_build_info": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _LIB = lib
+    return lib
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        lib = load()
+        raise EbeError(status, f"{lib.ebe_status_string(status).decode()}: {lib.ebe_last_error().decode()}")
+    return status
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+def _dev(t, dtype=None, shape=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return _vp(t.data_ptr())
+
+
+def _dtype_code(dtype) -> int:
+    import torch
+    if dtype == torch.float64:
+        return F64
+    if dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {dtype}: float64 or float32")
+
+
+def default_opts(**kw) -> PcgOpts:
+    o = PcgOpts()
+    load().ebe_pcg_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k in ("inner_eps", "inner_max"):
+            getattr(o, k)[0], getattr(o, k)[1] = v
+        else:
+            setattr(o, k, v)
+    return o
+
+
+class Mesh:
+    """A device-resident mesh handle (``ebe_mesh``)."""
+
+    def __init__(self, xyz, conn, n_vertices, young, poisson, fixed=None, stream=None):
+        lib = load()
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        young = np.ascontiguousarray(young, dtype=np.float64)
+        poisson = np.ascontiguousarray(poisson, dtype=np.float64)
+        fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+        self.n_nodes, self.n_vertices, self.n_elem = int(xyz.shape[0]), int(n_vertices), int(conn.shape[0])
+        if xyz.shape != (self.n_nodes, 3) or conn.shape != (self.n_elem, 10):
+            raise ValueError("xyz must be (N, 3) and conn (E, 10)")
+        if young.shape != (self.n_elem,) or poisson.shape != (self.n_elem,):
+            raise ValueError("young and poisson must be (E,)")
+        if fx is not None and fx.shape != (self.n_nodes, 3):
+            raise ValueError("fixed must be (N, 3)")
+        h = _vp()
+        _check(lib.ebe_mesh_create(xyz.ctypes.data, self.n_nodes, self.n_vertices, conn.ctypes.data, self.n_elem,
+                                   young.ctypes.data, poisson.ctypes.data,
+                                   None if fx is None else fx.ctypes.data,
+                                   _vp(None) if stream is None else _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_generated(cls, m, stream=None) -> "Mesh":
+        """Upload a ``meshgen.Mesh``."""
+        fixed = m.fixed if m.fixed.any() else None
+        return cls(m.xyz, m.conn, m.n_vertices, m.young, m.poisson, fixed, stream)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("mesh handle was destroyed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().ebe_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n, nv, ne = _i64(), _i64(), _i64()
+        _check(load().ebe_mesh_info(self.handle, ctypes.byref(n), ctypes.byref(nv), ctypes.byref(ne)))
+        return n.value, nv.value, ne.value
+
+    # ---- operators -------------------------------------------------------
+    def _vec_op(self, fn, x, rows_in, rows_out, apply_bc, out, stream):
+        import torch
+        if x.dim() != 3 or x.shape[0] != rows_in or x.shape[1] != 3:
+            raise ValueError(f"x must be ({rows_in}, 3, nrhs)")
+        nrhs = int(x.shape[2])
+        if out is None:
+            out = torch.empty((rows_out, 3, nrhs), dtype=x.dtype, device=x.device)
+        _check(fn(self.handle, _dtype_code(x.dtype), nrhs, _dev(x, name="x"),
+                  _dev(out, x.dtype, (rows_out, 3, nrhs), "out"), int(bool(apply_bc)), _stream(stream)))
+        return out
+
+    def matvec(self, x, apply_bc=False, out=None, stream=None):
+        """y = K x (quadratic elements); x (N, 3, nrhs) float64/float32."""
+        return self._vec_op(load().ebe_matvec, x, self.n_nodes, self.n_nodes, apply_bc, out, stream)
+
+    def matvec_add(self, x, y, apply_bc=False, stream=None):
+        """y += K x (in place); returns y."""
+        return self._vec_op(load().ebe_matvec_add, x, self.n_nodes, self.n_nodes, apply_bc, y, stream)
+
+    def matvec_p1(self, x, apply_bc=False, out=None, stream=None):
+        """y = K1 x on the corner-only linear mesh; x (Nv, 3, nrhs)."""
+        return self._vec_op(load().ebe_matvec_p1, x, self.n_vertices, self.n_vertices, apply_bc, out, stream)
+
+    def prolong(self, x, apply_bc=False, out=None, stream=None):
+        """y (N, 3, n) = P1 x (Nv, 3, n)."""
+        return self._vec_op(load().ebe_prolong_p1, x, self.n_vertices, self.n_nodes, apply_bc, out, stream)
+
+    def restrict(self, x, apply_bc=False, out=None, stream=None):
+        """y (Nv, 3, n) = P1^T x (N, 3, n)."""
+        return self._vec_op(load().ebe_restrict_p1, x, self.n_nodes, self.n_vertices, apply_bc, out, stream)
+
+    def block_jacobi(self, x, level=0, out=None, stream=None):
+        import torch
+        rows = self.n_nodes if level == 0 else self.n_vertices
+        if x.dim() != 3 or x.shape[0] != rows or x.shape[1] != 3:
+            raise ValueError(f"x must be ({rows}, 3, nrhs)")
+        nrhs = int(x.shape[2])
+        if out is None:
+            out = torch.empty_like(x)
+        _check(load().ebe_block_jacobi(self.handle, int(level), _dtype_code(x.dtype), nrhs, _dev(x, name="x"),
+                                       _dev(out, x.dtype, x.shape, "out"), _stream(stream)))
+        return out
+
+    def diag_blocks(self, level=0, stream=None):
+        """(rows, 3, 3) float64 nodal diagonal blocks (fixed rows/cols -> identity)."""
+        import torch
+        rows = self.n_nodes if level == 0 else self.n_vertices
+        out = torch.empty((rows, 3, 3), dtype=torch.float64, device="cuda")
+        _check(load().ebe_diag_blocks(self.handle, int(level), _dev(out), _stream(stream)))
+        return out
+
+    def set_material(self, young, poisson, stream=None):
+        import torch
+        _check(load().ebe_mesh_set_material(self.handle, _dev(young, torch.float64, (self.n_elem,), "young"),
+                                            _dev(poisson, torch.float64, (self.n_elem,), "poisson"),
+                                            _stream(stream)))
+
+    def adjoint_grad(self, u, lam, out=None, stream=None):
+        """g_e = -sum_c lam_{c,e}^T (K_e/E_e) u_{c,e}; u, lam (N, 3, nrhs) of one dtype."""
+        import torch
+        if u.shape != lam.shape or u.dtype != lam.dtype or u.dim() != 3 or u.shape[0] != self.n_nodes:
+            raise ValueError("u and lam must both be (N, 3, nrhs) of one dtype")
+        nrhs = int(u.shape[2])
+        if out is None:
+            out = torch.empty((self.n_elem,), dtype=u.dtype, device=u.device)
+        _check(load().ebe_adjoint_grad(self.handle, _dtype_code(u.dtype), nrhs, _dev(u, name="u"),
+                                       _dev(lam, name="lam"), _dev(out, u.dtype, (self.n_elem,), "out"),
+                                       _stream(stream)))
+        return out
+
+    def solve(self, f, u=None, opts: PcgOpts | None = None, stream=None, raise_on_nonconv=False, **kw):
+        """Solve P K P u = P f for f (N, 3, nrhs) float64; returns (u, stats dict)."""
+        import torch
+        if f.dim() != 3 or f.shape[0] != self.n_nodes or f.shape[1] != 3:
+            raise ValueError("f must be (N, 3, nrhs)")
+        nrhs = int(f.shape[2])
+        if u is None:
+            u = torch.empty_like(f)
+        if opts is None:
+            opts = default_opts(**kw)
+        st = PcgStats()
+        status = _check(load().ebe_pcg_solve(self.handle, nrhs, _dev(f, torch.float64, name="f"),
+                                             _dev(u, torch.float64, f.shape, "u"), ctypes.byref(opts),
+                                             ctypes.byref(st), _stream(stream)))
+        if raise_on_nonconv and status == NOT_CONVERGED:
+            raise EbeError(status, f"not converged: {st.as_dict()}")
+        return u, st.as_dict()
+
+
+def batch_solve(meshes, fs, us=None, opts: PcgOpts | None = None, stream=None, **kw):
+    """Solve several meshes (each with its own nrhs) as one batch; returns (us, [stats])."""
+    import torch
+    lib = load()
+    n = len(meshes)
+    if us is None:
+        us = [torch.empty_like(f) for f in fs]
+    for m, f, u in zip(meshes, fs, us):
+        if f.shape != (m.n_nodes, 3, f.shape[2]) or u.shape != f.shape:
+            raise ValueError("each f / u must be (N_i, 3, nrhs_i)")
+        _dev(f, torch.float64, name="f")
+        _dev(u, torch.float64, name="u")
+    hs = (_vp * n)(*[m.handle for m in meshes])
+    nr = (_i32 * n)(*[int(f.shape[2]) for f in fs])
+    b = _vp()
+    _check(lib.ebe_batch_create(hs, n, nr, ctypes.byref(b)))
+    try:
+        fp = (_vp * n)(*[f.data_ptr() for f in fs])
+        up = (_vp * n)(*[u.data_ptr() for u in us])
+        st = (PcgStats * n)()
+        if opts is None:
+            opts = default_opts(**kw)
+        _check(lib.ebe_batch_solve(b, fp, up, ctypes.byref(opts), st, _stream(stream)))
+    finally:
+        lib.ebe_batch_destroy(b)
+    return us, [s.as_dict() for s in st]

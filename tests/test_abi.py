@@ -1,0 +1,109 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+``include/ebe.h`` declares, reports statuses, carries the paper's solver
+defaults, and rejects invalid meshes in its host-side validation (which runs
+before any device call)."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1710_08679_amd import ebe, meshgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return ebe.load()
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "ebe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ebe_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported(lib):
+    names = header_functions()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(ebe.EXPORTED)
+
+
+def test_status_strings_and_build_info(lib):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10):
+        s = lib.ebe_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert b"gfx950" in lib.ebe_build_info()
+
+
+def test_default_options_follow_table2(lib):
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "table2_inner_loops.json")))
+    o = ebe.default_opts()
+    assert o.precond == ebe.PREC_MG2 and o.mode == ebe.MODE_MIXED
+    assert o.inner_eps[0] == g["levels"]["0"]["tolerance"]
+    assert o.inner_eps[1] == g["levels"]["1"]["tolerance"]
+    assert o.inner_max[0] == g["levels"]["0"]["max_iterations"]
+    assert o.inner_max[1] == g["levels"]["1"]["max_iterations"]
+    assert o.tol == g["outer_tolerance"]["value"]
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(ebe.PcgOpts) == 56
+    assert ctypes.sizeof(ebe.PcgStats) == 40
+
+
+def create(m, **over):
+    xyz = over.get("xyz", m.xyz)
+    conn = over.get("conn", m.conn)
+    nv = over.get("nv", m.n_vertices)
+    E = over.get("E", m.young)
+    nu = over.get("nu", m.poisson)
+    with pytest.raises(ebe.EbeError) as ei:
+        ebe.Mesh(xyz, conn, nv, E, nu)
+    return ei.value.status
+
+
+def test_validation_rejects_bad_meshes(lib):
+    m = meshgen.kuhn_mesh(2, 2, 2)
+    c = m.conn.copy()
+    c[3, 7] = m.n_nodes + 5
+    assert create(m, conn=c) == ebe.ERR_INDEX
+    c = m.conn.copy()
+    c[0, 1], c[0, 2] = m.conn[0, 2], m.conn[0, 1]  # swap two corners -> negative volume
+    assert create(m, conn=c) == ebe.ERR_INVERTED
+    x = m.xyz.copy()
+    x[m.conn[0, 5]] += 0.01  # move an edge node off its midpoint
+    assert create(m, xyz=x) == ebe.ERR_CURVED
+    E = m.young.copy()
+    E[4] = -1.0
+    assert create(m, E=E) == ebe.ERR_MATERIAL
+    nu = m.poisson.copy()
+    nu[4] = 0.5
+    assert create(m, nu=nu) == ebe.ERR_MATERIAL
+    c = m.conn.copy()
+    c[0, 4] = m.conn[0, 0]  # a corner used as an edge node
+    assert create(m, conn=c) == ebe.ERR_NUMBERING
+    x = m.xyz.copy()
+    x[0, 0] = np.nan
+    assert create(m, xyz=x) == ebe.ERR_NONFINITE
+    assert create(m, nv=m.n_nodes + 1) == ebe.ERR_ARG
+    c = m.conn.copy()
+    c[c == m.n_nodes - 1] = m.conn[0, 9]  # node n-1 unused (and an edge node reused inconsistently)
+    assert create(m, conn=c) in (ebe.ERR_INDEX, ebe.ERR_CURVED)
+
+
+def test_null_arguments_are_rejected(lib):
+    out = ctypes.c_void_p()
+    st = lib.ebe_mesh_create(None, 10, 4, None, 1, None, None, None, None, ctypes.byref(out))
+    assert st == ebe.ERR_ARG
+    assert out.value is None
+    assert b"null" in lib.ebe_last_error()
+    assert lib.ebe_matvec(None, 0, 1, None, None, 0, None) == ebe.ERR_ARG
+    assert lib.ebe_pcg_solve(None, 1, None, None, None, None, None) == ebe.ERR_ARG
+    b = ctypes.c_void_p()
+    assert lib.ebe_batch_create(None, 0, None, ctypes.byref(b)) == ebe.ERR_ARG

@@ -1,0 +1,169 @@
+"""GPU solves (Algorithm 1 and PCGE) against the oracle's direct solutions,
+plus the adjoint gradient through torch.autograd."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint, fem, solve
+from paper_1710_08679_amd import ebe, meshgen
+from paper_1710_08679_amd.autograd import surface_misfit
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def cube(gpu_lib):
+    m = meshgen.cube_mesh(4)
+    f = meshgen.top_face_random_loads(m, meshgen.rng_for(1, 0), nrhs=1)
+    K = fem.assemble(m.xyz, m.conn, m.young, m.poisson)
+    return m, ebe.Mesh.from_generated(m), f, K, solve.dense_solve(K, f, m.fixed)
+
+
+def test_small_cube_pcge_fp64_reaches_dense_solution(cube):
+    m, gm, f, K, ud = cube
+    print("[cube 4^3] PCGE FP64 tol 1e-10", flush=True)
+    u, st = gm.solve(dev(f), precond=ebe.PREC_PCGE, mode=ebe.MODE_FP64, tol=1e-10)
+    assert st["status"] == ebe.OK and st["max_rel_res"] <= 1e-10
+    un = u.cpu().numpy()
+    r = solve.residual(K, un, f, m.fixed)
+    assert np.linalg.norm(r) <= 1.5e-10 * np.linalg.norm(f)  # oracle residual of the GPU answer
+    u2, st2 = gm.solve(dev(f), precond=ebe.PREC_PCGE, mode=ebe.MODE_FP64, tol=1e-13)
+    assert rel_err(u2.cpu().numpy(), ud) <= 1e-10
+
+
+@pytest.mark.parametrize("precond,mode", [(ebe.PREC_MG2, ebe.MODE_MIXED), (ebe.PREC_MG2, ebe.MODE_FP64)])
+def test_small_cube_mg2(cube, precond, mode):
+    m, gm, f, K, ud = cube
+    u, st = gm.solve(dev(f), precond=precond, mode=mode, tol=1e-12)
+    assert st["status"] == ebe.OK
+    assert rel_err(u.cpu().numpy(), ud) <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def crust(gpu_lib):
+    m = meshgen.crust_mesh(12, 12, 6)
+    f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(3, 2), nrhs=16)
+    K = fem.assemble(m.xyz, m.conn, m.young, m.poisson)
+    print(f"[crust 12x12x6] DOF={m.n_dof}: oracle sparse LU", flush=True)
+    return m, ebe.Mesh.from_generated(m), f, K, solve.sparse_solve(K, f, m.fixed)
+
+
+@pytest.mark.parametrize("coarse_guess", [0, 1])
+def test_crust_mixed_mg2_within_1e6(crust, coarse_guess):
+    m, gm, f, K, ud = crust
+    u, st = gm.solve(dev(f), precond=ebe.PREC_MG2, mode=ebe.MODE_MIXED, tol=1e-8, coarse_guess=coarse_guess)
+    print(f"[crust mixed MG2] {st}", flush=True)
+    assert st["status"] == ebe.OK
+    un = u.cpu().numpy()
+    for j in range(f.shape[2]):
+        assert rel_err(un[:, :, j], ud[:, :, j]) <= 1e-6
+    assert np.all(un[m.fixed.astype(bool)] == 0)
+
+
+def test_crust_fp64_paths_within_1e10(crust):
+    m, gm, f, K, ud = crust
+    for precond in (ebe.PREC_PCGE, ebe.PREC_MG2):
+        u, st = gm.solve(dev(f), precond=precond, mode=ebe.MODE_FP64, tol=1e-13)
+        print(f"[crust FP64 precond={precond}] {st}", flush=True)
+        assert st["status"] == ebe.OK
+        assert rel_err(u.cpu().numpy(), ud) <= 1e-10
+
+
+def test_multi_case_equals_single_cases_and_zero_case(crust):
+    m, gm, f, K, ud = crust
+    f4 = f[:, :, :4].copy()
+    f4[:, :, 2] = 0.0
+    u, st = gm.solve(dev(f4), tol=1e-9)
+    assert st["status"] == ebe.OK
+    un = u.cpu().numpy()
+    assert np.all(un[:, :, 2] == 0.0)
+    for j in (0, 3):
+        uj, _ = gm.solve(dev(f4[:, :, j:j + 1]), tol=1e-9)
+        assert rel_err(un[:, :, j], uj.cpu().numpy()[:, :, 0]) <= 1e-7
+
+
+def test_initial_guess_and_iteration_cap(crust):
+    m, gm, f, K, ud = crust
+    u0 = dev(ud[:, :, :2])
+    u, st = gm.solve(dev(f[:, :, :2]), u=u0, use_x0=1, precond=ebe.PREC_PCGE, mode=ebe.MODE_FP64, tol=1e-8)
+    assert st["status"] == ebe.OK and st["outer_iters"] == 0
+    u, st = gm.solve(dev(f[:, :, :2]), precond=ebe.PREC_PCGE, mode=ebe.MODE_FP64, tol=1e-12, max_outer=3)
+    assert st["status"] == ebe.NOT_CONVERGED and st["outer_iters"] == 3
+
+
+def test_nonfinite_input_is_reported(crust):
+    m, gm, f, K, ud = crust
+    fb = f[:, :, :1].copy()
+    fb[np.nonzero(~m.fixed.astype(bool).any(axis=1))[0][0], 0, 0] = np.nan
+    with pytest.raises(ebe.EbeError) as ei:
+        gm.solve(dev(fb))
+    assert ei.value.status == ebe.ERR_NONFINITE
+
+
+def test_batch_of_uneven_meshes(gpu_lib):
+    ms, gms, fs, refs = [], [], [], []
+    for k, (g, n) in enumerate([((4, 4, 2), 3), ((6, 6, 3), 1), ((5, 5, 3), 16)]):
+        m = meshgen.crust_mesh(*g)
+        f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(5, k), nrhs=n)
+        K = fem.assemble(m.xyz, m.conn, m.young, m.poisson)
+        ms.append(m)
+        gms.append(ebe.Mesh.from_generated(m))
+        fs.append(dev(f))
+        refs.append(solve.sparse_solve(K, f, m.fixed))
+    us, sts = ebe.batch_solve(gms, fs, tol=1e-8)
+    for u, r, st in zip(us, refs, sts):
+        assert st["status"] == ebe.OK
+        assert rel_err(u.cpu().numpy(), r) <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# adjoint gradient
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def adj(gpu_lib):
+    m = meshgen.adjoint_mesh(8, 8, 4)
+    f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(4, 3), nrhs=4)
+    S = meshgen.top_surface_dofs(m)
+    d = 1e-3 * meshgen.rng_for(4, 4).standard_normal((S.size, 4))
+    L, g, u, lam = adjoint.gradient(m.xyz, m.conn, m.young, m.poisson, m.fixed, f, S, d)
+    return m, ebe.Mesh.from_generated(m), f, S, d, L, g
+
+
+@pytest.mark.parametrize("grad_dtype,tol", [(torch.float64, 1e-8), (torch.float32, 1e-4)])
+def test_autograd_gradient_matches_oracle(adj, grad_dtype, tol):
+    m, gm, f, S, d, L, g = adj
+    E = dev(m.young).requires_grad_(True)
+    opts = ebe.default_opts(precond=ebe.PREC_MG2, mode=ebe.MODE_MIXED, tol=1e-12)
+    loss = surface_misfit(E, gm, dev(m.poisson), dev(f), torch.from_numpy(S).cuda(), dev(d), opts, grad_dtype)
+    loss.backward()
+    assert abs(float(loss) - L) <= 1e-9 * abs(L)
+    gg = E.grad.cpu().numpy()
+    assert np.max(np.abs(gg - g)) <= tol * np.max(np.abs(g))
+
+
+def test_gradient_central_differences_on_gpu(adj):
+    m, gm, f, S, d, L, g = adj
+    opts = ebe.default_opts(precond=ebe.PREC_PCGE, mode=ebe.MODE_FP64, tol=1e-13)
+    Sd = torch.from_numpy(S).cuda()
+    E = dev(m.young).requires_grad_(True)
+    loss = surface_misfit(E, gm, dev(m.poisson), dev(f), Sd, dev(d), opts)
+    loss.backward()
+    gg = E.grad.cpu().numpy()
+    for e in meshgen.rng_for(4, 5).choice(m.n_elem, size=20, replace=False):
+        h = 1e-4 * m.young[e]
+        vals = []
+        for sgn in (1, -1):
+            Ep = m.young.copy()
+            Ep[e] += sgn * h
+            with torch.no_grad():
+                vals.append(float(surface_misfit(dev(Ep), gm, dev(m.poisson), dev(f), Sd, dev(d), opts)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - gg[e]) <= 1e-5 * np.max(np.abs(gg))
