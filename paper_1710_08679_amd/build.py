@@ -31,8 +31,8 @@ COMMON = [
 ]
 
 SOURCES = [
-    "mesh.cpp", "api.cpp", "solver.cpp", "batch.cpp",
-    "ebe_kernels.hip", "ebe_vec.hip", "ebe_adjoint.hip", "solver_kernels.hip",
+    "mesh.cpp", "patches.cpp", "api.cpp", "solver.cpp", "batch.cpp",
+    "ebe_kernels.hip", "setup_kernels.hip", "ebe_vec.hip", "ebe_adjoint.hip", "solver_kernels.hip",
 ]
 
 

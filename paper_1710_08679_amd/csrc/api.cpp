@@ -68,6 +68,7 @@ ebe_status ebe_matvec(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, vo
                       void* stream) {
   ebe_status st = check_common("ebe_matvec", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
+  if ((st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4)) != EBE_OK) return st;
   return hip_status("ebe_matvec", launch_ebe_p2(m, dt, nrhs, x, y, apply_bc && m->has_bc,
                                                 static_cast<hipStream_t>(stream)));
 }
@@ -76,7 +77,8 @@ ebe_status ebe_matvec_add(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x
                           void* stream) {
   ebe_status st = check_common("ebe_matvec_add", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
-  return hip_status("ebe_matvec_add", launch_ebe(m, 2, dt, nrhs, x, y, apply_bc && m->has_bc, false, nullptr,
+  if ((st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4)) != EBE_OK) return st;
+  return hip_status("ebe_matvec_add", launch_ebe(m, 2, dt, nrhs, x, y, apply_bc && m->has_bc, true, nullptr,
                                                  static_cast<hipStream_t>(stream)));
 }
 
@@ -84,6 +86,7 @@ ebe_status ebe_matvec_p1(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x,
                          void* stream) {
   ebe_status st = check_common("ebe_matvec_p1", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
+  if ((st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4)) != EBE_OK) return st;
   return hip_status("ebe_matvec_p1", launch_ebe_p1(m, dt, nrhs, x, y, apply_bc && m->has_bc,
                                                    static_cast<hipStream_t>(stream)));
 }

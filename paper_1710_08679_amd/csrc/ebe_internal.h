@@ -63,6 +63,25 @@ struct Workspace {
   int* host_flags = nullptr;  // pinned host mirror
 };
 
+// Element patches (patches.cpp): at most kPatchElems elements touching at
+// most kPatchNodes nodes, so a patch's node sums fit in LDS.
+constexpr int kPatchElems = 64;
+constexpr int kPatchNodes = 192;
+constexpr int kPatchCorners = 64;  // corner nodes of a patch (the linear level)
+
+// Patch tables of one level (0: all nodes of the quadratic mesh, 1: corners).
+struct PatchLevel {
+  DBuf poff;    // int32 [npatch+1] entry offsets
+  DBuf pnode;   // int32 [entries] node id | fix bits << 28 | shared << 31
+  DBuf pslot;   // int32 [entries] staging slot of a shared entry, -1 otherwise
+  DBuf snode;   // int32 [nshared] shared node id | fix bits << 28, increasing id
+  DBuf soff;    // int32 [nshared+1] offsets into sslot
+  DBuf sslot;   // int32 [nslots] staging slots of each shared node, in patch order
+  DBuf stage;   // staging buffer [nslots][3][nrhs] of the product's dtype
+  int64_t nslots = 0, nshared = 0, entries = 0;
+  int max_nodes = 0;
+};
+
 }  // namespace ebe
 
 struct ebe_mesh {
@@ -79,6 +98,12 @@ struct ebe_mesh {
   ebe::DBuf edge_ends;  // int32 [N-Nv][2]
   ebe::DBuf v2e_off;    // int32 [Nv+1] corner -> incident edge nodes (CSR)
   ebe::DBuf v2e_idx;    // int32 [2 (N-Nv)]
+  // element patches
+  int64_t n_patch = 0;
+  ebe::DBuf pelem;      // int32 [n_patch+1] element offsets
+  ebe::DBuf lconn;      // uint8 [E][16] patch-local ids of the 10 nodes (padded to 16 bytes)
+  ebe::DBuf lconn1;     // uint8 [E][4]  patch-local ids of the 4 corners
+  ebe::PatchLevel pl[2];
   // 3x3 block Jacobi: inverted symmetric blocks (xx yy zz yz zx xy), per level
   ebe::DBuf minv64[2], minv32[2];
   bool minv_ready = false;
@@ -93,10 +118,11 @@ hipError_t launch_ebe_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* 
                          bool bc, hipStream_t s);
 hipError_t launch_ebe_p1(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y,
                          bool bc, hipStream_t s);
-// general form: order 2 (quadratic) or 1 (linear); zero_first clears y; the
-// kernel does nothing when gate is non-null and *gate == 0 on the device.
+// general form: order 2 (quadratic) or 1 (linear); add: y += K x instead of
+// y = K x; the kernels do nothing when gate is non-null and *gate == 0 on the
+// device.  The staging buffers must have been sized by ensure_stage.
 hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,
-                      bool zero_first, const int* gate, hipStream_t s);
+                      bool add, const int* gate, hipStream_t s);
 hipError_t launch_diag_blocks(const ebe_mesh* m, int level, double* blk6, hipStream_t s);
 hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6, double* inv64,
                                 float* inv32, hipStream_t s);
@@ -118,5 +144,8 @@ hipError_t launch_adjoint(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void*
                           const void* lam, void* g, hipStream_t s);
 
 ebe_status ensure_blocks(ebe_mesh* m, hipStream_t s);
+ebe_status build_patches(ebe_mesh* m, const int32_t* conn10, const uint8_t* fix, hipStream_t s);
+// grow the staging buffers for products with up to nrhs cases of the given element size
+ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes);
 
 }  // namespace ebe

@@ -1,15 +1,24 @@
-// Element-by-element kernels for gfx950: the quadratic and linear EBE
-// products (Section 2, Eq. (3)), the 3x3 nodal diagonal blocks of K and K1
-// ("diag[ ]" of Algorithm 1), and small set-up kernels.
+// Element-by-element products on gfx950 (Section 2, Eq. (3)): y = K x for the
+// quadratic mesh and y = K1 x for the linear (corner) mesh, n cases at once.
 //
-// EBE product mapping.  One work-item per (element, case): the n cases of an
-// element sit in n consecutive lanes, so every gather and scatter of a node
-// touches n contiguous values of the [node][component][case] layout
-// (Section 3.1: the case loop is innermost and coalesced).  Each work-item
-// rebuilds the element geometry from the four corner coordinates, gathers
-// the 30 nodal values of its case, forms K_e u_e in registers (p2_element.h)
-// and adds the 30 results with hardware FP atomics (Section 3.2: atomics keep
-// the nodal data local in cache, unlike colouring).
+// Work decomposition (see patches.cpp).  One workgroup per element patch
+// (<= 64 elements, <= 192 nodes):
+//   1. the patch's node words (id, Dirichlet bits, shared flag) and staging
+//      slots go to LDS, together with a cleared FP64 force accumulator
+//      F[node][component][case];
+//   2. one work-item per element rebuilds the element geometry from the four
+//      corner coordinates and material (the element matrix is never stored,
+//      Section 2) and keeps it in LDS;
+//   3. one work-item per (element, case) gathers its 30 nodal values (the n
+//      cases of a node are contiguous: Section 3.1's coalesced case loop),
+//      forms K_e u_e in registers (p2_element.h) and adds the forces into F
+//      with LDS FP64 atomics (FP32 LDS atomics are much slower on this part);
+//   4. each patch node is written once: exclusive nodes straight into y,
+//      shared nodes as a partial sum into a staging slot.
+// A second, node-centric kernel adds the staged partials of each shared node
+// in patch order.  Global memory sees no atomics, every node is written
+// exactly once per product (so y needs no clearing pass), and the result does
+// not depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include "ebe_internal.h"
@@ -22,286 +31,176 @@ template <typename T> struct Pair;
 template <> struct Pair<double> { using type = double2; };
 template <> struct Pair<float> { using type = float2; };
 
-__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
-constexpr int kBlock = 256;
 
-inline unsigned grid_for(int64_t work, int block = kBlock) {
-  int64_t g = (work + block - 1) / block;
-  return unsigned(g < 1 ? 1 : g);
+
+constexpr int threads_for(int nr) {
+  return (kPatchElems * nr + 63) / 64 * 64 > 512 ? 512 : (kPatchElems * nr + 63) / 64 * 64;
 }
 
-// ---------------------------------------------------------------------------
-// y = K x, quadratic elements
-// ---------------------------------------------------------------------------
-template <typename T, int NR, bool BC>
-__global__ __launch_bounds__(kBlock) void k_ebe_p2(const int32_t* __restrict__ conn,
-                                                   const double4* __restrict__ xv,
-                                                   const typename Pair<T>::type* __restrict__ lame,
-                                                   const T* __restrict__ x, T* __restrict__ y,
-                                                   int64_t nelem, const int* __restrict__ gate) {
+template <typename T, int NR, int ORDER>
+__global__ __launch_bounds__(threads_for(NR)) void k_ebe_patch(
+    const int32_t* __restrict__ conn, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
+    const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
+    const double4* __restrict__ xv, const typename Pair<T>::type* __restrict__ lame, const T* __restrict__ x,
+    T* __restrict__ y, T* __restrict__ stage, int bc, int add, const int* __restrict__ gate) {
+  constexpr int NLOC = ORDER == 2 ? 10 : 4;
+  constexpr int W = 3 * NR;
+  constexpr int TPB = threads_for(NR);
+  constexpr int MAXN = ORDER == 2 ? kPatchNodes : kPatchCorners;
+  __shared__ double F[MAXN * W];
+  __shared__ T geo[kPatchElems][14];
+  __shared__ int32_t words[MAXN];
+  __shared__ int32_t slots[MAXN];
   if (gate && *gate == 0) return;
-  const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t e = t / NR;
-  const int r = int(t - e * NR);
-  if (e >= nelem) return;
-  int32_t cw[10];
-#pragma unroll
-  for (int a = 0; a < 10; ++a) cw[a] = conn[e * 10 + a];
-  T G[4][3];
-  const T V = tet_geometry<T>(xv[cw[0] & kIdxMask], xv[cw[1] & kIdxMask], xv[cw[2] & kIdxMask],
-                              xv[cw[3] & kIdxMask], G);
-  const auto lm = lame[e];
-  const T s = V * T(0.05);
-  T u[10][3];
-#pragma unroll
-  for (int a = 0; a < 10; ++a) {
-    const T* xp = x + size_t(cw[a] & kIdxMask) * (3 * NR) + r;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      T v = xp[c * NR];
-      if (BC && ((cw[a] >> (kIdxBits + c)) & 1)) v = T(0);
-      u[a][c] = v;
-    }
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x;
+  const int e0 = pelem[p], ne = pelem[p + 1] - e0;
+  const int o0 = poff[p], nn = poff[p + 1] - o0;
+  for (int i = tid; i < nn * W; i += TPB) F[i] = 0.0;
+  for (int i = tid; i < nn; i += TPB) {
+    words[i] = pnode[o0 + i];
+    slots[i] = pslot[o0 + i];
   }
-  T f[10][3];
-  p2_forces<T>(G, T(lm.x) * s, T(lm.y) * s, u, f);
+  for (int el = tid; el < ne; el += TPB) {
+    const int64_t e = int64_t(e0) + el;
+    T G[4][3];
+    const T V = tet_geometry<T>(xv[conn[e * 10 + 0] & kIdxMask], xv[conn[e * 10 + 1] & kIdxMask],
+                                xv[conn[e * 10 + 2] & kIdxMask], xv[conn[e * 10 + 3] & kIdxMask], G);
+    const auto lm = lame[e];
 #pragma unroll
-  for (int a = 0; a < 10; ++a) {
-    T* yp = y + size_t(cw[a] & kIdxMask) * (3 * NR) + r;
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (BC && ((cw[a] >> (kIdxBits + c)) & 1)) continue;
-      atomic_add(yp + c * NR, f[a][c]);
+      for (int d = 0; d < 3; ++d) geo[el][3 * k + d] = G[k][d];
+    geo[el][12] = T(lm.x) * V;
+    geo[el][13] = T(lm.y) * V;
+  }
+  __syncthreads();
+  for (int w = tid; w < ne * NR; w += TPB) {
+    const int el = w / NR;
+    const int r = w - el * NR;
+    const int64_t e = int64_t(e0) + el;
+    int lid[NLOC];
+    if constexpr (ORDER == 2) {
+      const uint4 q = *reinterpret_cast<const uint4*>(lconn + e * 16);
+      const uint32_t qw[3] = {q.x, q.y, q.z};
+#pragma unroll
+      for (int a = 0; a < NLOC; ++a) lid[a] = (qw[a >> 2] >> (8 * (a & 3))) & 0xff;
+    } else {
+      const uint32_t q = *reinterpret_cast<const uint32_t*>(lconn + e * 4);
+#pragma unroll
+      for (int a = 0; a < NLOC; ++a) lid[a] = (q >> (8 * a)) & 0xff;
+    }
+    T G[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) G[k][d] = geo[el][3 * k + d];
+    const T cl = geo[el][12], cm = geo[el][13];
+    T u[NLOC][3];
+#pragma unroll
+    for (int a = 0; a < NLOC; ++a) {
+      const int32_t wd = words[lid[a]];
+      const T* xp = x + size_t(wd & kIdxMask) * W + r;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T v = xp[c * NR];
+        if (bc && ((wd >> (kIdxBits + c)) & 1)) v = T(0);
+        u[a][c] = v;
+      }
+    }
+    T f[NLOC][3];
+    if constexpr (ORDER == 2)
+      p2_forces<T>(G, cl * T(0.05), cm * T(0.05), reinterpret_cast<const T(*)[3]>(u), reinterpret_cast<T(*)[3]>(f));
+    else
+      p1_forces<T>(G, cl, cm, reinterpret_cast<const T(*)[3]>(u), reinterpret_cast<T(*)[3]>(f));
+#pragma unroll
+    for (int a = 0; a < NLOC; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) atomicAdd(&F[lid[a] * W + c * NR + r], double(f[a][c]));
+  }
+  __syncthreads();
+  for (int i = tid; i < nn * W; i += TPB) {
+    const int ent = i / W;
+    const int rem = i - ent * W;
+    const int c = rem / NR;
+    const int32_t wd = words[ent];
+    const T v = T(F[i]);
+    if (wd < 0) {  // shared node: partial sum to its staging slot
+      stage[size_t(slots[ent]) * W + rem] = v;
+    } else {
+      T* yp = y + size_t(wd & kIdxMask) * W + rem;
+      const bool fixed = bc && ((wd >> (kIdxBits + c)) & 1);
+      if (add) {
+        if (!fixed) *yp += v;
+      } else {
+        *yp = fixed ? T(0) : v;
+      }
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// y = K1 x, linear elements on the corners (vertex-first numbering: corner ids
-// are also the coarse-vector ids)
-// ---------------------------------------------------------------------------
-template <typename T, int NR, bool BC>
-__global__ __launch_bounds__(kBlock) void k_ebe_p1(const int32_t* __restrict__ conn,
-                                                   const double4* __restrict__ xv,
-                                                   const typename Pair<T>::type* __restrict__ lame,
-                                                   const T* __restrict__ x, T* __restrict__ y,
-                                                   int64_t nelem, const int* __restrict__ gate) {
+// y[shared node] (=|+=) sum of its staged partials, in patch order
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_reduce_shared(const int32_t* __restrict__ snode,
+                                                       const int32_t* __restrict__ soff,
+                                                       const int32_t* __restrict__ sslot,
+                                                       const T* __restrict__ stage, T* __restrict__ y,
+                                                       int64_t nshared, int bc, int add,
+                                                       const int* __restrict__ gate) {
+  constexpr int W = 3 * NR;
   if (gate && *gate == 0) return;
-  const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t e = t / NR;
-  const int r = int(t - e * NR);
-  if (e >= nelem) return;
-  int32_t cw[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) cw[a] = conn[e * 10 + a];
-  T G[4][3];
-  const T V = tet_geometry<T>(xv[cw[0] & kIdxMask], xv[cw[1] & kIdxMask], xv[cw[2] & kIdxMask],
-                              xv[cw[3] & kIdxMask], G);
-  const auto lm = lame[e];
-  T u[4][3];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const T* xp = x + size_t(cw[a] & kIdxMask) * (3 * NR) + r;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      T v = xp[c * NR];
-      if (BC && ((cw[a] >> (kIdxBits + c)) & 1)) v = T(0);
-      u[a][c] = v;
-    }
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= nshared * W) return;
+  const int64_t k = i / W;
+  const int rem = int(i - k * W);
+  const int c = rem / NR;
+  const int32_t wd = snode[k];
+  double acc = 0.0;
+  for (int j = soff[k]; j < soff[k + 1]; ++j) acc += double(stage[size_t(sslot[j]) * W + rem]);
+  T* yp = y + size_t(wd & kIdxMask) * W + rem;
+  const bool fixed = bc && ((wd >> (kIdxBits + c)) & 1);
+  if (add) {
+    if (!fixed) *yp += T(acc);
+  } else {
+    *yp = fixed ? T(0) : T(acc);
   }
-  T f[4][3];
-  p1_forces<T>(G, T(lm.x) * V, T(lm.y) * V, u, f);
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    T* yp = y + size_t(cw[a] & kIdxMask) * (3 * NR) + r;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (BC && ((cw[a] >> (kIdxBits + c)) & 1)) continue;
-      atomic_add(yp + c * NR, f[a][c]);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// nodal 3x3 diagonal blocks (symmetric, 6 values), FP64
-//   K_aa = (lambda + mu) M_a + mu tr(M_a) I,  M_a = int grad N_a grad N_a^T dV
-//   quadratic corner i:  M = 3V/5 G_i G_i^T
-//   quadratic edge (i,j): M = 4V/5 (2 G_i G_i^T + G_i G_j^T + G_j G_i^T + 2 G_j G_j^T)
-//   linear corner i:     M = V G_i G_i^T
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void add_block(double* blk, const double M[6], double lam, double mu) {
-  const double tr = M[0] + M[1] + M[2];
-  const double lm = lam + mu;
-  atomic_add(blk + 0, lm * M[0] + mu * tr);
-  atomic_add(blk + 1, lm * M[1] + mu * tr);
-  atomic_add(blk + 2, lm * M[2] + mu * tr);
-  atomic_add(blk + 3, lm * M[3]);
-  atomic_add(blk + 4, lm * M[4]);
-  atomic_add(blk + 5, lm * M[5]);
-}
-
-__device__ __forceinline__ void outer_sym(const double a[3], const double b[3], double s, double M[6]) {
-  // M += s * (a b^T + b a^T) / 2 stored as (xx yy zz yz zx xy)
-  M[0] += s * a[0] * b[0];
-  M[1] += s * a[1] * b[1];
-  M[2] += s * a[2] * b[2];
-  M[3] += s * 0.5 * (a[1] * b[2] + a[2] * b[1]);
-  M[4] += s * 0.5 * (a[2] * b[0] + a[0] * b[2]);
-  M[5] += s * 0.5 * (a[0] * b[1] + a[1] * b[0]);
-}
-
-template <int LEVEL>
-__global__ __launch_bounds__(kBlock) void k_diag_blocks(const int32_t* __restrict__ conn,
-                                                        const double4* __restrict__ xv,
-                                                        const double2* __restrict__ lame,
-                                                        double* __restrict__ blk, int64_t nelem) {
-  const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (e >= nelem) return;
-  int32_t cw[10];
-#pragma unroll
-  for (int a = 0; a < 10; ++a) cw[a] = conn[e * 10 + a] & kIdxMask;
-  double G[4][3];
-  const double V = tet_geometry<double>(xv[cw[0]], xv[cw[1]], xv[cw[2]], xv[cw[3]], G);
-  const double2 lm = lame[e];
-  if (LEVEL == 1) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double M[6] = {0, 0, 0, 0, 0, 0};
-      outer_sym(G[i], G[i], V, M);
-      add_block(blk + size_t(cw[i]) * 6, M, lm.x, lm.y);
-    }
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    double M[6] = {0, 0, 0, 0, 0, 0};
-    outer_sym(G[i], G[i], 0.6 * V, M);
-    add_block(blk + size_t(cw[i]) * 6, M, lm.x, lm.y);
-  }
-#pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    const int i = edge_end(q, 0), j = edge_end(q, 1);
-    double M[6] = {0, 0, 0, 0, 0, 0};
-    const double s = 0.8 * V;
-    outer_sym(G[i], G[i], 2.0 * s, M);
-    outer_sym(G[j], G[j], 2.0 * s, M);
-    outer_sym(G[i], G[j], 2.0 * s, M);  // G_i G_j^T + G_j G_i^T
-    add_block(blk + size_t(cw[4 + q]) * 6, M, lm.x, lm.y);
-  }
-}
-
-// fixed DOFs -> identity rows/columns, then invert (symmetric 3x3, FP64)
-__global__ __launch_bounds__(kBlock) void k_invert_blocks(const double* __restrict__ blk,
-                                                          const uint8_t* __restrict__ fix,
-                                                          double* __restrict__ inv64,
-                                                          float* __restrict__ inv32, int64_t n) {
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= n) return;
-  double a[3][3];
-  const double* b = blk + 6 * i;
-  a[0][0] = b[0]; a[1][1] = b[1]; a[2][2] = b[2];
-  a[1][2] = a[2][1] = b[3];
-  a[2][0] = a[0][2] = b[4];
-  a[0][1] = a[1][0] = b[5];
-  const unsigned fx = fix[i];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-    if ((fx >> c) & 1) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) a[c][d] = a[d][c] = 0.0;
-      a[c][c] = 1.0;
-    }
-  const double c00 = a[1][1] * a[2][2] - a[1][2] * a[2][1];
-  const double c01 = a[1][2] * a[2][0] - a[1][0] * a[2][2];
-  const double c02 = a[1][0] * a[2][1] - a[1][1] * a[2][0];
-  const double det = a[0][0] * c00 + a[0][1] * c01 + a[0][2] * c02;
-  const double id = 1.0 / det;
-  double o[6];
-  o[0] = c00 * id;
-  o[1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) * id;
-  o[2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) * id;
-  o[3] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) * id;  // yz
-  o[4] = c02 * id;                                        // zx
-  o[5] = c01 * id;                                        // xy
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    inv64[6 * i + c] = o[c];
-    inv32[6 * i + c] = float(o[c]);
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_expand_blocks(const double* __restrict__ b6,
-                                                          double* __restrict__ b9, int64_t n) {
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double* b = b6 + 6 * i;
-  double* o = b9 + 9 * i;
-  o[0] = b[0]; o[1] = b[5]; o[2] = b[4];
-  o[3] = b[5]; o[4] = b[1]; o[5] = b[3];
-  o[6] = b[4]; o[7] = b[3]; o[8] = b[2];
-}
-
-__global__ __launch_bounds__(kBlock) void k_lame(const double* __restrict__ E,
-                                                 const double* __restrict__ nu,
-                                                 double2* __restrict__ l64, float2* __restrict__ l32,
-                                                 int64_t n) {
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double e = E[i], v = nu[i];
-  const double lam = e * v / ((1.0 + v) * (1.0 - 2.0 * v));
-  const double mu = e / (2.0 * (1.0 + v));
-  l64[i] = make_double2(lam, mu);
-  l32[i] = make_float2(float(lam), float(mu));
-}
-
-__global__ __launch_bounds__(kBlock) void k_check_material(const double* __restrict__ E,
-                                                           const double* __restrict__ nu,
-                                                           int* __restrict__ bad, int64_t n) {
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double e = E[i], v = nu[i];
-  const bool ok = isfinite(e) && isfinite(v) && e > 0.0 && v > -1.0 && v < 0.5;
-  if (!ok) atomicAdd(bad, 1);
-}
-
-__global__ __launch_bounds__(kBlock) void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
-    p[i] = 0u;
 }
 
 template <typename T, int NR>
-hipError_t ebe_dispatch_p(int order, const ebe_mesh* m, const void* x, void* y, bool bc,
+hipError_t ebe_dispatch_p(int order, const ebe_mesh* m, const void* x, void* y, bool bc, bool add,
                           const int* gate, hipStream_t s) {
   using P = typename Pair<T>::type;
   const P* lame = (sizeof(T) == 8) ? reinterpret_cast<const P*>(m->lame64.as<void>())
                                    : reinterpret_cast<const P*>(m->lame32.as<void>());
-  const unsigned grid = grid_for(m->n_elem * NR);
-  const int32_t* conn = m->conn.as<int32_t>();
-  const double4* xv = m->xv.as<double4>();
-  const T* xx = static_cast<const T*>(x);
-  T* yy = static_cast<T*>(y);
-  if (order == 2) {
-    if (bc)
-      hipLaunchKernelGGL((k_ebe_p2<T, NR, true>), dim3(grid), dim3(kBlock), 0, s, conn, xv, lame, xx, yy, m->n_elem, gate);
-    else
-      hipLaunchKernelGGL((k_ebe_p2<T, NR, false>), dim3(grid), dim3(kBlock), 0, s, conn, xv, lame, xx, yy, m->n_elem, gate);
-  } else {
-    if (bc)
-      hipLaunchKernelGGL((k_ebe_p1<T, NR, true>), dim3(grid), dim3(kBlock), 0, s, conn, xv, lame, xx, yy, m->n_elem, gate);
-    else
-      hipLaunchKernelGGL((k_ebe_p1<T, NR, false>), dim3(grid), dim3(kBlock), 0, s, conn, xv, lame, xx, yy, m->n_elem, gate);
-  }
+  const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
+  T* stage = L.stage.as<T>();
+  constexpr int TPB = threads_for(NR);
+  if (order == 2)
+    hipLaunchKernelGGL((k_ebe_patch<T, NR, 2>), dim3(unsigned(m->n_patch)), dim3(TPB), 0, s, m->conn.as<int32_t>(),
+                       m->lconn.as<uint8_t>(), m->pelem.as<int32_t>(), L.poff.as<int32_t>(), L.pnode.as<int32_t>(),
+                       L.pslot.as<int32_t>(), m->xv.as<double4>(), lame, static_cast<const T*>(x),
+                       static_cast<T*>(y), stage, int(bc), int(add), gate);
+  else
+    hipLaunchKernelGGL((k_ebe_patch<T, NR, 1>), dim3(unsigned(m->n_patch)), dim3(TPB), 0, s, m->conn.as<int32_t>(),
+                       m->lconn1.as<uint8_t>(), m->pelem.as<int32_t>(), L.poff.as<int32_t>(), L.pnode.as<int32_t>(),
+                       L.pslot.as<int32_t>(), m->xv.as<double4>(), lame, static_cast<const T*>(x),
+                       static_cast<T*>(y), stage, int(bc), int(add), gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || L.nshared == 0) return e;
+  const int64_t work = L.nshared * 3 * NR;
+  hipLaunchKernelGGL((k_reduce_shared<T, NR>), dim3(unsigned((work + 255) / 256)), dim3(256), 0, s,
+                     L.snode.as<int32_t>(), L.soff.as<int32_t>(), L.sslot.as<int32_t>(), stage, static_cast<T*>(y),
+                     L.nshared, int(bc), int(add), gate);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t ebe_dispatch(int order, const ebe_mesh* m, int nrhs, const void* x, void* y, bool bc,
+hipError_t ebe_dispatch(int order, const ebe_mesh* m, int nrhs, const void* x, void* y, bool bc, bool add,
                         const int* gate, hipStream_t s) {
   switch (nrhs) {
 #define EBE_CASE(n) \
-  case n: return ebe_dispatch_p<T, n>(order, m, x, y, bc, gate, s);
+  case n: return ebe_dispatch_p<T, n>(order, m, x, y, bc, add, gate, s);
     EBE_CASE(1) EBE_CASE(2) EBE_CASE(3) EBE_CASE(4) EBE_CASE(5) EBE_CASE(6) EBE_CASE(7) EBE_CASE(8)
     EBE_CASE(9) EBE_CASE(10) EBE_CASE(11) EBE_CASE(12) EBE_CASE(13) EBE_CASE(14) EBE_CASE(15) EBE_CASE(16)
 #undef EBE_CASE
@@ -311,75 +210,32 @@ hipError_t ebe_dispatch(int order, const ebe_mesh* m, int nrhs, const void* x, v
 
 }  // namespace
 
-hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
-  const int64_t n = int64_t(bytes / 4);
-  if (n == 0) return hipSuccess;
-  int64_t g = (n + kBlock - 1) / kBlock;
-  if (g > 65536) g = 65536;
-  hipLaunchKernelGGL(k_fill_zero, dim3(unsigned(g)), dim3(kBlock), 0, s, static_cast<uint32_t*>(p), n);
-  return hipGetLastError();
+ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes) {
+  for (int l = 0; l < 2; ++l) {
+    const size_t need = size_t(m->pl[l].nslots) * 3 * size_t(nrhs) * elem_bytes;
+    ebe_status st = m->pl[l].stage.alloc(need);
+    if (st != EBE_OK) return st;
+  }
+  return EBE_OK;
 }
 
 hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,
-                      bool zero_first, const int* gate, hipStream_t s) {
-  if (zero_first) {
-    const int64_t n = order == 2 ? m->n_nodes : m->n_vertices;
-    const size_t bytes = size_t(n) * 3 * nrhs * (dt == EBE_F64 ? 8 : 4);
-    hipError_t e = launch_fill_zero(y, bytes, s);
-    if (e != hipSuccess) return e;
-  }
-  return dt == EBE_F64 ? ebe_dispatch<double>(order, m, nrhs, x, y, bc, gate, s)
-                       : ebe_dispatch<float>(order, m, nrhs, x, y, bc, gate, s);
+                      bool add, const int* gate, hipStream_t s) {
+  const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
+  const size_t need = size_t(L.nslots) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4);
+  if (L.stage.bytes() < need || m->n_patch < 1) return hipErrorInvalidValue;  // staging not sized: host bug
+  return dt == EBE_F64 ? ebe_dispatch<double>(order, m, nrhs, x, y, bc, add, gate, s)
+                       : ebe_dispatch<float>(order, m, nrhs, x, y, bc, add, gate, s);
 }
 
 hipError_t launch_ebe_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,
                          hipStream_t s) {
-  return launch_ebe(m, 2, dt, nrhs, x, y, bc, true, nullptr, s);
+  return launch_ebe(m, 2, dt, nrhs, x, y, bc, false, nullptr, s);
 }
 
 hipError_t launch_ebe_p1(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,
                          hipStream_t s) {
-  return launch_ebe(m, 1, dt, nrhs, x, y, bc, true, nullptr, s);
-}
-
-hipError_t launch_diag_blocks(const ebe_mesh* m, int level, double* blk6, hipStream_t s) {
-  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
-  hipError_t e = launch_fill_zero(blk6, size_t(n) * 6 * sizeof(double), s);
-  if (e != hipSuccess) return e;
-  if (level == 0)
-    hipLaunchKernelGGL(k_diag_blocks<0>, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s,
-                       m->conn.as<int32_t>(), m->xv.as<double4>(), m->lame64.as<double2>(), blk6, m->n_elem);
-  else
-    hipLaunchKernelGGL(k_diag_blocks<1>, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s,
-                       m->conn.as<int32_t>(), m->xv.as<double4>(), m->lame64.as<double2>(), blk6, m->n_elem);
-  return hipGetLastError();
-}
-
-hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6, double* inv64,
-                                float* inv32, hipStream_t s) {
-  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
-  hipLaunchKernelGGL(k_invert_blocks, dim3(grid_for(n)), dim3(kBlock), 0, s, blk6, m->fix.as<uint8_t>(),
-                     inv64, inv32, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_expand_blocks(int64_t n, const double* blk6, double* out9, hipStream_t s) {
-  hipLaunchKernelGGL(k_expand_blocks, dim3(grid_for(n)), dim3(kBlock), 0, s, blk6, out9, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_lame(const ebe_mesh* m, hipStream_t s) {
-  hipLaunchKernelGGL(k_lame, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s, m->young.as<double>(),
-                     m->poisson.as<double>(), m->lame64.as<double2>(), m->lame32.as<float2>(), m->n_elem);
-  return hipGetLastError();
-}
-
-hipError_t launch_check_material(const double* young, const double* poisson, int64_t n, int* bad,
-                                 hipStream_t s) {
-  hipError_t e = launch_fill_zero(bad, sizeof(int), s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_check_material, dim3(grid_for(n)), dim3(kBlock), 0, s, young, poisson, bad, n);
-  return hipGetLastError();
+  return launch_ebe(m, 1, dt, nrhs, x, y, bc, false, nullptr, s);
 }
 
 }  // namespace ebe

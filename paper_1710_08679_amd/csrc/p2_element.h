@@ -30,7 +30,8 @@ namespace ebe {
 // local node of the edge between corners k != m (VTK quadratic-tetra order:
 // edges (0,1), (1,2), (0,2), (0,3), (1,3), (2,3) are local nodes 4..9)
 EBE_HD constexpr int edge_node(int k, int m) {
-  return (k > m) ? edge_node(m, k) : (k == 0 ? (m == 1 ? 4 : (m == 2 ? 6 : 7)) : (k == 1 ? (m == 2 ? 5 : 8) : 9));
+  const int a = k < m ? k : m, b = k < m ? m : k;
+  return a == 0 ? (b == 1 ? 4 : (b == 2 ? 6 : 7)) : (a == 1 ? (b == 2 ? 5 : 8) : 9);
 }
 EBE_HD constexpr int edge_end(int q, int side) {
   return side == 0 ? (q == 0 ? 0 : q == 1 ? 1 : q == 2 ? 0 : q == 3 ? 0 : q == 4 ? 1 : 2)

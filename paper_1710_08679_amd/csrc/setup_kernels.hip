@@ -1,0 +1,218 @@
+// Set-up kernels: nodal 3x3 diagonal blocks of K and K1 and their inverses
+// ("diag[ ]" of Algorithm 1), Lame parameters, material checks, clearing.
+#include <hip/hip_runtime.h>
+
+#include "ebe_internal.h"
+#include "p2_element.h"
+
+namespace ebe {
+namespace {
+
+__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(int64_t work, int block = kBlock) {
+  int64_t g = (work + block - 1) / block;
+  return unsigned(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------------------
+// nodal 3x3 diagonal blocks (symmetric, 6 values), FP64
+//   K_aa = (lambda + mu) M_a + mu tr(M_a) I,  M_a = int grad N_a grad N_a^T dV
+//   quadratic corner i:  M = 3V/5 G_i G_i^T
+//   quadratic edge (i,j): M = 4V/5 (2 G_i G_i^T + G_i G_j^T + G_j G_i^T + 2 G_j G_j^T)
+//   linear corner i:     M = V G_i G_i^T
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void add_block(double* blk, const double M[6], double lam, double mu) {
+  const double tr = M[0] + M[1] + M[2];
+  const double lm = lam + mu;
+  atomic_add(blk + 0, lm * M[0] + mu * tr);
+  atomic_add(blk + 1, lm * M[1] + mu * tr);
+  atomic_add(blk + 2, lm * M[2] + mu * tr);
+  atomic_add(blk + 3, lm * M[3]);
+  atomic_add(blk + 4, lm * M[4]);
+  atomic_add(blk + 5, lm * M[5]);
+}
+
+__device__ __forceinline__ void outer_sym(const double a[3], const double b[3], double s, double M[6]) {
+  // M += s * (a b^T + b a^T) / 2 stored as (xx yy zz yz zx xy)
+  M[0] += s * a[0] * b[0];
+  M[1] += s * a[1] * b[1];
+  M[2] += s * a[2] * b[2];
+  M[3] += s * 0.5 * (a[1] * b[2] + a[2] * b[1]);
+  M[4] += s * 0.5 * (a[2] * b[0] + a[0] * b[2]);
+  M[5] += s * 0.5 * (a[0] * b[1] + a[1] * b[0]);
+}
+
+template <int LEVEL>
+__global__ __launch_bounds__(kBlock) void k_diag_blocks(const int32_t* __restrict__ conn,
+                                                        const double4* __restrict__ xv,
+                                                        const double2* __restrict__ lame,
+                                                        double* __restrict__ blk, int64_t nelem) {
+  const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= nelem) return;
+  int32_t cw[10];
+#pragma unroll
+  for (int a = 0; a < 10; ++a) cw[a] = conn[e * 10 + a] & kIdxMask;
+  double G[4][3];
+  const double V = tet_geometry<double>(xv[cw[0]], xv[cw[1]], xv[cw[2]], xv[cw[3]], G);
+  const double2 lm = lame[e];
+  if (LEVEL == 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double M[6] = {0, 0, 0, 0, 0, 0};
+      outer_sym(G[i], G[i], V, M);
+      add_block(blk + size_t(cw[i]) * 6, M, lm.x, lm.y);
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double M[6] = {0, 0, 0, 0, 0, 0};
+    outer_sym(G[i], G[i], 0.6 * V, M);
+    add_block(blk + size_t(cw[i]) * 6, M, lm.x, lm.y);
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int i = edge_end(q, 0), j = edge_end(q, 1);
+    double M[6] = {0, 0, 0, 0, 0, 0};
+    const double s = 0.8 * V;
+    outer_sym(G[i], G[i], 2.0 * s, M);
+    outer_sym(G[j], G[j], 2.0 * s, M);
+    outer_sym(G[i], G[j], 2.0 * s, M);  // G_i G_j^T + G_j G_i^T
+    add_block(blk + size_t(cw[4 + q]) * 6, M, lm.x, lm.y);
+  }
+}
+
+// fixed DOFs -> identity rows/columns, then invert (symmetric 3x3, FP64)
+__global__ __launch_bounds__(kBlock) void k_invert_blocks(const double* __restrict__ blk,
+                                                          const uint8_t* __restrict__ fix,
+                                                          double* __restrict__ inv64,
+                                                          float* __restrict__ inv32, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double a[3][3];
+  const double* b = blk + 6 * i;
+  a[0][0] = b[0]; a[1][1] = b[1]; a[2][2] = b[2];
+  a[1][2] = a[2][1] = b[3];
+  a[2][0] = a[0][2] = b[4];
+  a[0][1] = a[1][0] = b[5];
+  const unsigned fx = fix[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if ((fx >> c) & 1) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a[c][d] = a[d][c] = 0.0;
+      a[c][c] = 1.0;
+    }
+  const double c00 = a[1][1] * a[2][2] - a[1][2] * a[2][1];
+  const double c01 = a[1][2] * a[2][0] - a[1][0] * a[2][2];
+  const double c02 = a[1][0] * a[2][1] - a[1][1] * a[2][0];
+  const double det = a[0][0] * c00 + a[0][1] * c01 + a[0][2] * c02;
+  const double id = 1.0 / det;
+  double o[6];
+  o[0] = c00 * id;
+  o[1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) * id;
+  o[2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) * id;
+  o[3] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) * id;  // yz
+  o[4] = c02 * id;                                        // zx
+  o[5] = c01 * id;                                        // xy
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    inv64[6 * i + c] = o[c];
+    inv32[6 * i + c] = float(o[c]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_expand_blocks(const double* __restrict__ b6,
+                                                          double* __restrict__ b9, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double* b = b6 + 6 * i;
+  double* o = b9 + 9 * i;
+  o[0] = b[0]; o[1] = b[5]; o[2] = b[4];
+  o[3] = b[5]; o[4] = b[1]; o[5] = b[3];
+  o[6] = b[4]; o[7] = b[3]; o[8] = b[2];
+}
+
+__global__ __launch_bounds__(kBlock) void k_lame(const double* __restrict__ E,
+                                                 const double* __restrict__ nu,
+                                                 double2* __restrict__ l64, float2* __restrict__ l32,
+                                                 int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double e = E[i], v = nu[i];
+  const double lam = e * v / ((1.0 + v) * (1.0 - 2.0 * v));
+  const double mu = e / (2.0 * (1.0 + v));
+  l64[i] = make_double2(lam, mu);
+  l32[i] = make_float2(float(lam), float(mu));
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_material(const double* __restrict__ E,
+                                                           const double* __restrict__ nu,
+                                                           int* __restrict__ bad, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double e = E[i], v = nu[i];
+  const bool ok = isfinite(e) && isfinite(v) && e > 0.0 && v > -1.0 && v < 0.5;
+  if (!ok) atomicAdd(bad, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    p[i] = 0u;
+}
+
+}  // namespace
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t n = int64_t(bytes / 4);
+  if (n == 0) return hipSuccess;
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_fill_zero, dim3(unsigned(g)), dim3(kBlock), 0, s, static_cast<uint32_t*>(p), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_blocks(const ebe_mesh* m, int level, double* blk6, hipStream_t s) {
+  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  hipError_t e = launch_fill_zero(blk6, size_t(n) * 6 * sizeof(double), s);
+  if (e != hipSuccess) return e;
+  if (level == 0)
+    hipLaunchKernelGGL(k_diag_blocks<0>, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s,
+                       m->conn.as<int32_t>(), m->xv.as<double4>(), m->lame64.as<double2>(), blk6, m->n_elem);
+  else
+    hipLaunchKernelGGL(k_diag_blocks<1>, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s,
+                       m->conn.as<int32_t>(), m->xv.as<double4>(), m->lame64.as<double2>(), blk6, m->n_elem);
+  return hipGetLastError();
+}
+
+hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6, double* inv64,
+                                float* inv32, hipStream_t s) {
+  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  hipLaunchKernelGGL(k_invert_blocks, dim3(grid_for(n)), dim3(kBlock), 0, s, blk6, m->fix.as<uint8_t>(),
+                     inv64, inv32, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_blocks(int64_t n, const double* blk6, double* out9, hipStream_t s) {
+  hipLaunchKernelGGL(k_expand_blocks, dim3(grid_for(n)), dim3(kBlock), 0, s, blk6, out9, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_lame(const ebe_mesh* m, hipStream_t s) {
+  hipLaunchKernelGGL(k_lame, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s, m->young.as<double>(),
+                     m->poisson.as<double>(), m->lame64.as<double2>(), m->lame32.as<float2>(), m->n_elem);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_material(const double* young, const double* poisson, int64_t n, int* bad,
+                                 hipStream_t s) {
+  hipError_t e = launch_fill_zero(bad, sizeof(int), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_check_material, dim3(grid_for(n)), dim3(kBlock), 0, s, young, poisson, bad, n);
+  return hipGetLastError();
+}
+
+}  // namespace ebe

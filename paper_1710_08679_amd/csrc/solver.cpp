@@ -86,7 +86,7 @@ ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int
                        SolverState& st, hipStream_t s) {
   const int order = level == 0 ? 2 : 1;
   InnerScalars* din = &st.sc->inner[level];
-  EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, u, q, true, true, &st.sc->outer_active, s));
+  EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, u, q, true, false, &st.sc->outer_active, s));
   EBE_K(sk_inner_init<T>(m, level, r, q, e, nr, eps, nmax, st, s));
   int enq = 0;
   int chunk = level == 0 ? 3 : 4;
@@ -185,6 +185,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   if (st_ != EBE_OK) return st_;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st_ = ensure_blocks(m, s)) != EBE_OK) return st_;
+  if ((st_ = ensure_stage(m, nr, sizeof(double))) != EBE_OK) return st_;
   if ((st_ = ensure_workspace(m, nr)) != EBE_OK) return st_;
 
   Workspace& w = m->ws;
@@ -203,7 +204,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   if (o.use_x0) EBE_K(sk_mask_u(m, u, nr, st, s));
   else EBE_K(launch_fill_zero(u, vbytes, s));
   // lines 4-5: r <= f - sum_i K_i u_i
-  EBE_K(launch_ebe(m, 2, EBE_F64, nr, u, b.q, true, true, nullptr, s));
+  EBE_K(launch_ebe(m, 2, EBE_F64, nr, u, b.q, true, false, nullptr, s));
   EBE_K(sk_outer_init(m, f, b.q, b.r, nr, o.tol, st, s));
 
   SolverScalars* h = nullptr;
