@@ -78,8 +78,9 @@ ebe_status ebe_matvec_add(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x
   ebe_status st = check_common("ebe_matvec_add", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
   if ((st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4)) != EBE_OK) return st;
-  return hip_status("ebe_matvec_add", launch_ebe(m, 2, dt, nrhs, x, y, apply_bc && m->has_bc, true, nullptr,
-                                                 static_cast<hipStream_t>(stream)));
+  const bool bc = apply_bc && m->has_bc;
+  return hip_status("ebe_matvec_add",
+                    launch_ebe(m, 2, dt, nrhs, x, y, bc, bc, true, nullptr, static_cast<hipStream_t>(stream)));
 }
 
 ebe_status ebe_matvec_p1(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, int32_t apply_bc,

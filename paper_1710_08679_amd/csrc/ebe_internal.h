@@ -65,9 +65,19 @@ struct Workspace {
 
 // Element patches (patches.cpp): at most kPatchElems elements touching at
 // most kPatchNodes nodes, so a patch's node sums fit in LDS.
-constexpr int kPatchElems = 64;
-constexpr int kPatchNodes = 192;
-constexpr int kPatchCorners = 64;  // corner nodes of a patch (the linear level)
+#ifndef EBE_PATCH_ELEMS
+#define EBE_PATCH_ELEMS 64
+#endif
+#ifndef EBE_PATCH_NODES
+#define EBE_PATCH_NODES 192
+#endif
+#ifndef EBE_PATCH_THREADS
+#define EBE_PATCH_THREADS 512
+#endif
+constexpr int kPatchElems = EBE_PATCH_ELEMS;
+constexpr int kPatchNodes = EBE_PATCH_NODES;
+constexpr int kPatchCorners = 64;                 // corner nodes of a patch (the linear level)
+constexpr int kPatchThreads = EBE_PATCH_THREADS;  // workgroup size cap of the patch kernels
 
 // Patch tables of one level (0: all nodes of the quadratic mesh, 1: corners).
 struct PatchLevel {
@@ -75,8 +85,7 @@ struct PatchLevel {
   DBuf pnode;   // int32 [entries] node id | fix bits << 28 | shared << 31
   DBuf pslot;   // int32 [entries] staging slot of a shared entry, -1 otherwise
   DBuf snode;   // int32 [nshared] shared node id | fix bits << 28, increasing id
-  DBuf soff;    // int32 [nshared+1] offsets into sslot
-  DBuf sslot;   // int32 [nslots] staging slots of each shared node, in patch order
+  DBuf soff;    // int32 [nshared+1] first staging slot of each shared node (its slots are consecutive)
   DBuf stage;   // staging buffer [nslots][3][nrhs] of the product's dtype
   int64_t nslots = 0, nshared = 0, entries = 0;
   int max_nodes = 0;
@@ -118,11 +127,12 @@ hipError_t launch_ebe_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* 
                          bool bc, hipStream_t s);
 hipError_t launch_ebe_p1(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y,
                          bool bc, hipStream_t s);
-// general form: order 2 (quadratic) or 1 (linear); add: y += K x instead of
+// general form: order 2 (quadratic) or 1 (linear); mask_in: zero x's fixed
+// DOFs while gathering; bc: zero y's fixed DOFs; add: y += K x instead of
 // y = K x; the kernels do nothing when gate is non-null and *gate == 0 on the
 // device.  The staging buffers must have been sized by ensure_stage.
-hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,
-                      bool add, const int* gate, hipStream_t s);
+hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in,
+                      bool bc, bool add, const int* gate, hipStream_t s);
 hipError_t launch_diag_blocks(const ebe_mesh* m, int level, double* blk6, hipStream_t s);
 hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6, double* inv64,
                                 float* inv32, hipStream_t s);

@@ -92,34 +92,88 @@ EBE_HD void stress(const T e[6], T cl, T cm, T S[6]) {
   S[5] = cm * e[5];
 }
 
+// w = engineering strain of d (x) g (one multiply per product, the second
+// product of each shear pair fused)
+template <typename T>
+EBE_HD void set_eng(T w[6], const T d[3], const T g[3]) {
+  w[0] = d[0] * g[0];
+  w[1] = d[1] * g[1];
+  w[2] = d[2] * g[2];
+  w[3] = d[1] * g[2];
+  w[3] += d[2] * g[1];
+  w[4] = d[2] * g[0];
+  w[4] += d[0] * g[2];
+  w[5] = d[0] * g[1];
+  w[5] += d[1] * g[0];
+}
+
+// w += engineering strain of d (x) g, as nine fused multiply-adds
+template <typename T>
+EBE_HD void fma_eng(T w[6], const T d[3], const T g[3]) {
+  w[0] += d[0] * g[0];
+  w[1] += d[1] * g[1];
+  w[2] += d[2] * g[2];
+  w[3] += d[1] * g[2];
+  w[3] += d[2] * g[1];
+  w[4] += d[2] * g[0];
+  w[4] += d[0] * g[2];
+  w[5] += d[0] * g[1];
+  w[5] += d[1] * g[0];
+}
+
+// out += P g for symmetric P
+template <typename T>
+EBE_HD void sym_mv_acc(const T P[6], const T g[3], T out[3]) {
+  out[0] += P[0] * g[0];
+  out[0] += P[5] * g[1];
+  out[0] += P[4] * g[2];
+  out[1] += P[5] * g[0];
+  out[1] += P[1] * g[1];
+  out[1] += P[3] * g[2];
+  out[2] += P[4] * g[0];
+  out[2] += P[3] * g[1];
+  out[2] += P[2] * g[2];
+}
+
 // f = K_e u for a straight 10-node tetrahedron; cl = lambda V / 20, cm = mu V / 20.
+//
+// Written with H_k = 4 (V_k + sum_{m != k} E_km) - sum_i V_i, V_i = u_i (x) G_i
+// and E_km = u_{km} (x) G_m (using G_k = -sum_{m != k} G_m), which needs 16
+// outer products and no differences; every accumulation is a fused
+// multiply-add.  About 440 floating-point instructions per element and case.
 template <typename T>
 EBE_HD void p2_forces(const T G[4][3], T cl, T cm, const T u[10][3], T f[10][3]) {
-  T a6[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  T Vv[4][6];
 #pragma unroll
-  for (int i = 1; i < 4; ++i) {
-    const T d[3] = {u[i][0] - u[0][0], u[i][1] - u[0][1], u[i][2] - u[0][2]};
-    acc_eng(a6, d, G[i]);
-  }
+  for (int i = 0; i < 4; ++i) set_eng(Vv[i], u[i], G[i]);
+  T A[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) A[c] = (Vv[0][c] + Vv[1][c]) + (Vv[2][c] + Vv[3][c]);
   T S[4][6];
-  T Ssum[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  T Ssum[6];
+  const T cm2 = cm + cm;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    T w6[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    T w[6];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      if (m == k) continue;
-      const int j = edge_node(k, m);
-      const T d[3] = {u[j][0] - u[k][0], u[j][1] - u[k][1], u[j][2] - u[k][2]};
-      acc_eng(w6, d, G[m]);
-    }
-    T e6[6];
+    for (int c = 0; c < 6; ++c) w[c] = Vv[k][c];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) e6[c] = T(4) * w6[c] - a6[c];
-    stress(e6, cl, cm, S[k]);
+    for (int m = 0; m < 4; ++m)
+      if (m != k) fma_eng(w, u[edge_node(k, m)], G[m]);
+    T e[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) Ssum[c] += S[k][c];
+    for (int c = 0; c < 6; ++c) e[c] = T(4) * w[c] - A[c];
+    const T clt = cl * ((e[0] + e[1]) + e[2]);
+    S[k][0] = cm2 * e[0] + clt;
+    S[k][1] = cm2 * e[1] + clt;
+    S[k][2] = cm2 * e[2] + clt;
+    S[k][3] = cm * e[3];
+    S[k][4] = cm * e[4];
+    S[k][5] = cm * e[5];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Ssum[c] = (k == 0) ? S[k][c] : Ssum[c] + S[k][c];
   }
+  // corners: f_i = (4 S'_i - S') G_i
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     T P[6];
@@ -127,20 +181,19 @@ EBE_HD void p2_forces(const T G[4][3], T cl, T cm, const T u[10][3], T f[10][3])
     for (int c = 0; c < 6; ++c) P[c] = T(4) * S[i][c] - Ssum[c];
     sym_mv(P, G[i], f[i]);
   }
-  // T'_k = 4 (S'_k + S'), reusing S
+  // edges: f_km = T'_m G_k + T'_k G_m with T'_k = 4 (S'_k + S')
+  T S4[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) S4[c] = T(4) * Ssum[c];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) S[k][c] = T(4) * (S[k][c] + Ssum[c]);
+    for (int c = 0; c < 6; ++c) S[k][c] = T(4) * S[k][c] + S4[c];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const int k = edge_end(q, 0), m = edge_end(q, 1);
-    T t1[3], t2[3];
-    sym_mv(S[m], G[k], t1);
-    sym_mv(S[k], G[m], t2);
-    f[4 + q][0] = t1[0] + t2[0];
-    f[4 + q][1] = t1[1] + t2[1];
-    f[4 + q][2] = t1[2] + t2[2];
+    sym_mv(S[m], G[k], f[4 + q]);
+    sym_mv_acc(S[k], G[m], f[4 + q]);
   }
 }
 

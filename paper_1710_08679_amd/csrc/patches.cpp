@@ -22,7 +22,7 @@ namespace {
 
 struct LevelTables {
   std::vector<int32_t> poff, pnode, pslot;      // per patch entries
-  std::vector<int32_t> snode, soff, sslot;      // reduction of shared nodes
+  std::vector<int32_t> snode, soff;             // reduction of shared nodes
   int64_t nslots = 0;
   int max_nodes = 0;
 };
@@ -52,28 +52,24 @@ void build_level(const std::vector<int32_t>& pelem, int nloc, int64_t n_nodes, c
     t.poff[p + 1] = int32_t(t.pnode.size());
     t.max_nodes = std::max(t.max_nodes, t.poff[p + 1] - base);
   }
-  // staging slots for shared entries, in entry (= patch) order
+  // Staging slots: the partial sums of one shared node sit in consecutive
+  // slots, nodes in increasing id, a node's partials in patch order.  start[]
+  // is cumulative over shared nodes only, so it doubles as the offset list.
+  std::vector<int64_t> start(n_nodes + 1, 0);
+  for (int64_t v = 0; v < n_nodes; ++v) start[v + 1] = start[v] + (count[v] > 1 ? count[v] : 0);
+  t.nslots = start[n_nodes];
   t.pslot.assign(t.pnode.size(), -1);
-  int64_t slot = 0;
+  std::vector<int64_t> fill(start.begin(), start.end() - 1);
   for (size_t i = 0; i < t.pnode.size(); ++i) {
     const int32_t v = t.pnode[i];
-    if (count[v] > 1) t.pslot[i] = int32_t(slot++);
+    if (count[v] > 1) t.pslot[i] = int32_t(fill[v]++);
   }
-  t.nslots = slot;
-  // shared nodes in increasing id, each with its slots in patch order;
-  // start[] is cumulative over shared nodes only, so it doubles as soff
   t.snode.clear();
   t.soff.assign(1, 0);
-  std::vector<int32_t> start(n_nodes + 1, 0);
-  for (int64_t v = 0; v < n_nodes; ++v) start[v + 1] = start[v] + (count[v] > 1 ? count[v] : 0);
-  t.sslot.assign(size_t(start[n_nodes]), 0);
-  std::vector<int32_t> fill(start.begin(), start.end() - 1);
-  for (size_t i = 0; i < t.pnode.size(); ++i)
-    if (t.pslot[i] >= 0) t.sslot[size_t(fill[t.pnode[i]]++)] = t.pslot[i];
   for (int64_t v = 0; v < n_nodes; ++v)
     if (count[v] > 1) {
       t.snode.push_back(int32_t(v) | (int32_t(fix[v]) << kIdxBits));
-      t.soff.push_back(start[v + 1]);
+      t.soff.push_back(int32_t(start[v + 1]));
     }
   // pack node words: id | fix bits | shared flag
   for (size_t i = 0; i < t.pnode.size(); ++i) {
@@ -151,7 +147,6 @@ ebe_status build_patches(ebe_mesh* m, const int32_t* conn10, const uint8_t* fix,
     if ((st = up(L[l]->pslot, T[l]->pslot, s)) != EBE_OK) return st;
     if ((st = up(L[l]->snode, T[l]->snode, s)) != EBE_OK) return st;
     if ((st = up(L[l]->soff, T[l]->soff, s)) != EBE_OK) return st;
-    if ((st = up(L[l]->sslot, T[l]->sslot, s)) != EBE_OK) return st;
     L[l]->nslots = T[l]->nslots;
     L[l]->nshared = int64_t(T[l]->snode.size());
     L[l]->entries = int64_t(T[l]->pnode.size());

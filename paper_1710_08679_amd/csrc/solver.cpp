@@ -86,7 +86,8 @@ ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int
                        SolverState& st, hipStream_t s) {
   const int order = level == 0 ? 2 : 1;
   InnerScalars* din = &st.sc->inner[level];
-  EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, u, q, true, false, &st.sc->outer_active, s));
+  // all solver vectors are kept zero on fixed DOFs, so inputs need no masking
+  EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, u, q, false, true, false, &st.sc->outer_active, s));
   EBE_K(sk_inner_init<T>(m, level, r, q, e, nr, eps, nmax, st, s));
   int enq = 0;
   int chunk = level == 0 ? 3 : 4;
@@ -94,7 +95,7 @@ ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int
     const int k = std::min(chunk, nmax - 1 - enq);
     for (int c = 0; c < k; ++c) {
       EBE_K(sk_inner_p<T>(m, level, e, p, q, nr, st, s));
-      EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, p, q, true, false, &din->active, s));
+      EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, p, q, false, true, false, &din->active, s));
       EBE_K(sk_inner_alpha<T>(m, level, p, q, nr, st, s));
       EBE_K(sk_inner_update<T>(m, level, e, u, q, p, nr, eps, nmax, st, s));
     }
@@ -204,7 +205,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   if (o.use_x0) EBE_K(sk_mask_u(m, u, nr, st, s));
   else EBE_K(launch_fill_zero(u, vbytes, s));
   // lines 4-5: r <= f - sum_i K_i u_i
-  EBE_K(launch_ebe(m, 2, EBE_F64, nr, u, b.q, true, false, nullptr, s));
+  EBE_K(launch_ebe(m, 2, EBE_F64, nr, u, b.q, false, true, false, nullptr, s));
   EBE_K(sk_outer_init(m, f, b.q, b.r, nr, o.tol, st, s));
 
   SolverScalars* h = nullptr;
@@ -224,7 +225,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
         EBE_K(sk_outer_z_bj(m, b.r, b.q, b.z, nr, st, s));   // z <= M^-1 r ; (z,q), (z,r)
       }
       EBE_K(sk_outer_p(m, b.z, b.p, b.q, nr, st, s));        // p <= z + beta p ; q <= 0
-      EBE_K(launch_ebe(m, 2, EBE_F64, nr, b.p, b.q, true, false, &st.sc->outer_active, s));  // q <= K p
+      EBE_K(launch_ebe(m, 2, EBE_F64, nr, b.p, b.q, false, true, false, &st.sc->outer_active, s));  // q <= K p
       EBE_K(sk_outer_alpha(m, b.p, b.q, nr, st, s));         // alpha <= rho / (p, q)
       EBE_K(sk_outer_update(m, b.r, u, b.q, b.p, nr, o.tol, o.max_outer, st, s));  // r, u updates
     }

@@ -182,7 +182,6 @@ struct BodyPUpdate {
       const int64_t i = NC_IDX(node, c, col);
       // beta = 0 starts a new direction: do not read p (it may hold stale bits)
       p[i] = (b == T(0)) ? z[i] : z[i] + b * p[i];
-      q[i] = T(0);
     }
   }
 };
@@ -292,9 +291,6 @@ struct BodyInnerP {
       p[i0 + nr] = z1 + b * p[i0 + nr];
       p[i0 + 2 * nr] = z2 + b * p[i0 + 2 * nr];
     }
-    q[i0] = T(0);
-    q[i0 + nr] = T(0);
-    q[i0 + 2 * nr] = T(0);
   }
 };
 
