@@ -101,7 +101,7 @@ def cpu_baseline(mesh, n, n_elem_sample):
             "host_cpus": os.cpu_count()}
 
 
-def solver_block(torch, ebe, meshgen):
+def solver_block(torch, ebe, meshgen, modes=("mixed_mg2", "fp64_mg2", "fp64_pcge")):
     """Solves per second of the multi-case crust workload: 96x96x48 hexes x 6
     = 2,654,208 tetrahedra, 16 dislocation-pair cases, to 1e-8."""
     m = meshgen.crust_mesh(96, 96, 48)
@@ -112,9 +112,10 @@ def solver_block(torch, ebe, meshgen):
     out = {"workload": "crust 96x96x48 hexes x 6 tets, 3 layers, 16 cases, tol 1e-8 (unsquared, max over cases)",
            "elements": m.n_elem, "dof": m.n_dof, "runs": []}
     ref = None
-    for name, precond, mode in (("mixed_mg2", ebe.PREC_MG2, ebe.MODE_MIXED),
-                                ("fp64_mg2", ebe.PREC_MG2, ebe.MODE_FP64),
-                                ("fp64_pcge", ebe.PREC_PCGE, ebe.MODE_FP64)):
+    table = {"mixed_mg2": (ebe.PREC_MG2, ebe.MODE_MIXED), "fp64_mg2": (ebe.PREC_MG2, ebe.MODE_FP64),
+             "fp64_pcge": (ebe.PREC_PCGE, ebe.MODE_FP64)}
+    for name in modes:
+        precond, mode = table[name]
         gm.solve(fd, precond=precond, mode=mode, tol=1e-8)  # warm-up: block Jacobi set-up, workspace
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -146,6 +147,7 @@ def main():
     ap.add_argument("--variants", default="f64:1,f64:4,f64:16,f32:1,f32:4,f32:16",
                     help="comma list of dtype:n products to time")
     ap.add_argument("--no-solver", action="store_true")
+    ap.add_argument("--solver-modes", default="mixed_mg2,fp64_mg2,fp64_pcge")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=100000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -245,7 +247,7 @@ def main():
                        "elements": E, "nodes": N, "dof": 3 * N, "nrhs": 16},
             "roofline": roof, "roofline_alt": alt, "variants": variants}
     if not args.no_solver:
-        line["solver"] = solver_block(torch, ebe, meshgen)
+        line["solver"] = solver_block(torch, ebe, meshgen, args.solver_modes.split(","))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(mesh, 16, args.cpu_elems)
     print(json.dumps(line))

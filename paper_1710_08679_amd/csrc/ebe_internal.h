@@ -51,7 +51,7 @@ class DBuf {
 struct Workspace {
   int nrhs_cap = 0;
   // FP64 outer vectors [N][3][nrhs]
-  DBuf r, p, q, z;
+  DBuf r, p, q;
   // preconditioner vectors (FP32 or FP64) on level 0 and level 1
   DBuf rb, ub, e0, p0, q0;
   DBuf r1, u1, e1, p1, q1;
@@ -78,6 +78,11 @@ constexpr int kPatchElems = EBE_PATCH_ELEMS;
 constexpr int kPatchNodes = EBE_PATCH_NODES;
 constexpr int kPatchCorners = 64;                 // corner nodes of a patch (the linear level)
 constexpr int kPatchThreads = EBE_PATCH_THREADS;  // workgroup size cap of the patch kernels
+// (x, K x) sums of the patch kernels: workgroup w adds its per-case sums to
+// slot w % kGammaSlots (one 128-byte line each), and the last workgroup to
+// finish folds the slots into the caller's result.
+constexpr int kGammaSlots = 64;
+constexpr size_t kGammaBytes = size_t(kGammaSlots) * EBE_MAX_RHS * sizeof(double) + 64;  // slots + counter
 
 // Patch tables of one level (0: all nodes of the quadratic mesh, 1: corners).
 struct PatchLevel {
@@ -113,6 +118,7 @@ struct ebe_mesh {
   ebe::DBuf lconn;      // uint8 [E][16] patch-local ids of the 10 nodes (padded to 16 bytes)
   ebe::DBuf lconn1;     // uint8 [E][4]  patch-local ids of the 4 corners
   ebe::PatchLevel pl[2];
+  ebe::DBuf gacc;       // kGammaBytes: (x, K x) slots, then the arrival counter; zero between products
   // 3x3 block Jacobi: inverted symmetric blocks (xx yy zz yz zx xy), per level
   ebe::DBuf minv64[2], minv32[2];
   bool minv_ready = false;
@@ -130,9 +136,11 @@ hipError_t launch_ebe_p1(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* 
 // general form: order 2 (quadratic) or 1 (linear); mask_in: zero x's fixed
 // DOFs while gathering; bc: zero y's fixed DOFs; add: y += K x instead of
 // y = K x; the kernels do nothing when gate is non-null and *gate == 0 on the
-// device.  The staging buffers must have been sized by ensure_stage.
+// device.  gamma (optional, device [nrhs] FP64): gamma[r] += (x_r, K x_r)
+// formed element by element.  The staging buffers must have been sized by
+// ensure_stage.
 hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in,
-                      bool bc, bool add, const int* gate, hipStream_t s);
+                      bool bc, bool add, const int* gate, hipStream_t s, double* gamma = nullptr);
 hipError_t launch_diag_blocks(const ebe_mesh* m, int level, double* blk6, hipStream_t s);
 hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6, double* inv64,
                                 float* inv32, hipStream_t s);

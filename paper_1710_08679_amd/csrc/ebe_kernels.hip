@@ -70,13 +70,16 @@ __device__ __forceinline__ int spread_element(int j, int ne) {
 
 // MASK_IN: zero the fixed DOFs of x while gathering (y = P K P x); callers
 // whose x is already zero there (the solver) skip it.  bc: zero the fixed
-// DOFs of y.  add: y += K x instead of y = K x.
+// DOFs of y.  add: y += K x instead of y = K x.  gamma (optional): gamma[r]
+// += (x_r, K x_r) formed element by element as sum_e x_eᵀ K_e x_e, which is
+// what CG needs from q = K p without a separate inner-product pass.
 template <typename T, int NR, int ORDER, bool MASK_IN>
 __global__ __launch_bounds__(threads_for(NR)) void k_ebe_patch(
     const int32_t* __restrict__ conn, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
     const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
     const double4* __restrict__ xv, const typename Pair<T>::type* __restrict__ lame, const T* __restrict__ x,
-    T* __restrict__ y, T* __restrict__ stage, int bc, int add, const int* __restrict__ gate) {
+    T* __restrict__ y, T* __restrict__ stage, int bc, int add, double* __restrict__ gamma,
+    double* __restrict__ gslot, unsigned* __restrict__ gcount, const int* __restrict__ gate) {
   constexpr int NLOC = ORDER == 2 ? 10 : 4;
   constexpr int W = 3 * NR;
   constexpr int TPB = threads_for(NR);
@@ -86,12 +89,14 @@ __global__ __launch_bounds__(threads_for(NR)) void k_ebe_patch(
   __shared__ T geo[kPatchElems][14];
   __shared__ int32_t words[MAXN];
   __shared__ int32_t slots[MAXN];
+  __shared__ double gsum[NR];
   if (gate && *gate == 0) return;
   const int tid = threadIdx.x;
   const int p = xcd_patch(blockIdx.x, gridDim.x);
   const int e0 = pelem[p], ne = pelem[p + 1] - e0;
   const int o0 = poff[p], nn = poff[p + 1] - o0;
   for (int i = tid; i < nn * W; i += TPB) F[i] = 0.0;
+  if (tid < NR) gsum[tid] = 0.0;
   for (int i = tid; i < nn; i += TPB) {
     words[i] = pnode[o0 + i];
     slots[i] = pslot[o0 + i];
@@ -111,6 +116,11 @@ __global__ __launch_bounds__(threads_for(NR)) void k_ebe_patch(
     geo[el][13] = T(lm.y) * s;
   }
   __syncthreads();
+  // (x, K x) contributions: when n divides 64 a work-item keeps one case for
+  // all its items, so it sums them in a register and the lanes of a case are
+  // combined across the wavefront before one LDS atomic per case.
+  constexpr bool kLaneCase = (64 % NR) == 0;
+  double en_acc = 0.0;
   const int nj = spread_count<NR>(ne);
   for (int w = tid; w < nj * NR; w += TPB) {
     const int j = w / NR;
@@ -158,6 +168,22 @@ __global__ __launch_bounds__(threads_for(NR)) void k_ebe_patch(
 #pragma unroll
       for (int c = 0; c < 3; ++c) atomicAdd(fp + c * NR, double(f[a][c]));
     }
+    if (gamma) {
+      T en = T(0);
+#pragma unroll
+      for (int a = 0; a < NLOC; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) en += u[a][c] * f[a][c];
+      if constexpr (kLaneCase) en_acc += double(en);
+      else atomicAdd(&gsum[r], double(en));
+    }
+  }
+  if constexpr (kLaneCase) {
+    if (gamma) {
+#pragma unroll
+      for (int off = 32; off >= NR; off >>= 1) en_acc += __shfl_xor(en_acc, off, 64);
+      if ((tid & 63) < NR) atomicAdd(&gsum[tid & 63], en_acc);
+    }
   }
   __syncthreads();
   const int eo = tid / W;
@@ -180,6 +206,34 @@ __global__ __launch_bounds__(threads_for(NR)) void k_ebe_patch(
       }
     }
   }
+  if (!gamma) return;
+  // Spread the device-scope additions over kGammaSlots lines (thousands of
+  // workgroups adding to one line serialise on it), then let the last
+  // workgroup to arrive fold the slots into gamma, clearing them as it reads.
+  // Every access of this protocol is a device-scope atomic, so no fence is
+  // needed (an agent-scope fence writes back the XCD's L2, which costs far
+  // more than the product when every workgroup does it): a work-item waits
+  // for the value its addition returns, which proves the addition done,
+  // before the workgroup arrives at the counter.
+  __shared__ bool last;
+  if (tid < NR) {
+    const double old = __hip_atomic_fetch_add(gslot + (blockIdx.x % kGammaSlots) * EBE_MAX_RHS + tid, gsum[tid],
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("" ::"v"(old));
+  }
+  __syncthreads();
+  if (tid == 0) last = atomicAdd(gcount, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  if (tid < NR) gsum[tid] = 0.0;
+  __syncthreads();
+  for (int i = tid; i < kGammaSlots * NR; i += TPB) {
+    const int sl = i / NR, r = i - sl * NR;
+    atomicAdd(&gsum[r], atomicExch(gslot + sl * EBE_MAX_RHS + r, 0.0));
+  }
+  __syncthreads();
+  if (tid < NR) unsafeAtomicAdd(gamma + tid, gsum[tid]);
+  if (tid == 0) atomicExch(gcount, 0u);
 }
 
 // y[shared node] (=|+=) sum of its consecutive staged partials (patch order).
@@ -245,7 +299,7 @@ __global__ __launch_bounds__(256) void k_reduce_shared(const int32_t* __restrict
 
 template <typename T, int NR, int ORDER, bool MASK_IN>
 void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool bc, bool add,
-                  const int* gate, hipStream_t s) {
+                  const int* gate, hipStream_t s, double* gamma) {
   using P = typename Pair<T>::type;
   const P* lame = (sizeof(T) == 8) ? reinterpret_cast<const P*>(m->lame64.as<void>())
                                    : reinterpret_cast<const P*>(m->lame32.as<void>());
@@ -253,20 +307,21 @@ void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y
                      s, m->conn.as<int32_t>(), ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(),
                      m->pelem.as<int32_t>(), L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(),
                      m->xv.as<double4>(), lame, static_cast<const T*>(x), static_cast<T*>(y), stage, int(bc),
-                     int(add), gate);
+                     int(add), gamma, m->gacc.as<double>(),
+                     reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64), gate);
 }
 
 template <typename T, int NR>
 hipError_t ebe_dispatch_p(int order, const ebe_mesh* m, const void* x, void* y, bool mask_in, bool bc, bool add,
-                          const int* gate, hipStream_t s) {
+                          const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   T* stage = L.stage.as<T>();
   if (order == 2) {
-    if (mask_in) launch_patch<T, NR, 2, true>(m, L, x, y, stage, bc, add, gate, s);
-    else launch_patch<T, NR, 2, false>(m, L, x, y, stage, bc, add, gate, s);
+    if (mask_in) launch_patch<T, NR, 2, true>(m, L, x, y, stage, bc, add, gate, s, gamma);
+    else launch_patch<T, NR, 2, false>(m, L, x, y, stage, bc, add, gate, s, gamma);
   } else {
-    if (mask_in) launch_patch<T, NR, 1, true>(m, L, x, y, stage, bc, add, gate, s);
-    else launch_patch<T, NR, 1, false>(m, L, x, y, stage, bc, add, gate, s);
+    if (mask_in) launch_patch<T, NR, 1, true>(m, L, x, y, stage, bc, add, gate, s, gamma);
+    else launch_patch<T, NR, 1, false>(m, L, x, y, stage, bc, add, gate, s, gamma);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || L.nshared == 0) return e;
@@ -279,10 +334,10 @@ hipError_t ebe_dispatch_p(int order, const ebe_mesh* m, const void* x, void* y, 
 
 template <typename T>
 hipError_t ebe_dispatch(int order, const ebe_mesh* m, int nrhs, const void* x, void* y, bool mask_in, bool bc,
-                        bool add, const int* gate, hipStream_t s) {
+                        bool add, const int* gate, hipStream_t s, double* gamma) {
   switch (nrhs) {
 #define EBE_CASE(n) \
-  case n: return ebe_dispatch_p<T, n>(order, m, x, y, mask_in, bc, add, gate, s);
+  case n: return ebe_dispatch_p<T, n>(order, m, x, y, mask_in, bc, add, gate, s, gamma);
     EBE_CASE(1) EBE_CASE(2) EBE_CASE(3) EBE_CASE(4) EBE_CASE(5) EBE_CASE(6) EBE_CASE(7) EBE_CASE(8)
     EBE_CASE(9) EBE_CASE(10) EBE_CASE(11) EBE_CASE(12) EBE_CASE(13) EBE_CASE(14) EBE_CASE(15) EBE_CASE(16)
 #undef EBE_CASE
@@ -308,12 +363,12 @@ ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes) {
 }
 
 hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in,
-                      bool bc, bool add, const int* gate, hipStream_t s) {
+                      bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   const size_t need = size_t(L.nslots) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4);
   if (L.stage.bytes() < need || m->n_patch < 1) return hipErrorInvalidValue;  // staging not sized: host bug
-  return dt == EBE_F64 ? ebe_dispatch<double>(order, m, nrhs, x, y, mask_in, bc, add, gate, s)
-                       : ebe_dispatch<float>(order, m, nrhs, x, y, mask_in, bc, add, gate, s);
+  return dt == EBE_F64 ? ebe_dispatch<double>(order, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma)
+                       : ebe_dispatch<float>(order, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma);
 }
 
 hipError_t launch_ebe_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,

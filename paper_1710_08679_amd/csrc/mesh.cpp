@@ -265,8 +265,10 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
   if (st == EBE_OK) st = m->lame64.alloc(size_t(E) * 2 * sizeof(double));
   if (st == EBE_OK) st = m->lame32.alloc(size_t(E) * 2 * sizeof(float));
   if (st == EBE_OK) st = build_patches(m, conn10, fix.data(), s);
+  if (st == EBE_OK) st = m->gacc.alloc(kGammaBytes);
   if (st == EBE_OK) {
     hipError_t he = launch_lame(m, s);
+    if (he == hipSuccess) he = launch_fill_zero(m->gacc.as<void>(), kGammaBytes, s);
     if (he == hipSuccess) he = hipStreamSynchronize(s);
     if (he != hipSuccess) {
       set_error("ebe_mesh_create: upload failed: %s", hipGetErrorString(he));

@@ -26,7 +26,7 @@ namespace {
 constexpr int kMaxBlocks = 1024;
 
 struct Bufs {
-  double *r, *p, *q, *z;  // outer, [N][3][n] FP64
+  double *r, *p, *q;  // outer, [N][3][n] FP64
   void *rb, *ub, *e0, *p0, *q0;  // level 0
   void *r1, *u1, *e1, *p1, *q1;  // level 1
 };
@@ -36,7 +36,7 @@ ebe_status ensure_workspace(ebe_mesh* m, int nr) {
   const size_t v0 = size_t(m->n_nodes) * 3 * nr * sizeof(double);
   const size_t v1 = size_t(m->n_vertices) * 3 * nr * sizeof(double);
   ebe_status st = EBE_OK;
-  DBuf* outer[] = {&w.r, &w.p, &w.q, &w.z, &w.rb, &w.ub, &w.e0, &w.p0, &w.q0};
+  DBuf* outer[] = {&w.r, &w.p, &w.q, &w.rb, &w.ub, &w.e0, &w.p0, &w.q0};
   for (DBuf* b : outer)
     if ((st = b->alloc(v0)) != EBE_OK) return st;
   DBuf* coarse[] = {&w.r1, &w.u1, &w.e1, &w.p1, &w.q1};
@@ -95,8 +95,7 @@ ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int
     const int k = std::min(chunk, nmax - 1 - enq);
     for (int c = 0; c < k; ++c) {
       EBE_K(sk_inner_p<T>(m, level, e, p, q, nr, st, s));
-      EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, p, q, false, true, false, &din->active, s));
-      EBE_K(sk_inner_alpha<T>(m, level, p, q, nr, st, s));
+      EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, p, q, false, true, false, &din->active, s, din->gamma));
       EBE_K(sk_inner_update<T>(m, level, e, u, q, p, nr, eps, nmax, st, s));
     }
     enq += k;
@@ -109,7 +108,8 @@ ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int
   return EBE_OK;
 }
 
-// Lines 9-18 of Algorithm 1(a): z from r through both inner levels.
+// Lines 9-18 of Algorithm 1(a): z from r through both inner levels, then the
+// new search direction p from z.
 template <typename T>
 ebe_status mg2_precondition(ebe_mesh* m, int nr, const ebe_pcg_opts& o, const Bufs& b, SolverState& st,
                             hipStream_t s) {
@@ -132,7 +132,8 @@ ebe_status mg2_precondition(ebe_mesh* m, int nr, const ebe_pcg_opts& o, const Bu
   rs = inner_solve<T>(m, 0, rb, ub, static_cast<T*>(b.e0), static_cast<T*>(b.p0), static_cast<T*>(b.q0), nr,
                       o.inner_eps[0], o.inner_max[0], st, s);
   if (rs != EBE_OK) return rs;
-  EBE_K(sk_outer_z_cast<T>(m, ub, b.r, b.q, b.z, nr, st, s));  // z <= u_bar ; (z,q), (z,r)
+  EBE_K(sk_outer_z_cast<T>(m, ub, b.r, b.q, nr, st, s));  // z = u_bar: (z,q), (z,r), beta
+  EBE_K(sk_outer_p_cast<T>(m, ub, b.p, nr, st, s));       // p <= z + beta p
   return EBE_OK;
 }
 
@@ -194,7 +195,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   st.sc = w.scal.as<SolverScalars>();
   st.partials = w.partials.as<void>();
   st.counter = w.counter.as<unsigned>();
-  Bufs b{w.r.as<double>(), w.p.as<double>(), w.q.as<double>(), w.z.as<double>(), w.rb.as<void>(),
+  Bufs b{w.r.as<double>(), w.p.as<double>(), w.q.as<double>(), w.rb.as<void>(),
          w.ub.as<void>(), w.e0.as<void>(), w.p0.as<void>(), w.q0.as<void>(), w.r1.as<void>(),
          w.u1.as<void>(), w.e1.as<void>(), w.p1.as<void>(), w.q1.as<void>()};
   const size_t vbytes = size_t(m->n_nodes) * 3 * nr * sizeof(double);
@@ -222,12 +223,12 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
                                         : mg2_precondition<double>(m, nr, o, b, st, s);
         if (rs != EBE_OK) return rs;
       } else {
-        EBE_K(sk_outer_z_bj(m, b.r, b.q, b.z, nr, st, s));   // z <= M^-1 r ; (z,q), (z,r)
+        EBE_K(sk_outer_z_bj(m, b.r, b.q, nr, st, s));   // z = M^-1 r: (z,q), (z,r), beta
+        EBE_K(sk_outer_p_bj(m, b.r, b.p, nr, st, s));   // p <= z + beta p
       }
-      EBE_K(sk_outer_p(m, b.z, b.p, b.q, nr, st, s));        // p <= z + beta p ; q <= 0
-      EBE_K(launch_ebe(m, 2, EBE_F64, nr, b.p, b.q, false, true, false, &st.sc->outer_active, s));  // q <= K p
-      EBE_K(sk_outer_alpha(m, b.p, b.q, nr, st, s));         // alpha <= rho / (p, q)
-      EBE_K(sk_outer_update(m, b.r, u, b.q, b.p, nr, o.tol, o.max_outer, st, s));  // r, u updates
+      // q <= K p, gamma <= (p, K p)
+      EBE_K(launch_ebe(m, 2, EBE_F64, nr, b.p, b.q, false, true, false, &st.sc->outer_active, s, st.sc->gamma));
+      EBE_K(sk_outer_update(m, b.r, u, b.q, b.p, nr, o.tol, o.max_outer, st, s));  // alpha; r, u updates
     }
     enq += k;
     if ((rs = read_scalars(m, s, &h)) != EBE_OK) return rs;

@@ -23,7 +23,7 @@ namespace {
 
 constexpr int kMaxBlocks = 1024;
 
-inline int block_for(int nr) { return (256 / nr) * nr; }
+__host__ __device__ constexpr int block_for(int nr) { return (256 / nr) * nr; }
 
 template <typename T>
 __device__ __forceinline__ void bj_apply(const T* __restrict__ m, T x0, T x1, T x2, T& y0, T& y1, T& y2) {
@@ -42,14 +42,18 @@ __global__ __launch_bounds__(256) void k_nodecase(Body body, Epi epi, int64_t n_
                                                   Acc* __restrict__ partials, unsigned* __restrict__ counter,
                                                   const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
-  const int bd = blockDim.x;
+  // 256 work-items per workgroup; the first bd = (256 / nr) nr of them walk
+  // the (node, case) units with a stride that is a multiple of nr, so each
+  // keeps one case; the others only join the reductions.
+  const int bd = block_for(nr);
   const int col = threadIdx.x % nr;
   Acc acc[NDOT > 0 ? NDOT : 1];
 #pragma unroll
   for (int d = 0; d < (NDOT > 0 ? NDOT : 1); ++d) acc[d] = Acc(0);
   const int64_t units = n_nodes * nr;
-  for (int64_t u = int64_t(blockIdx.x) * bd + threadIdx.x; u < units; u += int64_t(gridDim.x) * bd)
-    body(u / nr, col, acc);
+  if (int(threadIdx.x) < bd)
+    for (int64_t u = int64_t(blockIdx.x) * bd + threadIdx.x; u < units; u += int64_t(gridDim.x) * bd)
+      body(u / nr, col, acc);
   if constexpr (NDOT > 0) {
     __shared__ Acc sh[256 * NDOT];
     __shared__ bool last;
@@ -69,13 +73,22 @@ __global__ __launch_bounds__(256) void k_nodecase(Body body, Epi epi, int64_t n_
     __syncthreads();
     if (!last) return;
     __threadfence();
+    // Sum the per-workgroup partials with all 256 work-items: output o gets
+    // partials b = t, t + 256, ... from work-item t, then a fixed-order
+    // wavefront tree and a sum over the 4 wavefronts (deterministic).
     __shared__ double tot[3 * EBE_MAX_RHS];
-    if (threadIdx.x < nsum) {
+    __shared__ double wsum[4][3 * EBE_MAX_RHS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 0; o < nsum; ++o) {
       double s = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b)
-        s += double(__builtin_nontemporal_load(&partials[size_t(b) * nsum + threadIdx.x]));
-      tot[threadIdx.x] = s;
+      for (unsigned b = threadIdx.x; b < gridDim.x; b += 256) s += double(partials[size_t(b) * nsum + o]);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == 0) wsum[wave][o] = s;
     }
+    __syncthreads();
+    if (threadIdx.x < nsum) tot[threadIdx.x] = (wsum[0][threadIdx.x] + wsum[1][threadIdx.x]) +
+                                               (wsum[2][threadIdx.x] + wsum[3][threadIdx.x]);
     __syncthreads();
     if (threadIdx.x == 0) {
       *counter = 0u;
@@ -91,7 +104,7 @@ hipError_t run_nodecase(Body body, Epi epi, int64_t n_nodes, int nr, SolverState
   int64_t g = (n_nodes * nr + bd - 1) / bd;
   if (g > kMaxBlocks) g = kMaxBlocks;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL((k_nodecase<Acc, NDOT, Body, Epi>), dim3(unsigned(g)), dim3(bd), 0, s, body, epi, n_nodes,
+  hipLaunchKernelGGL((k_nodecase<Acc, NDOT, Body, Epi>), dim3(unsigned(g)), dim3(256), 0, s, body, epi, n_nodes,
                      nr, reinterpret_cast<Acc*>(st.partials), st.counter, gate);
   return hipGetLastError();
 }
@@ -139,19 +152,14 @@ struct BodyOuterInit {
   }
 };
 
-// z = M^-1 r (PCGE) or z = (double) ub (MG2); sums: (z, q), (z, r)
+// The outer preconditioned residual z is never stored: it is M^-1 r (PCGE)
+// or the preconditioner's output u_bar (MG2), recomputed or read where used.
 template <int MODE, typename TU>
-struct BodyOuterZ {
-  const double* minv;  // MODE 0
-  const TU* ub;        // MODE 1
-  const double* r;
-  const double* q;
-  double* z;
-  int nr;
-  __device__ void operator()(int64_t node, int col, double* acc) const {
-    const int64_t i0 = NC_IDX(node, 0, col);
-    const double r0 = r[i0], r1 = r[i0 + nr], r2 = r[i0 + 2 * nr];
-    double z0, z1, z2;
+struct OuterZ {
+  const double* minv;  // MODE 0: z = M^-1 r
+  const TU* ub;        // MODE 1: z = (double) u_bar
+  __device__ __forceinline__ void operator()(int64_t node, int64_t i0, int nr, double r0, double r1, double r2,
+                                             double& z0, double& z1, double& z2) const {
     if (MODE == 0) {
       bj_apply(minv + 6 * node, r0, r1, r2, z0, z1, z2);
     } else {
@@ -159,59 +167,72 @@ struct BodyOuterZ {
       z1 = double(ub[i0 + nr]);
       z2 = double(ub[i0 + 2 * nr]);
     }
-    z[i0] = z0;
-    z[i0 + nr] = z1;
-    z[i0 + 2 * nr] = z2;
+  }
+};
+
+// sums: (z, q) with q the previous K p, and (z, r)
+template <int MODE, typename TU>
+struct BodyOuterZ {
+  OuterZ<MODE, TU> zf;
+  const double* r;
+  const double* q;
+  int nr;
+  __device__ void operator()(int64_t node, int col, double* acc) const {
+    const int64_t i0 = NC_IDX(node, 0, col);
+    const double r0 = r[i0], r1 = r[i0 + nr], r2 = r[i0 + 2 * nr];
+    double z0, z1, z2;
+    zf(node, i0, nr, r0, r1, r2, z0, z1, z2);
     acc[0] += z0 * q[i0] + z1 * q[i0 + nr] + z2 * q[i0 + 2 * nr];
     acc[1] += z0 * r0 + z1 * r1 + z2 * r2;
   }
 };
 
-// p = z + beta p ; q = 0
-template <typename T>
-struct BodyPUpdate {
-  const T* z;
-  T* p;
-  T* q;
+// p = z + beta p (z recomputed as above)
+template <int MODE, typename TU>
+struct BodyOuterP {
+  OuterZ<MODE, TU> zf;
+  const double* r;
+  double* p;
   const double* beta;
   int nr;
   __device__ void operator()(int64_t node, int col, double*) const {
-    const T b = T(beta[col]);
+    const int64_t i0 = NC_IDX(node, 0, col);
+    double z[3];
+    zf(node, i0, nr, MODE == 0 ? r[i0] : 0.0, MODE == 0 ? r[i0 + nr] : 0.0, MODE == 0 ? r[i0 + 2 * nr] : 0.0,
+       z[0], z[1], z[2]);
+    const double b = beta[col];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const int64_t i = NC_IDX(node, c, col);
+      const int64_t i = i0 + c * nr;
       // beta = 0 starts a new direction: do not read p (it may hold stale bits)
-      p[i] = (b == T(0)) ? z[i] : z[i] + b * p[i];
+      p[i] = (b == 0.0) ? z[c] : z[c] + b * p[i];
     }
   }
 };
 
-// sums: (p, q)
-template <typename T>
-struct BodyDot {
-  const T* a;
-  const T* b;
-  int nr;
-  template <typename Acc>
-  __device__ void operator()(int64_t node, int col, Acc* acc) const {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int64_t i = NC_IDX(node, c, col);
-      acc[0] += Acc(a[i]) * Acc(b[i]);
-    }
-  }
-};
+// CG step length alpha = rho / (p, K p).  The outer loop takes no step for a
+// non-positive curvature (flagged as a breakdown in its scalar step); an
+// inner column whose denominator vanished is frozen.
+__device__ __forceinline__ double outer_alpha(double rho, double gamma) {
+  const double a = gamma > 0.0 ? rho / gamma : 0.0;
+  return isfinite(a) ? a : 0.0;
+}
+__device__ __forceinline__ double inner_alpha(double rho, double gamma) {
+  const double a = gamma != 0.0 ? rho / gamma : 0.0;
+  return isfinite(a) ? a : 0.0;
+}
 
-// r -= alpha q ; u += alpha p ; sums: ||r||^2
+// r -= alpha q ; u += alpha p ; sums: ||r||^2   (alpha = rho / gamma per case;
+// gamma = (p, K p) was accumulated by the product that formed q)
 struct BodyOuterUpdate {
   double* r;
   double* u;
   const double* q;
   const double* p;
-  const double* alpha;
+  const SolverScalars* sc;
   int nr;
   __device__ void operator()(int64_t node, int col, double* acc) const {
-    const double a = alpha[col];
+    const double a = outer_alpha(sc->rho[col], sc->gamma[col]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t i = NC_IDX(node, c, col);
@@ -302,11 +323,11 @@ struct BodyInnerUpdate {
   const T* q;
   const T* p;
   const T* minv;
-  const double* alpha;
+  const InnerScalars* in;
   int nr;
   __device__ void operator()(int64_t node, int col, T* acc) const {
     const int64_t i0 = NC_IDX(node, 0, col);
-    const T a = T(alpha[col]);
+    const T a = T(inner_alpha(in->rho_a[col], in->gamma[col]));
     T ev[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -368,24 +389,8 @@ struct EpiOuterBeta {
   }
 };
 
-struct EpiOuterAlpha {
-  SolverScalars* sc;
-  __device__ void operator()(const double* tot, int nr) const {
-    for (int j = 0; j < nr; ++j) {
-      const double g = tot[j];
-      double a = 0.0;
-      if (g > 0.0) a = sc->rho[j] / g;
-      else if (g < 0.0 || (g == 0.0 && sc->rr[j] > 0.0 && sc->rho[j] != 0.0)) sc->err = EBE_ERR_BREAKDOWN;
-      if (!finite_d(g) || !finite_d(a)) {
-        sc->err = EBE_ERR_NONFINITE;
-        a = 0.0;
-      }
-      sc->alpha[j] = a;
-    }
-    if (sc->err) sc->outer_active = 0;
-  }
-};
-
+// scalar step after r -= alpha q, u += alpha p: record alpha (used by the next
+// beta), check the curvature (p, K p), clear its accumulator, test convergence
 struct EpiOuterConv {
   SolverScalars* sc;
   double tol;
@@ -393,6 +398,13 @@ struct EpiOuterConv {
   __device__ void operator()(const double* tot, int nr) const {
     double worst = 0.0;
     bool bad = false;
+    for (int j = 0; j < nr; ++j) {
+      const double g = sc->gamma[j];
+      if (g < 0.0 || (g == 0.0 && sc->rr[j] > 0.0 && sc->rho[j] != 0.0)) sc->err = EBE_ERR_BREAKDOWN;
+      if (!finite_d(g)) sc->err = EBE_ERR_NONFINITE;
+      sc->alpha[j] = outer_alpha(sc->rho[j], g);
+      sc->gamma[j] = 0.0;
+    }
     for (int j = 0; j < nr; ++j) {
       const double rr = tot[j];
       sc->rr[j] = rr;
@@ -423,26 +435,15 @@ struct EpiInnerStart {
       in->rho_a[j] = ze;
       in->beta[j] = 0.0;
       in->alpha[j] = 0.0;
+      in->gamma[j] = 0.0;
     }
     in->i = 1;
     in->active = (worst > eps && in->i < nmax) ? 1 : 0;
   }
 };
 
-template <typename T>
-struct EpiInnerAlpha {
-  InnerScalars* in;
-  __device__ void operator()(const double* tot, int nr) const {
-    for (int j = 0; j < nr; ++j) {
-      const double g = tot[j];
-      double a = (g != 0.0) ? in->rho_a[j] / g : 0.0;
-      if (!isfinite(a)) a = 0.0;  // a column whose step vanished is frozen
-      in->alpha[j] = a;
-      in->rho_b[j] = in->rho_a[j];
-    }
-  }
-};
-
+// scalar step after e -= alpha q, u += alpha p: beta = rho_a(new) / rho_a(old)
+// (a column with rho_a(old) = 0 restarts), clear the (p, K p) accumulator
 template <typename T>
 struct EpiInnerStep {
   InnerScalars* in;
@@ -454,10 +455,13 @@ struct EpiInnerStep {
       const double ee = tot[j], ze = tot[nr + j];
       const double ratio = in->nr2[j] > 0.0 ? ee / in->nr2[j] : 0.0;
       if (isfinite(ratio)) worst = fmax(worst, ratio);
-      in->rho_a[j] = ze;
-      double b = (in->rho_b[j] != 0.0) ? ze / in->rho_b[j] : 0.0;
+      const double rho_old = in->rho_a[j];
+      in->alpha[j] = inner_alpha(rho_old, in->gamma[j]);
+      in->gamma[j] = 0.0;
+      double b = (rho_old != 0.0) ? ze / rho_old : 0.0;
       if (!isfinite(b)) b = 0.0;
       in->beta[j] = b;
+      in->rho_a[j] = ze;
     }
     in->i += 1;
     in->steps += 1;
@@ -480,38 +484,40 @@ hipError_t sk_outer_init(const ebe_mesh* m, const double* f, const double* q, do
                                  m->n_nodes, nr, st, nullptr, s);
 }
 
-hipError_t sk_outer_z_bj(const ebe_mesh* m, const double* r, const double* q, double* z, int nr, SolverState& st,
+hipError_t sk_outer_z_bj(const ebe_mesh* m, const double* r, const double* q, int nr, SolverState& st,
                          hipStream_t s) {
-  BodyOuterZ<0, double> b{m->minv64[0].as<double>(), nullptr, r, q, z, nr};
+  BodyOuterZ<0, double> b{{m->minv64[0].as<double>(), nullptr}, r, q, nr};
   return run_nodecase<double, 2>(b, EpiOuterBeta{st.sc}, m->n_nodes, nr, st, &st.sc->outer_active, s);
 }
 
 template <typename T>
-hipError_t sk_outer_z_cast(const ebe_mesh* m, const T* ub, const double* r, const double* q, double* z, int nr,
+hipError_t sk_outer_z_cast(const ebe_mesh* m, const T* ub, const double* r, const double* q, int nr,
                            SolverState& st, hipStream_t s) {
-  BodyOuterZ<1, T> b{nullptr, ub, r, q, z, nr};
+  BodyOuterZ<1, T> b{{nullptr, ub}, r, q, nr};
   return run_nodecase<double, 2>(b, EpiOuterBeta{st.sc}, m->n_nodes, nr, st, &st.sc->outer_active, s);
 }
-template hipError_t sk_outer_z_cast<float>(const ebe_mesh*, const float*, const double*, const double*, double*,
-                                           int, SolverState&, hipStream_t);
-template hipError_t sk_outer_z_cast<double>(const ebe_mesh*, const double*, const double*, const double*, double*,
-                                            int, SolverState&, hipStream_t);
+template hipError_t sk_outer_z_cast<float>(const ebe_mesh*, const float*, const double*, const double*, int,
+                                           SolverState&, hipStream_t);
+template hipError_t sk_outer_z_cast<double>(const ebe_mesh*, const double*, const double*, const double*, int,
+                                            SolverState&, hipStream_t);
 
-hipError_t sk_outer_p(const ebe_mesh* m, const double* z, double* p, double* q, int nr, SolverState& st,
-                      hipStream_t s) {
-  return run_nodecase<double, 0>(BodyPUpdate<double>{z, p, q, st.sc->beta, nr}, NoEpi{}, m->n_nodes, nr, st,
-                                 &st.sc->outer_active, s);
+hipError_t sk_outer_p_bj(const ebe_mesh* m, const double* r, double* p, int nr, SolverState& st, hipStream_t s) {
+  BodyOuterP<0, double> b{{m->minv64[0].as<double>(), nullptr}, r, p, st.sc->beta, nr};
+  return run_nodecase<double, 0>(b, NoEpi{}, m->n_nodes, nr, st, &st.sc->outer_active, s);
 }
 
-hipError_t sk_outer_alpha(const ebe_mesh* m, const double* p, const double* q, int nr, SolverState& st,
-                          hipStream_t s) {
-  return run_nodecase<double, 1>(BodyDot<double>{p, q, nr}, EpiOuterAlpha{st.sc}, m->n_nodes, nr, st,
-                                 &st.sc->outer_active, s);
+template <typename T>
+hipError_t sk_outer_p_cast(const ebe_mesh* m, const T* ub, double* p, int nr, SolverState& st, hipStream_t s) {
+  BodyOuterP<1, T> b{{nullptr, ub}, nullptr, p, st.sc->beta, nr};
+  return run_nodecase<double, 0>(b, NoEpi{}, m->n_nodes, nr, st, &st.sc->outer_active, s);
 }
+template hipError_t sk_outer_p_cast<float>(const ebe_mesh*, const float*, double*, int, SolverState&, hipStream_t);
+template hipError_t sk_outer_p_cast<double>(const ebe_mesh*, const double*, double*, int, SolverState&,
+                                            hipStream_t);
 
 hipError_t sk_outer_update(const ebe_mesh* m, double* r, double* u, const double* q, const double* p, int nr,
                            double tol, int max_outer, SolverState& st, hipStream_t s) {
-  return run_nodecase<double, 1>(BodyOuterUpdate{r, u, q, p, st.sc->alpha, nr}, EpiOuterConv{st.sc, tol, max_outer},
+  return run_nodecase<double, 1>(BodyOuterUpdate{r, u, q, p, st.sc, nr}, EpiOuterConv{st.sc, tol, max_outer},
                                  m->n_nodes, nr, st, &st.sc->outer_active, s);
 }
 
@@ -549,18 +555,10 @@ hipError_t sk_inner_p(const ebe_mesh* m, int level, const T* e, T* p, T* q, int 
 }
 
 template <typename T>
-hipError_t sk_inner_alpha(const ebe_mesh* m, int level, const T* p, const T* q, int nr, SolverState& st,
-                          hipStream_t s) {
-  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
-  return run_nodecase<T, 1>(BodyDot<T>{p, q, nr}, EpiInnerAlpha<T>{&st.sc->inner[level]}, n, nr, st,
-                            &st.sc->inner[level].active, s);
-}
-
-template <typename T>
 hipError_t sk_inner_update(const ebe_mesh* m, int level, T* e, T* u, const T* q, const T* p, int nr, double eps,
                            int nmax, SolverState& st, hipStream_t s) {
   const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
-  return run_nodecase<T, 2>(BodyInnerUpdate<T>{e, u, q, p, minv_of<T>(m, level), st.sc->inner[level].alpha, nr},
+  return run_nodecase<T, 2>(BodyInnerUpdate<T>{e, u, q, p, minv_of<T>(m, level), &st.sc->inner[level], nr},
                             EpiInnerStep<T>{&st.sc->inner[level], eps, nmax}, n, nr, st,
                             &st.sc->inner[level].active, s);
 }
@@ -569,7 +567,6 @@ hipError_t sk_inner_update(const ebe_mesh* m, int level, T* e, T* u, const T* q,
   template hipError_t sk_inner_init<T>(const ebe_mesh*, int, const T*, const T*, T*, int, double, int,            \
                                        SolverState&, hipStream_t);                                               \
   template hipError_t sk_inner_p<T>(const ebe_mesh*, int, const T*, T*, T*, int, SolverState&, hipStream_t);      \
-  template hipError_t sk_inner_alpha<T>(const ebe_mesh*, int, const T*, const T*, int, SolverState&, hipStream_t); \
   template hipError_t sk_inner_update<T>(const ebe_mesh*, int, T*, T*, const T*, const T*, int, double, int,       \
                                          SolverState&, hipStream_t);
 EBE_INST(float)

@@ -11,8 +11,8 @@ namespace ebe {
 
 struct InnerScalars {          // Algorithm 1(b), one set per level
   double nr2[EBE_MAX_RHS];     // ||r_j||^2 of the inner right-hand side
-  double rho_a[EBE_MAX_RHS];
-  double rho_b[EBE_MAX_RHS];
+  double rho_a[EBE_MAX_RHS];    // (M^-1 e, e) of the current step
+  double gamma[EBE_MAX_RHS];    // (p, K p), accumulated by the product that forms q
   double alpha[EBE_MAX_RHS];
   double beta[EBE_MAX_RHS];
   int active;                  // 1 while max_j ||e_j||^2/||r_j||^2 > eps and i < N
@@ -27,6 +27,7 @@ struct SolverScalars {         // Algorithm 1(a)
   double rho[EBE_MAX_RHS];
   double alpha[EBE_MAX_RHS];
   double beta[EBE_MAX_RHS];
+  double gamma[EBE_MAX_RHS];     // (p, K p), accumulated by the product that forms q
   double max_rel;
   int outer_active;            // 1 while max_j rel_j > tol and iterations remain
   int outer_iter;
@@ -45,15 +46,16 @@ struct SolverState {
 hipError_t sk_mask_u(const ebe_mesh* m, double* u, int nr, SolverState& st, hipStream_t s);
 hipError_t sk_outer_init(const ebe_mesh* m, const double* f, const double* q, double* r, int nr, double tol,
                          SolverState& st, hipStream_t s);
-hipError_t sk_outer_z_bj(const ebe_mesh* m, const double* r, const double* q, double* z, int nr, SolverState& st,
+// z = M^-1 r (PCGE) or z = u_bar (MG2) is formed where it is used and never stored:
+// the z kernels sum (z, q) and (z, r) and set beta; the p kernels form p = z + beta p.
+hipError_t sk_outer_z_bj(const ebe_mesh* m, const double* r, const double* q, int nr, SolverState& st,
                          hipStream_t s);
 template <typename T>
-hipError_t sk_outer_z_cast(const ebe_mesh* m, const T* ub, const double* r, const double* q, double* z, int nr,
+hipError_t sk_outer_z_cast(const ebe_mesh* m, const T* ub, const double* r, const double* q, int nr,
                            SolverState& st, hipStream_t s);
-hipError_t sk_outer_p(const ebe_mesh* m, const double* z, double* p, double* q, int nr, SolverState& st,
-                      hipStream_t s);
-hipError_t sk_outer_alpha(const ebe_mesh* m, const double* p, const double* q, int nr, SolverState& st,
-                          hipStream_t s);
+hipError_t sk_outer_p_bj(const ebe_mesh* m, const double* r, double* p, int nr, SolverState& st, hipStream_t s);
+template <typename T>
+hipError_t sk_outer_p_cast(const ebe_mesh* m, const T* ub, double* p, int nr, SolverState& st, hipStream_t s);
 hipError_t sk_outer_update(const ebe_mesh* m, double* r, double* u, const double* q, const double* p, int nr,
                            double tol, int max_outer, SolverState& st, hipStream_t s);
 template <typename T>
@@ -64,9 +66,6 @@ hipError_t sk_inner_init(const ebe_mesh* m, int level, const T* r, const T* q, T
 template <typename T>
 hipError_t sk_inner_p(const ebe_mesh* m, int level, const T* e, T* p, T* q, int nr, SolverState& st,
                       hipStream_t s);
-template <typename T>
-hipError_t sk_inner_alpha(const ebe_mesh* m, int level, const T* p, const T* q, int nr, SolverState& st,
-                          hipStream_t s);
 template <typename T>
 hipError_t sk_inner_update(const ebe_mesh* m, int level, T* e, T* u, const T* q, const T* p, int nr, double eps,
                            int nmax, SolverState& st, hipStream_t s);
