@@ -138,6 +138,48 @@ def solver_block(torch, ebe, meshgen, modes=("mixed_mg2", "fp64_mg2", "fp64_pcge
     return out
 
 
+FORM_NAMES = {0: "gather", 1: "staged"}
+
+
+def batch_block(torch, ebe, meshgen, n_mesh, with_big):
+    """Batched uneven serving-size set: n_mesh crust meshes with log-uniform
+    element counts in [5e4, 2e6] and 1..16 cases each (optionally plus the
+    128x128x64 mesh with 16 cases), mixed MG2 to 1e-8, solved as one batch
+    and then one after another."""
+    grids, nrhs = meshgen.batch_sizes(meshgen.rng_for(5, 0), n_mesh=n_mesh)
+    if with_big:
+        grids.append((128, 128, 64))
+        nrhs.append(16)
+    gms, fs = [], []
+    for k, (gr, n) in enumerate(zip(grids, nrhs)):
+        m = meshgen.crust_mesh(*gr)
+        f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(5, 100 + k), nrhs=n)
+        gms.append(ebe.Mesh.from_generated(m))
+        fs.append(torch.from_numpy(f).cuda())
+        print(f"# batch mesh {k}: grid {gr}, {m.n_elem} tets, {n} cases", file=sys.stderr, flush=True)
+    opts = ebe.default_opts(tol=1e-8)
+    ebe.batch_solve(gms, fs, opts=opts)  # warm-up: block Jacobi set-up, workspaces
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st_b = ebe.batch_solve(gms, fs, opts=opts)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    st_s = [gm.solve(f, opts=opts)[1] for gm, f in zip(gms, fs)]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    cases = int(sum(nrhs))
+    out = {"workload": f"{n_mesh} crust meshes, log-uniform 5e4..2e6 tets, 1..16 cases each"
+                       + (" + 128x128x64 (16 cases)" if with_big else "") + ", mixed MG2 to 1e-8",
+           "n_mesh": len(grids), "elements_total": int(sum(g.n_elem for g in gms)), "cases_total": cases,
+           "batch_seconds": tb, "sequential_seconds": ts, "speedup": ts / tb,
+           "solves_per_s_batch": cases / tb, "solves_per_s_sequential": cases / ts,
+           "max_rel_res": max(s["max_rel_res"] for s in st_b),
+           "all_converged": all(s["status"] == ebe.OK for s in st_b + st_s)}
+    print(f"# batch: {tb:.3f} s batched vs {ts:.3f} s one by one, {cases} cases", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +192,9 @@ def main():
     ap.add_argument("--solver-modes", default="mixed_mg2,fp64_mg2,fp64_pcge")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=100000)
+    ap.add_argument("--batch", type=int, default=0, metavar="N_MESH",
+                    help="also time a batch of N_MESH uneven crust meshes against one-by-one solves")
+    ap.add_argument("--batch-big", action="store_true", help="add the 128x128x64 mesh to the batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -178,15 +223,19 @@ def main():
         dt, p = tdt[name]
         vec_bytes = 3 * N * n * p
         sets = max(3, int(np.ceil(1.1e9 / (2 * vec_bytes))))  # > 1 GB of x/y: no reuse through the 256 MB MALL
+        tg, tst = gm.autotune(0, dt, n)  # keeps the faster product form for (dtype, n) on this mesh
         xs = [torch.randn((N, 3, n), dtype=torch.float64, device="cuda").to(dt) for _ in range(sets)]
         ys = [torch.empty((N, 3, n), dtype=dt, device="cuda") for _ in range(sets)]
         t_op = time_launches(lambda i: gm.matvec(xs[i % sets], out=ys[i % sets]), args.steps, args.warmup, torch)
         B = product_bytes(N, Nv, E, n, p)
-        rec = {"dtype": name, "nrhs": n, "ms": t_op, "gdof_rhs_per_s": 3 * N * n / (t_op * 1e-3) / 1e9,
+        rec = {"dtype": name, "nrhs": n, "ms": t_op, "form": FORM_NAMES[gm.form(0, dt, n)],
+               "autotune_ms": {"gather": tg, "staged": tst},
+               "gdof_rhs_per_s": 3 * N * n / (t_op * 1e-3) / 1e9,
                "hbm_frac": B / (t_op * 1e-3) / 1e9 / HBM_PEAK_GBS,
                "alu_frac": E * n * FLOPS_PER_ELEM_RHS / (t_op * 1e-3) / 1e12 / ALU_PEAK_TFLOPS}
         variants.append(rec)
-        print(f"# {name} n={n}: {t_op:.3f} ms, {rec['gdof_rhs_per_s']:.1f} GDOF*RHS/s, "
+        print(f"# {name} n={n} ({rec['form']}; tuning: gather {tg:.3f} / staged {tst:.3f} ms): "
+              f"{t_op:.3f} ms, {rec['gdof_rhs_per_s']:.1f} GDOF*RHS/s, "
               f"HBM {rec['hbm_frac']:.2%}, ALU {rec['alu_frac']:.2%}", file=sys.stderr, flush=True)
         del xs, ys
         torch.cuda.empty_cache()
@@ -200,8 +249,12 @@ def main():
         del a, b
         torch.cuda.empty_cache()
 
-    # timed region of the headline step: FP32, 16 cases, y = K x
+    # timed region of the headline step: FP32, 16 cases, y = K x, in the form
+    # the autotuner picked on this mesh
     n, dt, p = 16, torch.float32, 4
+    if gm.form(0, dt, n) == -1 or "f32:16" not in args.variants.split(","):
+        gm.autotune(0, dt, n)
+    form = FORM_NAMES[gm.form(0, dt, n)]
     sets = 3
     xs = [torch.randn((N, 3, n), dtype=torch.float64, device="cuda").to(dt) for _ in range(sets)]
     ys = [torch.empty((N, 3, n), dtype=dt, device="cuda") for _ in range(sets)]
@@ -230,9 +283,10 @@ def main():
     alu = {"bound": "alu", "achieved": F / t / 1e12, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
            "frac": F / t / 1e12 / ALU_PEAK_TFLOPS}
     roof, alt = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
-    traffic = load_traffic("f32:16")
+    traffic = load_traffic(f"f32:16:{form}")
     roof["traffic"] = traffic
-    roof["kernel"] = "EBE product FP32 n=16: k_ebe_patch<float,16,2,false> + k_reduce_shared<float,16>"
+    roof["kernel"] = (f"EBE product FP32 n=16, {form} form: k_ebe_patch<float,16,2,{str(form == 'staged').lower()}>"
+                      " + k_reduce_shared<float,16>")
     roof["ms_per_launch"] = ms_events
     roof["algorithmic_bytes"] = B
     roof["algorithmic_flops"] = F
@@ -248,6 +302,8 @@ def main():
             "roofline": roof, "roofline_alt": alt, "variants": variants}
     if not args.no_solver:
         line["solver"] = solver_block(torch, ebe, meshgen, args.solver_modes.split(","))
+    if args.batch > 0:
+        line["batch"] = batch_block(torch, ebe, meshgen, args.batch, args.batch_big)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(mesh, 16, args.cpu_elems)
     print(json.dumps(line))

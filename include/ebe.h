@@ -20,8 +20,9 @@
  *   (Section 3.1: the case index is the innermost, contiguous loop), so a
  *   vector of n cases on N nodes holds 3*N*n values.  Quadratic-level vectors
  *   have N = n_nodes; linear-level (corner-only) vectors have N = n_vertices.
- * - Buffers must not overlap unless stated.  Device buffers must be aligned
- *   to their element size.
+ * - Buffers must not overlap unless stated.  Device buffers must be 16-byte
+ *   aligned (every hipMalloc / torch allocation is); a misaligned one is
+ *   rejected with EBE_ERR_ARG.
  * - `stream` is a hipStream_t (NULL = the default stream).  Calls marked
  *   "asynchronous" only enqueue work on it; the others synchronise it.
  * - A mesh handle must be used by one stream at a time.
@@ -67,6 +68,12 @@ typedef int32_t ebe_dtype;
 #define EBE_MODE_FP64 0
 #define EBE_MODE_MIXED 1 /* preconditioner (inner loops, EBE products) in FP32 */
 
+/* Forms of the EBE product kernel (same result, different speed): GATHER
+ * reads each element's nodal values straight from x; STAGED copies a patch's
+ * node rows into LDS first, a few cases at a time.  AUTO: the mesh's tuned
+ * choice, else a fixed default. */
+typedef enum { EBE_FORM_AUTO = -1, EBE_FORM_GATHER = 0, EBE_FORM_STAGED = 1 } ebe_form;
+
 typedef struct ebe_mesh ebe_mesh;   /* opaque; owns device copies of the mesh and workspace */
 typedef struct ebe_batch ebe_batch; /* opaque; a set of meshes solved together */
 
@@ -83,6 +90,11 @@ typedef struct {
   int32_t inner_max[2]; /* inner loops run while i < N, i from 1: at most N-1 steps */
   int32_t use_x0;       /* 1: u_dev holds the initial guess on entry; 0: start from zero */
   int32_t coarse_guess; /* 0: u1 = P1^T u as printed; 1: u1 = corner values of u */
+  int32_t graphs;       /* 1 (default): replay captured HIP graphs of the fixed runs of
+                           inner steps (and of PCGE outer steps) enqueued between two
+                           convergence checks; needs a stream other than NULL (the legacy
+                           default stream cannot be captured), else ignored */
+  int32_t reserved;     /* 0 */
 } ebe_pcg_opts;
 
 typedef struct {
@@ -185,11 +197,37 @@ ebe_status ebe_pcg_solve(ebe_mesh* mesh, int32_t nrhs, const double* f_dev, doub
 ebe_status ebe_adjoint_grad(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* u_dev,
                             const void* lam_dev, void* g_dev, void* stream);
 
+/* ---- product forms and the autotuner ------------------------------------ */
+
+/* Time both product forms of y = K x (level 0: quadratic mesh, level 1:
+ * linear mesh) for (dtype, nrhs) on this mesh and keep the faster one for
+ * every later product with these parameters; ms_out[2] (or NULL) receives
+ * the gather and staged times in milliseconds.  Synchronous; allocates
+ * temporary vectors.  ebe_pcg_solve tunes the products it uses by itself. */
+ebe_status ebe_autotune(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, void* stream,
+                        double* ms_out);
+
+/* Force (EBE_FORM_GATHER / _STAGED) or reset (EBE_FORM_AUTO) the form used
+ * for (level, dtype, nrhs), and read the form that would be used. */
+ebe_status ebe_set_product_form(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, int32_t form);
+ebe_status ebe_get_product_form(const ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs,
+                                int32_t* form);
+
 /* ---- batches: many meshes / case sets solved together ------------------ */
 
-/* A batch runs the solves of several meshes, each with its own nrhs, on one
- * stream, interleaving their iterations so that small meshes share the GPU
- * (Section 5 solves case sets one after another; here they overlap). */
+/* A batch runs the solves of several meshes, each with its own nrhs (1..16),
+ * several at a time so that meshes too small to fill the GPU share it
+ * (Section 5 solves its case sets one after another; here they overlap).
+ * ebe_batch_create: meshes[n_mesh] distinct handles on one device, nrhs[n_mesh];
+ *   the batch keeps the pointers (the meshes must outlive it) and creates its
+ *   own worker streams (default priority).
+ * ebe_batch_solve: f_dev[i], u_dev[i] are mesh i's [N_i][3][nrhs_i] FP64
+ *   vectors; opts as ebe_pcg_solve (NULL: defaults) for every mesh;
+ *   stats[n_mesh] or NULL.  Work starts after what is already enqueued on
+ *   `stream`; the call returns when every solve has finished (synchronous).
+ *   Returns the first error met (the message names the mesh), else
+ *   EBE_NOT_CONVERGED if any mesh did not converge, else EBE_OK.  A batch is
+ *   used by one thread at a time. */
 ebe_status ebe_batch_create(ebe_mesh* const* meshes, int32_t n_mesh, const int32_t* nrhs,
                             ebe_batch** out);
 ebe_status ebe_batch_solve(ebe_batch* batch, const double* const* f_dev, double* const* u_dev,

@@ -31,7 +31,7 @@ COMMON = [
 ]
 
 SOURCES = [
-    "mesh.cpp", "patches.cpp", "api.cpp", "solver.cpp", "batch.cpp",
+    "mesh.cpp", "patches.cpp", "api.cpp", "solver.cpp", "batch.cpp", "autotune.cpp",
     "ebe_kernels.hip", "setup_kernels.hip", "ebe_vec.hip", "ebe_adjoint.hip", "solver_kernels.hip",
 ]
 
@@ -64,7 +64,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

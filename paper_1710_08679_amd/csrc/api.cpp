@@ -27,6 +27,10 @@ ebe_status check_common(const char* fn, const ebe_mesh* m, ebe_dtype dt, int32_t
     set_error("%s: input and output must not alias", fn);
     return EBE_ERR_ARG;
   }
+  if (!aligned16(x) || !aligned16(y)) {
+    set_error("%s: device buffers must be 16-byte aligned", fn);
+    return EBE_ERR_ARG;
+  }
   return EBE_OK;
 }
 
@@ -141,8 +145,8 @@ ebe_status ebe_adjoint_grad(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void*
                             void* stream) {
   ebe_status st = check_common("ebe_adjoint_grad", m, dt, nrhs, u, g);
   if (st != EBE_OK) return st;
-  if (!lam || lam == g) {
-    set_error("ebe_adjoint_grad: lam is NULL or aliases g");
+  if (!lam || lam == g || !aligned16(lam)) {
+    set_error("ebe_adjoint_grad: lam is NULL, aliases g or is not 16-byte aligned");
     return EBE_ERR_ARG;
   }
   return hip_status("ebe_adjoint_grad", launch_adjoint(m, dt, nrhs, u, lam, g, static_cast<hipStream_t>(stream)));

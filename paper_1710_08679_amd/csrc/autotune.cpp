@@ -1,0 +1,110 @@
+// Per-mesh choice of the EBE product form.  Which form of the patch kernel
+// is faster depends on the dtype, the number of cases and the mesh (patch
+// node counts, how many nodes are shared), so it is measured: both forms run
+// the same product a few times on the mesh itself and the faster is kept for
+// that (level, dtype, nrhs).  Search over implementation parameters, as the
+// paper does for its own kernels (Section 4), only automated.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+
+#include "ebe_internal.h"
+
+using namespace ebe;
+
+namespace {
+
+constexpr int kRuns = 3;
+
+bool valid_args(const ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, const char* fn) {
+  if (!m || (level != 0 && level != 1) || (dt != EBE_F64 && dt != EBE_F32) || nrhs < 1 || nrhs > EBE_MAX_RHS) {
+    set_error("%s: null mesh, level not 0/1, bad dtype or nrhs outside 1..%d", fn, EBE_MAX_RHS);
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+namespace ebe {
+
+ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const void* x, void* y, hipStream_t s,
+                        double ms[2]) {
+  const int order = level == 0 ? 2 : 1;
+  ebe_status st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4);
+  if (st != EBE_OK) return st;
+  hipEvent_t a = nullptr, b = nullptr;
+  EBE_TRY_HIP(hipEventCreate(&a));
+  hipError_t e = hipEventCreate(&b);
+  double best[2] = {DBL_MAX, DBL_MAX};
+  for (int form = 0; form < 2 && e == hipSuccess; ++form) {
+    e = launch_ebe_form(m, order, form, dt, nrhs, x, y, false, m->has_bc, false, nullptr, s);  // warm-up
+    for (int r = 0; r < kRuns && e == hipSuccess; ++r) {
+      e = hipEventRecord(a, s);
+      if (e == hipSuccess) e = launch_ebe_form(m, order, form, dt, nrhs, x, y, false, m->has_bc, false, nullptr, s);
+      if (e == hipSuccess) e = hipEventRecord(b, s);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+      if (e == hipSuccess) best[form] = std::min(best[form], double(t));
+    }
+  }
+  (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (e != hipSuccess) {
+    set_error("autotune: %s", hipGetErrorString(e));
+    return EBE_ERR_HIP;
+  }
+  m->form[level][dt == EBE_F64 ? 0 : 1][nrhs] = int8_t(best[1] < best[0] ? EBE_FORM_STAGED : EBE_FORM_GATHER);
+  if (ms) {
+    ms[0] = best[0];
+    ms[1] = best[1];
+  }
+  return EBE_OK;
+}
+
+}  // namespace ebe
+
+extern "C" {
+
+ebe_status ebe_autotune(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, void* stream, double* ms_out) {
+  if (!valid_args(m, level, dt, nrhs, "ebe_autotune")) return EBE_ERR_ARG;
+  const int64_t rows = level == 0 ? m->n_nodes : m->n_vertices;
+  const size_t bytes = size_t(rows) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4);
+  DBuf x, y;
+  ebe_status st = x.alloc(bytes);
+  if (st == EBE_OK) st = y.alloc(bytes);
+  if (st != EBE_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  EBE_TRY_HIP(launch_fill_zero(x.as<void>(), bytes, s));
+  double ms[2];
+  st = tune_product(m, level, dt, nrhs, x.as<void>(), y.as<void>(), s, ms);
+  if (st == EBE_OK && ms_out) {
+    ms_out[0] = ms[0];
+    ms_out[1] = ms[1];
+  }
+  EBE_TRY_HIP(hipStreamSynchronize(s));  // the temporaries are freed on return
+  return st;
+}
+
+ebe_status ebe_set_product_form(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, int32_t form) {
+  if (!valid_args(m, level, dt, nrhs, "ebe_set_product_form")) return EBE_ERR_ARG;
+  if (form != EBE_FORM_AUTO && form != EBE_FORM_GATHER && form != EBE_FORM_STAGED) {
+    set_error("ebe_set_product_form: form %d is not EBE_FORM_AUTO, _GATHER or _STAGED", form);
+    return EBE_ERR_ARG;
+  }
+  m->form[level][dt == EBE_F64 ? 0 : 1][nrhs] = int8_t(form);
+  return EBE_OK;
+}
+
+ebe_status ebe_get_product_form(const ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, int32_t* form) {
+  if (!valid_args(m, level, dt, nrhs, "ebe_get_product_form") || !form) {
+    if (m && !form) set_error("ebe_get_product_form: form is NULL");
+    return EBE_ERR_ARG;
+  }
+  *form = product_form(m, level == 0 ? 2 : 1, dt, nrhs);
+  return EBE_OK;
+}
+
+}  // extern "C"

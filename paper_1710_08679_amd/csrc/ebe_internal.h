@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,9 @@ constexpr int32_t kIdxBits = 28;
 constexpr int32_t kIdxMask = (1 << kIdxBits) - 1;
 
 void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
+// Kernels move node rows of vectors in 16-byte pieces.
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 #define EBE_TRY_HIP(call)                                                        \
   do {                                                                           \
@@ -61,6 +65,13 @@ struct Workspace {
   DBuf flags;     // int32 device flags
   DBuf counter;   // int32/uint32 arrival counters for last-block reductions
   int* host_flags = nullptr;  // pinned host mirror
+  // Instantiated graphs of fixed runs of solver steps, keyed by everything
+  // baked into their kernel arguments (buffer addresses, nrhs, step count).
+  struct Graph {
+    std::vector<uintptr_t> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<Graph> graphs;
 };
 
 // Element patches (patches.cpp): at most kPatchElems elements touching at
@@ -119,6 +130,10 @@ struct ebe_mesh {
   ebe::DBuf lconn1;     // uint8 [E][4]  patch-local ids of the 4 corners
   ebe::PatchLevel pl[2];
   ebe::DBuf gacc;       // kGammaBytes: (x, K x) slots, then the arrival counter; zero between products
+  // EBE product form per [level][dtype F64, F32][nrhs]: EBE_FORM_GATHER,
+  // EBE_FORM_STAGED, or EBE_FORM_AUTO (untuned: a fixed default)
+  int8_t form[2][2][EBE_MAX_RHS + 1];
+  ebe_mesh() { std::memset(form, EBE_FORM_AUTO, sizeof(form)); }
   // 3x3 block Jacobi: inverted symmetric blocks (xx yy zz yz zx xy), per level
   ebe::DBuf minv64[2], minv32[2];
   bool minv_ready = false;
@@ -141,6 +156,15 @@ hipError_t launch_ebe_p1(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* 
 // ensure_stage.
 hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in,
                       bool bc, bool add, const int* gate, hipStream_t s, double* gamma = nullptr);
+// the same with the product form given (EBE_FORM_GATHER or EBE_FORM_STAGED)
+hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt, int nrhs, const void* x, void* y,
+                           bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma = nullptr);
+// the form launch_ebe uses for (order, dtype, nrhs)
+int product_form(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs);
+// time both forms of y = K x on this mesh (x, y: device vectors of the
+// level's size; y is overwritten) and record the faster; synchronous.
+ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const void* x, void* y, hipStream_t s,
+                        double ms[2]);
 hipError_t launch_diag_blocks(const ebe_mesh* m, int level, double* blk6, hipStream_t s);
 hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6, double* inv64,
                                 float* inv32, hipStream_t s);

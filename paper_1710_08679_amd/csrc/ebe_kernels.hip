@@ -3,18 +3,22 @@
 //
 // Work decomposition (see patches.cpp).  One workgroup per element patch
 // (<= 64 elements, <= 192 nodes):
-//   1. the patch's node words (id, Dirichlet bits, shared flag) and staging
-//      slots go to LDS, together with a cleared FP64 force accumulator
-//      F[node][component][case];
-//   2. one work-item per element rebuilds the element geometry from the four
+//   1. one work-item per element rebuilds the element geometry from the four
 //      corner coordinates and material (the element matrix is never stored,
 //      Section 2) and keeps it in LDS;
-//   3. one work-item per (element, case) gathers its nodal values (the n
-//      cases of a node are contiguous: Section 3.1's coalesced case loop),
-//      forms K_e u_e in registers (p2_element.h) and adds the forces into F
-//      with LDS FP64 atomics (FP32 LDS atomics are much slower on this part);
-//   4. each patch node is written once: exclusive nodes straight into y,
-//      shared nodes as a partial sum into their staging slot.
+//   2. one work-item per (element, case) streams the element's nodal values
+//      through K_e (p2_element.h) and adds each nodal force into an FP64 LDS
+//      accumulator F[node][component][case] (FP32 LDS atomics are much slower
+//      on this part).  The nodal values come in one of two forms:
+//        gather: straight from x (the n cases of a node are contiguous:
+//          Section 3.1's case loop), all cases in one pass;
+//        staged: the cases are taken in passes of at most 8 (FP32: two
+//          workgroups per CU) or 8 (FP64, 1024 work-items); a pass first
+//          copies the patch's node rows into LDS with coalesced vector loads;
+//      which form is faster depends on the dtype, n and the mesh, and is
+//      measured per mesh (autotune.cpp);
+//   3. each patch node is written once per pass: exclusive nodes straight
+//      into y, shared nodes as a partial sum into their staging slot.
 // A second, node-centric kernel adds the consecutive staged partials of each
 // shared node in patch order.  Global memory sees no atomics, every node is
 // written exactly once per product (so y needs no clearing pass), and the
@@ -27,12 +31,65 @@
 namespace ebe {
 namespace {
 
+template <typename T, int VW>
+struct alignas(sizeof(T) * VW) VecT {
+  T v[VW];
+};
+
+// widest vector (at most 16 bytes) whose width divides both n and the pass
+// width, so every vector of a node row lies inside one pass and is aligned
+constexpr int pass_vec(int nr, int cw, int value_bytes) {
+  int v = 16 / value_bytes;
+  while (v > 1 && (nr % v != 0 || cw % v != 0)) v /= 2;
+  return v;
+}
+
 template <typename T> struct Pair;
 template <> struct Pair<double> { using type = double2; };
 template <> struct Pair<float> { using type = float2; };
 
-constexpr int threads_for(int nr) {
-  return (kPatchElems * nr + 63) / 64 * 64 > kPatchThreads ? kPatchThreads : (kPatchElems * nr + 63) / 64 * 64;
+// Cases per pass of the staged form on the quadratic mesh: at most
+// EBE_P2_PASS_F32 / _F64, in passes of equal width, so that a 192-node
+// patch's staged rows and FP64 accumulator fit the occupancy the form is
+// built for.  The gather form and the linear mesh (<= 64 corners) take all n
+// cases in one pass.
+#ifndef EBE_P2_PASS_F32
+#define EBE_P2_PASS_F32 8
+#endif
+#ifndef EBE_P2_PASS_F64
+#define EBE_P2_PASS_F64 8
+#endif
+constexpr int chunk_for(int nr, int order, int value_bytes, bool stage) {
+  const int widest = value_bytes == 8 ? EBE_P2_PASS_F64 : EBE_P2_PASS_F32;
+  const int passes = (nr + widest - 1) / widest;
+  return (order == 1 || !stage) ? nr : (nr + passes - 1) / passes;
+}
+
+// one work-item per (element, case) of a pass, at most kPatchThreads
+constexpr int threads_for(int nr, int order, int value_bytes, bool stage) {
+  const int want = (kPatchElems * chunk_for(nr, order, value_bytes, stage) + 63) / 64 * 64;
+  return want > kPatchThreads ? kPatchThreads : want;
+}
+
+// LDS of one patch workgroup and the wavefronts per SIMD that LDS leaves
+// room for (160 KiB per CU, 4 SIMDs); the kernel asks the compiler for no
+// more registers than that occupancy allows, but never for fewer than the
+// element arithmetic needs without spilling: 128 (FP32, and the linear
+// element) or 256 (quadratic FP64).
+template <typename T>
+constexpr int patch_lds_bytes(int nr, int order, bool stage) {
+  const int maxn = order == 2 ? kPatchNodes : kPatchCorners;
+  const int wc = 3 * chunk_for(nr, order, int(sizeof(T)), stage);
+  return maxn * wc * 8 + (stage ? maxn * wc * int(sizeof(T)) : 0) + kPatchElems * 14 * int(sizeof(T)) +
+         8 * maxn + 8 * nr + 16;
+}
+template <typename T>
+constexpr int patch_waves_per_simd(int nr, int order, bool stage) {
+  const int lds = (patch_lds_bytes<T>(nr, order, stage) + 511) / 512 * 512;  // allocation granule
+  const int wg = 163840 / lds;
+  const int w = (wg > 0 ? wg : 1) * (threads_for(nr, order, int(sizeof(T)), stage) / 64) / 4;
+  const int most = (sizeof(T) == 8 && order == 2) ? 2 : 4;
+  return w > most ? most : (w < 1 ? 1 : w);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
@@ -68,24 +125,37 @@ __device__ __forceinline__ int spread_element(int j, int ne) {
   }
 }
 
-// MASK_IN: zero the fixed DOFs of x while gathering (y = P K P x); callers
-// whose x is already zero there (the solver) skip it.  bc: zero the fixed
-// DOFs of y.  add: y += K x instead of y = K x.  gamma (optional): gamma[r]
-// += (x_r, K x_r) formed element by element as sum_e x_eᵀ K_e x_e, which is
-// what CG needs from q = K p without a separate inner-product pass.
-template <typename T, int NR, int ORDER, bool MASK_IN>
-__global__ __launch_bounds__(threads_for(NR)) void k_ebe_patch(
+// STAGE: the staged form (else the gather form).  mask_in: zero the fixed
+// DOFs of x while reading it (y = P K P x); callers whose x is already zero
+// there (the solver) skip it.  bc: zero the fixed DOFs of y.  add: y += K x
+// instead of y = K x.  gamma (optional): gamma[r] += (x_r, K x_r) formed
+// element by element as sum_e x_eᵀ K_e x_e, which is what CG needs from
+// q = K p without a separate inner-product pass.
+template <typename T, int NR, int ORDER, bool STAGE>
+__global__ __launch_bounds__(threads_for(NR, ORDER, int(sizeof(T)), STAGE))
+__attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) void k_ebe_patch(
     const int32_t* __restrict__ conn, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
     const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
     const double4* __restrict__ xv, const typename Pair<T>::type* __restrict__ lame, const T* __restrict__ x,
-    T* __restrict__ y, T* __restrict__ stage, int bc, int add, double* __restrict__ gamma,
+    T* __restrict__ y, T* __restrict__ stage, int mask_in, int bc, int add, double* __restrict__ gamma,
     double* __restrict__ gslot, unsigned* __restrict__ gcount, const int* __restrict__ gate) {
   constexpr int NLOC = ORDER == 2 ? 10 : 4;
-  constexpr int W = 3 * NR;
-  constexpr int TPB = threads_for(NR);
+  constexpr int CW = chunk_for(NR, ORDER, int(sizeof(T)), STAGE);  // cases per pass
+  constexpr int NPASS = (NR + CW - 1) / CW;
+  constexpr int W = 3 * NR;   // values of a node in x, y and the staging buffer
+  constexpr int WC = 3 * CW;  // values of a node in one pass
+  constexpr int TPB = threads_for(NR, ORDER, int(sizeof(T)), STAGE);
   constexpr int MAXN = ORDER == 2 ? kPatchNodes : kPatchCorners;
-  constexpr int EPP = TPB / W;  // patch nodes written per pass
-  __shared__ double F[MAXN * W];
+  constexpr int VEC = pass_vec(NR, CW, int(sizeof(T)));  // values per vector access of a node row
+  constexpr int NV = WC / VEC;                            // vectors of a node in one pass
+  // Node-row staging: work-item t moves vector t % NV of nodes t / NV,
+  // t / NV + EPK, ... (EPK = TPB / NV nodes per sweep), so its place in the
+  // row, and with it the case and component, never changes.
+  constexpr int EPK = TPB / NV;                           // nodes per sweep
+  constexpr int KIT = (MAXN + EPK - 1) / EPK;             // sweeps per pass, at most
+  using V = VecT<T, VEC>;
+  __shared__ double F[MAXN * WC];
+  __shared__ __align__(16) T X[STAGE ? MAXN * WC : 1];
   __shared__ T geo[kPatchElems][14];
   __shared__ int32_t words[MAXN];
   __shared__ int32_t slots[MAXN];
@@ -95,12 +165,11 @@ __global__ __launch_bounds__(threads_for(NR)) void k_ebe_patch(
   const int p = xcd_patch(blockIdx.x, gridDim.x);
   const int e0 = pelem[p], ne = pelem[p + 1] - e0;
   const int o0 = poff[p], nn = poff[p + 1] - o0;
-  for (int i = tid; i < nn * W; i += TPB) F[i] = 0.0;
-  if (tid < NR) gsum[tid] = 0.0;
   for (int i = tid; i < nn; i += TPB) {
     words[i] = pnode[o0 + i];
     slots[i] = pslot[o0 + i];
   }
+  if (tid < NR) gsum[tid] = 0.0;
   for (int el = tid; el < ne; el += TPB) {
     const int64_t e = int64_t(e0) + el;
     T G[4][3];
@@ -115,96 +184,138 @@ __global__ __launch_bounds__(threads_for(NR)) void k_ebe_patch(
     geo[el][12] = T(lm.x) * s;
     geo[el][13] = T(lm.y) * s;
   }
+  // (x, K x) contributions: when the pass width divides 64 a work-item keeps
+  // one case for all its items, so it sums them in a register and the lanes
+  // of a case are combined across the wavefront before one LDS atomic.
+  constexpr bool kLaneCase = (64 % CW) == 0 && (TPB % CW) == 0;
+  const int nj = spread_count<CW>(ne);
+  const int sv = tid % NV;                 // this work-item's vector in a node row
+  const int sent = tid < EPK * NV ? tid / NV : MAXN;  // its first node (none if past the sweep)
+  const int sq = sv * VEC;                 // value offset in the pass row
+  const int sc = sq / CW, scc = sq - sc * CW;  // component and first case of the vector
   __syncthreads();
-  // (x, K x) contributions: when n divides 64 a work-item keeps one case for
-  // all its items, so it sums them in a register and the lanes of a case are
-  // combined across the wavefront before one LDS atomic per case.
-  constexpr bool kLaneCase = (64 % NR) == 0;
-  double en_acc = 0.0;
-  const int nj = spread_count<NR>(ne);
-  for (int w = tid; w < nj * NR; w += TPB) {
-    const int j = w / NR;
-    const int r = w - j * NR;
-    const int el = spread_element<NR>(j, ne);
-    if (el >= ne) continue;
-    const int64_t e = int64_t(e0) + el;
-    int lid[NLOC];
-    if constexpr (ORDER == 2) {
-      const uint4 q = *reinterpret_cast<const uint4*>(lconn + e * 16);
-      const uint32_t qw[3] = {q.x, q.y, q.z};
+#pragma unroll 1
+  for (int pass = 0; pass < NPASS; ++pass) {
+    const int c0 = pass * CW;
+    const int cw = NR - c0 < CW ? NR - c0 : CW;
+    // Clear the accumulator and (staged form) copy this pass's node rows,
+    // zero for fixed DOFs under mask_in and for the unused lanes of a short
+    // last pass.  A fixed trip count lets every work-item issue all its loads
+    // at once.
 #pragma unroll
-      for (int a = 0; a < NLOC; ++a) lid[a] = (qw[a >> 2] >> (8 * (a & 3))) & 0xff;
-    } else {
-      const uint32_t q = *reinterpret_cast<const uint32_t*>(lconn + e * 4);
+    for (int k = 0; k < KIT; ++k) {
+      const int ent = sent + k * EPK;
+      if (ent < nn) {
+        const int q = sq, c = sc, cc = scc;
+        if constexpr (STAGE) {
+          const int32_t wd = words[ent];
+          V v;
+          if (cc < cw && !(mask_in && ((wd >> (kIdxBits + c)) & 1))) {
+            v = *reinterpret_cast<const V*>(x + size_t(uint32_t(wd) & uint32_t(kIdxMask)) * W + c * NR + c0 + cc);
+          } else {
 #pragma unroll
-      for (int a = 0; a < NLOC; ++a) lid[a] = (q >> (8 * a)) & 0xff;
-    }
-    T G[4][3];
+            for (int t = 0; t < VEC; ++t) v.v[t] = T(0);
+          }
+          *reinterpret_cast<V*>(X + ent * WC + q) = v;
+        }
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) G[k][d] = geo[el][3 * k + d];
-    const T cl = geo[el][12], cm = geo[el][13];
-    T u[NLOC][3];
-#pragma unroll
-    for (int a = 0; a < NLOC; ++a) {
-      const int32_t wd = words[lid[a]];
-      const T* xp = x + size_t(uint32_t(wd) & uint32_t(kIdxMask)) * W + r;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T v = xp[c * NR];
-        if constexpr (MASK_IN) v = ((wd >> (kIdxBits + c)) & 1) ? T(0) : v;
-        u[a][c] = v;
+        for (int t = 0; t < VEC; ++t) F[ent * WC + q + t] = 0.0;
       }
     }
-    T f[NLOC][3];
-    if constexpr (ORDER == 2)
-      p2_forces<T>(G, cl, cm, reinterpret_cast<const T(*)[3]>(u), reinterpret_cast<T(*)[3]>(f));
-    else
-      p1_forces<T>(G, cl, cm, reinterpret_cast<const T(*)[3]>(u), reinterpret_cast<T(*)[3]>(f));
+    __syncthreads();
+    double en_acc = 0.0;
+    for (int w = tid; w < nj * CW; w += TPB) {
+      const int j = w / CW;
+      const int r = w - j * CW;
+      const int el = spread_element<CW>(j, ne);
+      if (el >= ne || r >= cw) continue;
+      const int64_t e = int64_t(e0) + el;
+      int lid[NLOC];  // F (and X) index of the node's first component in this work-item's case
+      int gw[NLOC];   // gather form: the node's word (id and Dirichlet bits)
+      if constexpr (ORDER == 2) {
+        const uint4 q = *reinterpret_cast<const uint4*>(lconn + e * 16);
+        const uint32_t qw[3] = {q.x, q.y, q.z};
 #pragma unroll
-    for (int a = 0; a < NLOC; ++a) {
-      double* fp = F + lid[a] * W + r;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) atomicAdd(fp + c * NR, double(f[a][c]));
-    }
-    if (gamma) {
-      T en = T(0);
-#pragma unroll
-      for (int a = 0; a < NLOC; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) en += u[a][c] * f[a][c];
-      if constexpr (kLaneCase) en_acc += double(en);
-      else atomicAdd(&gsum[r], double(en));
-    }
-  }
-  if constexpr (kLaneCase) {
-    if (gamma) {
-#pragma unroll
-      for (int off = 32; off >= NR; off >>= 1) en_acc += __shfl_xor(en_acc, off, 64);
-      if ((tid & 63) < NR) atomicAdd(&gsum[tid & 63], en_acc);
-    }
-  }
-  __syncthreads();
-  const int eo = tid / W;
-  const int rem = tid - eo * W;
-  const int c = rem / NR;
-  if (eo < EPP) {
-    for (int ent = eo; ent < nn; ent += EPP) {
-      const int32_t wd = words[ent];
-      const T v = T(F[ent * W + rem]);
-      if (wd < 0) {  // shared node: partial sum to its staging slot
-        stage[size_t(slots[ent]) * W + rem] = v;
+        for (int a = 0; a < NLOC; ++a) lid[a] = (qw[a >> 2] >> (8 * (a & 3))) & 0xff;
       } else {
-        T* yp = y + size_t(wd & kIdxMask) * W + rem;
-        const bool fixed = bc && ((wd >> (kIdxBits + c)) & 1);
-        if (add) {
-          if (!fixed) *yp += v;
+        const uint32_t q = *reinterpret_cast<const uint32_t*>(lconn + e * 4);
+#pragma unroll
+        for (int a = 0; a < NLOC; ++a) lid[a] = (q >> (8 * a)) & 0xff;
+      }
+#pragma unroll
+      for (int a = 0; a < NLOC; ++a) {
+        if constexpr (!STAGE) gw[a] = words[lid[a]];
+        lid[a] = lid[a] * WC + r;
+      }
+      T G[4][3];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) G[k][d] = geo[el][3 * k + d];
+      const T cl = geo[el][12], cm = geo[el][13];
+      T en = T(0);
+      auto u = [&](int a, int c) -> T {
+        if constexpr (STAGE) {
+          return X[lid[a] + c * CW];
         } else {
-          *yp = fixed ? T(0) : v;
+          const T v = x[size_t(uint32_t(gw[a]) & uint32_t(kIdxMask)) * W + c * NR + r];
+          return (mask_in && ((gw[a] >> (kIdxBits + c)) & 1)) ? T(0) : v;
+        }
+      };
+      auto emit = [&](int a, const T f[3]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(F + lid[a] + c * CW, double(f[c]));
+      };
+      if constexpr (ORDER == 2) p2_apply<T>(G, cl, cm, u, emit, gamma != nullptr, en);
+      else p1_apply<T>(G, cl, cm, u, emit, gamma != nullptr, en);
+      if (gamma) {
+        if constexpr (kLaneCase) en_acc += double(en);
+        else atomicAdd(&gsum[c0 + r], double(en));
+      }
+    }
+    if constexpr (kLaneCase) {
+      if (gamma) {
+#pragma unroll
+        for (int off = 32; off >= CW; off >>= 1) en_acc += __shfl_xor(en_acc, off, 64);
+        if ((tid & 63) < cw) atomicAdd(&gsum[c0 + (tid & 63)], en_acc);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KIT; ++k) {
+      const int ent = sent + k * EPK;
+      if (ent < nn) {
+        const int q = sq, c = sc, cc = scc;
+        if (cc < cw) {
+          const int32_t wd = words[ent];
+          const int col = c * NR + c0 + cc;
+          V v;
+#pragma unroll
+          for (int t = 0; t < VEC; ++t) v.v[t] = T(F[ent * WC + q + t]);
+          if (wd < 0) {  // shared node: partial sum to its staging slot
+            *reinterpret_cast<V*>(stage + size_t(slots[ent]) * W + col) = v;
+          } else {
+            V* yp = reinterpret_cast<V*>(y + size_t(wd & kIdxMask) * W + col);
+            const bool fixed = bc && ((wd >> (kIdxBits + c)) & 1);
+            if (add) {
+              if (!fixed) {
+                V o = *yp;
+#pragma unroll
+                for (int t = 0; t < VEC; ++t) o.v[t] += v.v[t];
+                *yp = o;
+              }
+            } else {
+              if (fixed) {
+#pragma unroll
+                for (int t = 0; t < VEC; ++t) v.v[t] = T(0);
+              }
+              *yp = v;
+            }
+          }
         }
       }
     }
+    if (pass + 1 < NPASS) __syncthreads();  // X and F are refilled by the next pass
   }
   if (!gamma) return;
   // Spread the device-scope additions over kGammaSlots lines (thousands of
@@ -238,10 +349,6 @@ __global__ __launch_bounds__(threads_for(NR)) void k_ebe_patch(
 
 // y[shared node] (=|+=) sum of its consecutive staged partials (patch order).
 // The host guarantees nshared * 3 * NR < 2^31 and nslots * 3 * NR < 2^31.
-template <typename T, int VW>
-struct alignas(sizeof(T) * VW) VecT {
-  T v[VW];
-};
 
 // values per 16-byte vector that divide a node row of 3 n values
 template <typename T, int NR>
@@ -297,31 +404,32 @@ __global__ __launch_bounds__(256) void k_reduce_shared(const int32_t* __restrict
   *yp = out;
 }
 
-template <typename T, int NR, int ORDER, bool MASK_IN>
-void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool bc, bool add,
-                  const int* gate, hipStream_t s, double* gamma) {
+template <typename T, int NR, int ORDER, bool STAGE>
+void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool mask_in, bool bc,
+                  bool add, const int* gate, hipStream_t s, double* gamma) {
   using P = typename Pair<T>::type;
   const P* lame = (sizeof(T) == 8) ? reinterpret_cast<const P*>(m->lame64.as<void>())
                                    : reinterpret_cast<const P*>(m->lame32.as<void>());
-  hipLaunchKernelGGL((k_ebe_patch<T, NR, ORDER, MASK_IN>), dim3(unsigned(m->n_patch)), dim3(threads_for(NR)), 0,
-                     s, m->conn.as<int32_t>(), ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(),
-                     m->pelem.as<int32_t>(), L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(),
-                     m->xv.as<double4>(), lame, static_cast<const T*>(x), static_cast<T*>(y), stage, int(bc),
-                     int(add), gamma, m->gacc.as<double>(),
-                     reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64), gate);
+  hipLaunchKernelGGL((k_ebe_patch<T, NR, ORDER, STAGE>), dim3(unsigned(m->n_patch)),
+                     dim3(threads_for(NR, ORDER, int(sizeof(T)), STAGE)), 0, s, m->conn.as<int32_t>(),
+                     ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(), m->pelem.as<int32_t>(),
+                     L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(), m->xv.as<double4>(), lame,
+                     static_cast<const T*>(x), static_cast<T*>(y), stage, int(mask_in), int(bc), int(add), gamma,
+                     m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64),
+                     gate);
 }
 
 template <typename T, int NR>
-hipError_t ebe_dispatch_p(int order, const ebe_mesh* m, const void* x, void* y, bool mask_in, bool bc, bool add,
-                          const int* gate, hipStream_t s, double* gamma) {
+hipError_t ebe_dispatch_p(int order, int form, const ebe_mesh* m, const void* x, void* y, bool mask_in, bool bc,
+                          bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   T* stage = L.stage.as<T>();
   if (order == 2) {
-    if (mask_in) launch_patch<T, NR, 2, true>(m, L, x, y, stage, bc, add, gate, s, gamma);
-    else launch_patch<T, NR, 2, false>(m, L, x, y, stage, bc, add, gate, s, gamma);
+    if (form == EBE_FORM_STAGED) launch_patch<T, NR, 2, true>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
+    else launch_patch<T, NR, 2, false>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
   } else {
-    if (mask_in) launch_patch<T, NR, 1, true>(m, L, x, y, stage, bc, add, gate, s, gamma);
-    else launch_patch<T, NR, 1, false>(m, L, x, y, stage, bc, add, gate, s, gamma);
+    if (form == EBE_FORM_STAGED) launch_patch<T, NR, 1, true>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
+    else launch_patch<T, NR, 1, false>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || L.nshared == 0) return e;
@@ -333,11 +441,11 @@ hipError_t ebe_dispatch_p(int order, const ebe_mesh* m, const void* x, void* y, 
 }
 
 template <typename T>
-hipError_t ebe_dispatch(int order, const ebe_mesh* m, int nrhs, const void* x, void* y, bool mask_in, bool bc,
-                        bool add, const int* gate, hipStream_t s, double* gamma) {
+hipError_t ebe_dispatch(int order, int form, const ebe_mesh* m, int nrhs, const void* x, void* y, bool mask_in,
+                        bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
   switch (nrhs) {
 #define EBE_CASE(n) \
-  case n: return ebe_dispatch_p<T, n>(order, m, x, y, mask_in, bc, add, gate, s, gamma);
+  case n: return ebe_dispatch_p<T, n>(order, form, m, x, y, mask_in, bc, add, gate, s, gamma);
     EBE_CASE(1) EBE_CASE(2) EBE_CASE(3) EBE_CASE(4) EBE_CASE(5) EBE_CASE(6) EBE_CASE(7) EBE_CASE(8)
     EBE_CASE(9) EBE_CASE(10) EBE_CASE(11) EBE_CASE(12) EBE_CASE(13) EBE_CASE(14) EBE_CASE(15) EBE_CASE(16)
 #undef EBE_CASE
@@ -362,13 +470,29 @@ ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes) {
   return EBE_OK;
 }
 
-hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in,
-                      bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
+int product_form(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs) {
+  const int f = m->form[order == 2 ? 0 : 1][dt == EBE_F64 ? 0 : 1][nrhs];
+  if (f == EBE_FORM_GATHER || f == EBE_FORM_STAGED) return f;
+  // untuned: the form measured faster on the reference workloads
+  return dt == EBE_F64 && order == 2 ? EBE_FORM_STAGED : EBE_FORM_GATHER;
+}
+
+hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt, int nrhs, const void* x, void* y,
+                           bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   const size_t need = size_t(L.nslots) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4);
-  if (L.stage.bytes() < need || m->n_patch < 1) return hipErrorInvalidValue;  // staging not sized: host bug
-  return dt == EBE_F64 ? ebe_dispatch<double>(order, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma)
-                       : ebe_dispatch<float>(order, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma);
+  if (L.stage.bytes() < need || m->n_patch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS ||
+      (form != EBE_FORM_GATHER && form != EBE_FORM_STAGED))
+    return hipErrorInvalidValue;  // staging not sized or bad form: host bug
+  return dt == EBE_F64 ? ebe_dispatch<double>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma)
+                       : ebe_dispatch<float>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma);
+}
+
+hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in,
+                      bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
+  if (nrhs < 1 || nrhs > EBE_MAX_RHS) return hipErrorInvalidValue;
+  return launch_ebe_form(m, order, product_form(m, order, dt, nrhs), dt, nrhs, x, y, mask_in, bc, add, gate, s,
+                         gamma);
 }
 
 hipError_t launch_ebe_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,

@@ -323,6 +323,7 @@ ebe_status ebe_mesh_info(const ebe_mesh* m, int64_t* n_nodes, int64_t* n_vertice
 void ebe_mesh_destroy(ebe_mesh* m) {
   if (!m) return;
   if (m->ws.host_flags) (void)hipHostFree(m->ws.host_flags);
+  for (auto& g : m->ws.graphs) (void)hipGraphExecDestroy(g.exec);
   delete m;
 }
 

@@ -141,45 +141,75 @@ EBE_HD void sym_mv_acc(const T P[6], const T g[3], T out[3]) {
 // and E_km = u_{km} (x) G_m (using G_k = -sum_{m != k} G_m), which needs 16
 // outer products and no differences; every accumulation is a fused
 // multiply-add.  About 440 floating-point instructions per element and case.
-template <typename T>
-EBE_HD void p2_forces(const T G[4][3], T cl, T cm, const T u[10][3], T f[10][3]) {
-  T Vv[4][6];
+//
+// Streaming form: u(a, c) returns component c of local node a and is called
+// once per node and component while the strains are accumulated (an edge
+// node's value feeds both of its corners' strains at once); emit(a, f) takes
+// the force of node a as soon as it is known.  Only the 30 strain sums (then
+// the 30 stresses) and the gradients stay live, never all 30 nodal values.
+//
+// with_energy: energy = u_eᵀ K_e u_e = int sigma : eps dV, formed from
+// the strains e_k = 4 w_k - A and scaled stresses as
+//     sum_k S'_k : e_k + S' : sum_k e_k
+// (int L_k L_l dV = V (1 + delta_kl) / 20; engineering shears pair with the
+// shear stresses), so the nodal values need not be kept for it.
+template <typename T, class U, class Emit>
+EBE_HD void p2_apply(const T G[4][3], T cl, T cm, U&& u, Emit&& emit, bool with_energy, T& energy) {
+  T w[4][6];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) set_eng(Vv[i], u[i], G[i]);
+  for (int i = 0; i < 4; ++i) {
+    const T ui[3] = {u(i, 0), u(i, 1), u(i, 2)};
+    set_eng(w[i], ui, G[i]);
+  }
   T A[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) A[c] = (Vv[0][c] + Vv[1][c]) + (Vv[2][c] + Vv[3][c]);
-  T S[4][6];
-  T Ssum[6];
+  for (int c = 0; c < 6; ++c) A[c] = (w[0][c] + w[1][c]) + (w[2][c] + w[3][c]);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int k = edge_end(q, 0), m = edge_end(q, 1);
+    const T ue[3] = {u(4 + q, 0), u(4 + q, 1), u(4 + q, 2)};
+    fma_eng(w[k], ue, G[m]);
+    fma_eng(w[m], ue, G[k]);
+  }
+  // S'_k from the strain 4 w_k - A (w is overwritten by S'_k)
+  T Ssum[6], esum[6];
+  T en = T(0);
   const T cm2 = cm + cm;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    T w[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) w[c] = Vv[k][c];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-      if (m != k) fma_eng(w, u[edge_node(k, m)], G[m]);
     T e[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) e[c] = T(4) * w[c] - A[c];
+    for (int c = 0; c < 6; ++c) e[c] = T(4) * w[k][c] - A[c];
     const T clt = cl * ((e[0] + e[1]) + e[2]);
-    S[k][0] = cm2 * e[0] + clt;
-    S[k][1] = cm2 * e[1] + clt;
-    S[k][2] = cm2 * e[2] + clt;
-    S[k][3] = cm * e[3];
-    S[k][4] = cm * e[4];
-    S[k][5] = cm * e[5];
+    w[k][0] = cm2 * e[0] + clt;
+    w[k][1] = cm2 * e[1] + clt;
+    w[k][2] = cm2 * e[2] + clt;
+    w[k][3] = cm * e[3];
+    w[k][4] = cm * e[4];
+    w[k][5] = cm * e[5];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) Ssum[c] = (k == 0) ? S[k][c] : Ssum[c] + S[k][c];
+    for (int c = 0; c < 6; ++c) Ssum[c] = (k == 0) ? w[k][c] : Ssum[c] + w[k][c];
+    if (with_energy) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        en += w[k][c] * e[c];
+        esum[c] = (k == 0) ? e[c] : esum[c] + e[c];
+      }
+    }
+  }
+  if (with_energy) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) en += Ssum[c] * esum[c];
+    energy = en;
   }
   // corners: f_i = (4 S'_i - S') G_i
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    T P[6];
+    T P[6], f[3];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) P[c] = T(4) * S[i][c] - Ssum[c];
-    sym_mv(P, G[i], f[i]);
+    for (int c = 0; c < 6; ++c) P[c] = T(4) * w[i][c] - Ssum[c];
+    sym_mv(P, G[i], f);
+    emit(i, f);
   }
   // edges: f_km = T'_m G_k + T'_k G_m with T'_k = 4 (S'_k + S')
   T S4[6];
@@ -188,28 +218,68 @@ EBE_HD void p2_forces(const T G[4][3], T cl, T cm, const T u[10][3], T f[10][3])
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) S[k][c] = T(4) * S[k][c] + S4[c];
+    for (int c = 0; c < 6; ++c) w[k][c] = T(4) * w[k][c] + S4[c];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const int k = edge_end(q, 0), m = edge_end(q, 1);
-    sym_mv(S[m], G[k], f[4 + q]);
-    sym_mv_acc(S[k], G[m], f[4 + q]);
+    T f[3];
+    sym_mv(w[m], G[k], f);
+    sym_mv_acc(w[k], G[m], f);
+    emit(4 + q, f);
   }
 }
 
-// f = K1_e u for a 4-node tetrahedron (constant strain); cl = lambda V, cm = mu V.
 template <typename T>
-EBE_HD void p1_forces(const T G[4][3], T cl, T cm, const T u[4][3], T f[4][3]) {
+EBE_HD void p2_forces(const T G[4][3], T cl, T cm, const T u[10][3], T f[10][3]) {
+  T unused = T(0);
+  p2_apply<T>(
+      G, cl, cm, [&](int a, int c) { return u[a][c]; },
+      [&](int a, const T fa[3]) {
+        f[a][0] = fa[0];
+        f[a][1] = fa[1];
+        f[a][2] = fa[2];
+      },
+      false, unused);
+}
+
+// f = K1_e u for a 4-node tetrahedron (constant strain); cl = lambda V, cm = mu V.
+// with_energy: energy = u_eᵀ K1_e u_e = S : e (V already in cl, cm).
+template <typename T, class U, class Emit>
+EBE_HD void p1_apply(const T G[4][3], T cl, T cm, U&& u, Emit&& emit, bool with_energy, T& energy) {
+  const T u0[3] = {u(0, 0), u(0, 1), u(0, 2)};
   T e6[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int i = 1; i < 4; ++i) {
-    const T d[3] = {u[i][0] - u[0][0], u[i][1] - u[0][1], u[i][2] - u[0][2]};
+    const T d[3] = {u(i, 0) - u0[0], u(i, 1) - u0[1], u(i, 2) - u0[2]};
     acc_eng(e6, d, G[i]);
   }
   T S[6];
   stress(e6, cl, cm, S);
+  if (with_energy) {
+    T en = T(0);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) sym_mv(S, G[i], f[i]);
+    for (int c = 0; c < 6; ++c) en += S[c] * e6[c];
+    energy = en;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    T f[3];
+    sym_mv(S, G[i], f);
+    emit(i, f);
+  }
+}
+
+template <typename T>
+EBE_HD void p1_forces(const T G[4][3], T cl, T cm, const T u[4][3], T f[4][3]) {
+  T unused = T(0);
+  p1_apply<T>(
+      G, cl, cm, [&](int a, int c) { return u[a][c]; },
+      [&](int a, const T fa[3]) {
+        f[a][0] = fa[0];
+        f[a][1] = fa[1];
+        f[a][2] = fa[2];
+      },
+      false, unused);
 }
 
 }  // namespace ebe

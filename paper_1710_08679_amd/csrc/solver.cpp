@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <vector>
 
 #include "ebe_internal.h"
 #include "solver_state.h"
@@ -80,10 +81,59 @@ constexpr ebe_dtype dtype_of() {
   return sizeof(T) == 8 ? EBE_F64 : EBE_F32;
 }
 
+constexpr size_t kMaxGraphs = 24;
+
+// Enqueue a fixed run of solver steps on s: directly, or (graphs on, s not
+// the legacy default stream) by replaying a graph captured from the same run
+// the first time it is met.  key holds everything the run's kernels take as
+// arguments, so a replay is exactly the run it stands for.
+template <class Steps>
+ebe_status enqueue_steps(ebe_mesh* m, std::vector<uintptr_t>&& key, bool graphs, hipStream_t s, Steps&& steps) {
+  if (!graphs || s == nullptr) return steps();
+  auto& G = m->ws.graphs;
+  for (auto& g : G)
+    if (g.key == key) {
+      EBE_TRY_HIP(hipGraphLaunch(g.exec, s));
+      return EBE_OK;
+    }
+  if (G.size() >= kMaxGraphs) {
+    for (auto& g : G) (void)hipGraphExecDestroy(g.exec);
+    G.clear();
+  }
+  EBE_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const ebe_status st = steps();
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  if (st != EBE_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != EBE_OK) return st;
+    set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    return EBE_ERR_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    return EBE_ERR_HIP;
+  }
+  G.push_back(Workspace::Graph{std::move(key), exec});
+  EBE_TRY_HIP(hipGraphLaunch(exec, s));
+  return EBE_OK;
+}
+
+uintptr_t bits_of(double v) {
+  uintptr_t b = 0;
+  std::memcpy(&b, &v, sizeof(v) < sizeof(b) ? sizeof(v) : sizeof(b));
+  return b;
+}
+
+uintptr_t addr(const void* p) { return reinterpret_cast<uintptr_t>(p); }
+
 // Algorithm 1(b) on one level: approximately solve A u = r starting from u.
 template <typename T>
 ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int nr, double eps, int nmax,
-                       SolverState& st, hipStream_t s) {
+                       bool graphs, SolverState& st, hipStream_t s) {
   const int order = level == 0 ? 2 : 1;
   InnerScalars* din = &st.sc->inner[level];
   // all solver vectors are kept zero on fixed DOFs, so inputs need no masking
@@ -93,14 +143,24 @@ ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int
   int chunk = level == 0 ? 3 : 4;
   while (enq < nmax - 1) {
     const int k = std::min(chunk, nmax - 1 - enq);
-    for (int c = 0; c < k; ++c) {
-      EBE_K(sk_inner_p<T>(m, level, e, p, q, nr, st, s));
-      EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, p, q, false, true, false, &din->active, s, din->gamma));
-      EBE_K(sk_inner_update<T>(m, level, e, u, q, p, nr, eps, nmax, st, s));
-    }
+    const PatchLevel& L = m->pl[level];
+    ebe_status rs = enqueue_steps(
+        m,
+        {1, uintptr_t(level), uintptr_t(k), uintptr_t(nr), sizeof(T), addr(e), addr(p), addr(q), addr(u),
+         addr(st.sc), addr(st.partials), addr(st.counter), addr(L.stage.as<void>()), addr(m->gacc.as<void>()),
+         addr(m->minv64[level].as<void>()), addr(m->minv32[level].as<void>()), bits_of(eps), uintptr_t(nmax)},
+        graphs, s, [&]() -> ebe_status {
+          for (int c = 0; c < k; ++c) {
+            EBE_K(sk_inner_p<T>(m, level, e, p, q, nr, st, s));
+            EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, p, q, false, true, false, &din->active, s, din->gamma));
+            EBE_K(sk_inner_update<T>(m, level, e, u, q, p, nr, eps, nmax, st, s));
+          }
+          return EBE_OK;
+        });
+    if (rs != EBE_OK) return rs;
     enq += k;
     SolverScalars* h = nullptr;
-    ebe_status rs = read_scalars(m, s, &h);
+    rs = read_scalars(m, s, &h);
     if (rs != EBE_OK) return rs;
     if (!h->inner[level].active) break;
     chunk = std::min(chunk * 2, 32);
@@ -126,11 +186,11 @@ ebe_status mg2_precondition(ebe_mesh* m, int nr, const ebe_pcg_opts& o, const Bu
     EBE_K(launch_restrict(m, dt, nr, ub, u1, true, s));        // u1 <= P1^T u_bar
   }
   ebe_status rs = inner_solve<T>(m, 1, r1, u1, static_cast<T*>(b.e1), static_cast<T*>(b.p1),
-                                 static_cast<T*>(b.q1), nr, o.inner_eps[1], o.inner_max[1], st, s);
+                                 static_cast<T*>(b.q1), nr, o.inner_eps[1], o.inner_max[1], o.graphs != 0, st, s);
   if (rs != EBE_OK) return rs;
   EBE_K(launch_prolong(m, dt, nr, u1, ub, true, s));           // u_bar <= P1 u1
   rs = inner_solve<T>(m, 0, rb, ub, static_cast<T*>(b.e0), static_cast<T*>(b.p0), static_cast<T*>(b.q0), nr,
-                      o.inner_eps[0], o.inner_max[0], st, s);
+                      o.inner_eps[0], o.inner_max[0], o.graphs != 0, st, s);
   if (rs != EBE_OK) return rs;
   EBE_K(sk_outer_z_cast<T>(m, ub, b.r, b.q, nr, st, s));  // z = u_bar: (z,q), (z,r), beta
   EBE_K(sk_outer_p_cast<T>(m, ub, b.p, nr, st, s));       // p <= z + beta p
@@ -141,7 +201,7 @@ ebe_status check_opts(const ebe_pcg_opts& o) {
   if ((o.precond != EBE_PREC_PCGE && o.precond != EBE_PREC_MG2) ||
       (o.mode != EBE_MODE_FP64 && o.mode != EBE_MODE_MIXED) || !(o.tol > 0.0) || o.max_outer < 1 ||
       o.check_every < 1 || o.inner_max[0] < 1 || o.inner_max[1] < 1 || !(o.inner_eps[0] >= 0.0) ||
-      !(o.inner_eps[1] >= 0.0) || (o.coarse_guess != 0 && o.coarse_guess != 1)) {
+      !(o.inner_eps[1] >= 0.0) || (o.coarse_guess != 0 && o.coarse_guess != 1) || (o.graphs != 0 && o.graphs != 1)) {
     set_error("ebe_pcg_solve: invalid options");
     return EBE_ERR_ARG;
   }
@@ -166,6 +226,7 @@ void ebe_pcg_default_opts(ebe_pcg_opts* o) {
   o->inner_max[1] = 300;
   o->use_x0 = 0;
   o->coarse_guess = 0;
+  o->graphs = 1;
 }
 
 ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, const ebe_pcg_opts* opts,
@@ -174,6 +235,10 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (!m || !f || !u || f == u) {
     set_error("ebe_pcg_solve: null or aliasing argument");
+    return EBE_ERR_ARG;
+  }
+  if (!aligned16(f) || !aligned16(u)) {
+    set_error("ebe_pcg_solve: device buffers must be 16-byte aligned");
     return EBE_ERR_ARG;
   }
   if (nr < 1 || nr > EBE_MAX_RHS) {
@@ -200,6 +265,25 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
          w.u1.as<void>(), w.e1.as<void>(), w.p1.as<void>(), w.q1.as<void>()};
   const size_t vbytes = size_t(m->n_nodes) * 3 * nr * sizeof(double);
 
+  // Pick the product forms this solve uses, once per mesh and case count,
+  // before anything is captured into a graph (tuning waits on the stream).
+  const bool mg = o.precond == EBE_PREC_MG2;
+  const ebe_dtype inner_dt = o.mode == EBE_MODE_MIXED ? EBE_F32 : EBE_F64;
+  const size_t v1bytes = size_t(m->n_vertices) * 3 * nr * sizeof(double);
+  struct Tune {
+    int level;
+    ebe_dtype dt;
+    void *x, *y;
+    size_t bytes;
+  } tunes[3] = {{0, EBE_F64, b.p, b.q, vbytes}, {0, inner_dt, b.p0, b.q0, vbytes}, {1, inner_dt, b.p1, b.q1, v1bytes}};
+  for (int t = 0; t < (mg ? 3 : 1); ++t) {
+    const Tune& k = tunes[t];
+    if (m->form[k.level][k.dt == EBE_F64 ? 0 : 1][nr] != EBE_FORM_AUTO) continue;
+    EBE_K(launch_fill_zero(k.x, k.bytes, s));
+    double ms[2];
+    if ((st_ = tune_product(m, k.level, k.dt, nr, k.x, k.y, s, ms)) != EBE_OK) return st_;
+  }
+
   EBE_K(launch_fill_zero(st.sc, sizeof(SolverScalars), s));
   EBE_K(launch_fill_zero(st.counter, 64, s));
   EBE_K(launch_fill_zero(b.p, vbytes, s));
@@ -212,23 +296,39 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   SolverScalars* h = nullptr;
   ebe_status rs = read_scalars(m, s, &h);
   if (rs != EBE_OK) return rs;
-  const bool mg = o.precond == EBE_PREC_MG2;
   const int per_check = mg ? 1 : o.check_every;
   int enq = 0;
   while (h->outer_active && !h->err && enq < o.max_outer) {
     const int k = std::min(per_check, o.max_outer - enq);
-    for (int c = 0; c < k; ++c) {
-      if (mg) {
+    // q <= K p, gamma <= (p, K p); alpha; r, u updates
+    auto product_and_update = [&]() -> ebe_status {
+      EBE_K(launch_ebe(m, 2, EBE_F64, nr, b.p, b.q, false, true, false, &st.sc->outer_active, s, st.sc->gamma));
+      EBE_K(sk_outer_update(m, b.r, u, b.q, b.p, nr, o.tol, o.max_outer, st, s));
+      return EBE_OK;
+    };
+    if (mg) {
+      for (int c = 0; c < k; ++c) {
         rs = (o.mode == EBE_MODE_MIXED) ? mg2_precondition<float>(m, nr, o, b, st, s)
                                         : mg2_precondition<double>(m, nr, o, b, st, s);
         if (rs != EBE_OK) return rs;
-      } else {
-        EBE_K(sk_outer_z_bj(m, b.r, b.q, nr, st, s));   // z = M^-1 r: (z,q), (z,r), beta
-        EBE_K(sk_outer_p_bj(m, b.r, b.p, nr, st, s));   // p <= z + beta p
+        if ((rs = product_and_update()) != EBE_OK) return rs;
       }
-      // q <= K p, gamma <= (p, K p)
-      EBE_K(launch_ebe(m, 2, EBE_F64, nr, b.p, b.q, false, true, false, &st.sc->outer_active, s, st.sc->gamma));
-      EBE_K(sk_outer_update(m, b.r, u, b.q, b.p, nr, o.tol, o.max_outer, st, s));  // alpha; r, u updates
+    } else {
+      rs = enqueue_steps(m,
+                         {2, uintptr_t(k), uintptr_t(nr), addr(b.r), addr(b.p), addr(b.q), addr(u), addr(st.sc),
+                          addr(st.partials), addr(st.counter), addr(m->pl[0].stage.as<void>()),
+                          addr(m->gacc.as<void>()), addr(m->minv64[0].as<void>()), bits_of(o.tol),
+                          uintptr_t(o.max_outer)},
+                         o.graphs != 0, s, [&]() -> ebe_status {
+                           for (int c = 0; c < k; ++c) {
+                             EBE_K(sk_outer_z_bj(m, b.r, b.q, nr, st, s));  // z = M^-1 r: (z,q), (z,r), beta
+                             EBE_K(sk_outer_p_bj(m, b.r, b.p, nr, st, s));  // p <= z + beta p
+                             ebe_status r2 = product_and_update();
+                             if (r2 != EBE_OK) return r2;
+                           }
+                           return EBE_OK;
+                         });
+      if (rs != EBE_OK) return rs;
     }
     enq += k;
     if ((rs = read_scalars(m, s, &h)) != EBE_OK) return rs;

@@ -22,13 +22,15 @@ F64, F32 = 0, 1
 PREC_PCGE, PREC_MG2 = 0, 1
 MODE_FP64, MODE_MIXED = 0, 1
 MAX_RHS = 16
+FORM_AUTO, FORM_GATHER, FORM_STAGED = -1, 0, 1
 
 EXPORTED = (
     "ebe_mesh_create", "ebe_mesh_set_material", "ebe_mesh_info", "ebe_mesh_destroy", "ebe_matvec",
     "ebe_matvec_add",
     "ebe_matvec_p1", "ebe_prolong_p1", "ebe_restrict_p1", "ebe_diag_blocks", "ebe_block_jacobi",
     "ebe_pcg_default_opts", "ebe_pcg_solve", "ebe_adjoint_grad", "ebe_batch_create", "ebe_batch_solve",
-    "ebe_batch_destroy", "ebe_status_string", "ebe_last_error", "ebe_build_info",
+    "ebe_batch_destroy", "ebe_status_string", "ebe_last_error", "ebe_build_info", "ebe_autotune",
+    "ebe_set_product_form", "ebe_get_product_form",
 )
 
 
@@ -36,7 +38,8 @@ class PcgOpts(ctypes.Structure):
     _fields_ = [("precond", ctypes.c_int32), ("mode", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("inner_eps", ctypes.c_double * 2), ("inner_max", ctypes.c_int32 * 2),
-                ("use_x0", ctypes.c_int32), ("coarse_guess", ctypes.c_int32)]
+                ("use_x0", ctypes.c_int32), ("coarse_guess", ctypes.c_int32), ("graphs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class PcgStats(ctypes.Structure):
@@ -92,6 +95,9 @@ def load():
         "ebe_status_string": ([_i32], ctypes.c_char_p),
         "ebe_last_error": ([], ctypes.c_char_p),
         "ebe_build_info": ([], ctypes.c_char_p),
+        "ebe_autotune": ([_vp, _i32, _i32, _i32, _vp, ctypes.POINTER(ctypes.c_double)], _i32),
+        "ebe_set_product_form": ([_vp, _i32, _i32, _i32, _i32], _i32),
+        "ebe_get_product_form": ([_vp, _i32, _i32, _i32, ctypes.POINTER(_i32)], _i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -112,6 +118,18 @@ def _stream(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return _vp(s.cuda_stream)
+
+
+def _dtype_code(dtype) -> int:
+    """F64 / F32 from an ebe code or a torch dtype."""
+    import torch
+    if dtype in (F64, F32):
+        return int(dtype)
+    if dtype == torch.float64:
+        return F64
+    if dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {dtype!r}")
 
 
 def _dev(t, dtype=None, shape=None, name="tensor"):
@@ -139,7 +157,10 @@ def _dtype_code(dtype) -> int:
 def default_opts(**kw) -> PcgOpts:
     o = PcgOpts()
     load().ebe_pcg_default_opts(ctypes.byref(o))
+    names = {f[0] for f in PcgOpts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown solver option {k!r}")
         if k in ("inner_eps", "inner_max"):
             getattr(o, k)[0], getattr(o, k)[1] = v
         else:
@@ -210,6 +231,21 @@ class Mesh:
         _check(fn(self.handle, _dtype_code(x.dtype), nrhs, _dev(x, name="x"),
                   _dev(out, x.dtype, (rows_out, 3, nrhs), "out"), int(bool(apply_bc)), _stream(stream)))
         return out
+
+    def autotune(self, level, dtype, nrhs, stream=None):
+        """Time both product forms for (level, dtype, nrhs) and keep the faster;
+        returns (gather ms, staged ms)."""
+        ms = (ctypes.c_double * 2)()
+        _check(load().ebe_autotune(self.handle, int(level), _dtype_code(dtype), int(nrhs), _stream(stream), ms))
+        return float(ms[0]), float(ms[1])
+
+    def set_form(self, level, dtype, nrhs, form):
+        _check(load().ebe_set_product_form(self.handle, int(level), _dtype_code(dtype), int(nrhs), int(form)))
+
+    def form(self, level, dtype, nrhs):
+        f = _i32()
+        _check(load().ebe_get_product_form(self.handle, int(level), _dtype_code(dtype), int(nrhs), ctypes.byref(f)))
+        return int(f.value)
 
     def matvec(self, x, apply_bc=False, out=None, stream=None):
         """y = K x (quadratic elements); x (N, 3, nrhs) float64/float32."""

@@ -6,6 +6,7 @@ import ctypes
 import json
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -52,9 +53,35 @@ def test_default_options_follow_table2(lib):
     assert o.tol == g["outer_tolerance"]["value"]
 
 
-def test_struct_layouts_match_header():
-    assert ctypes.sizeof(ebe.PcgOpts) == 56
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structures match the C header, field by field:
+    a C program built from include/ebe.h prints sizes and offsets."""
+    assert ctypes.sizeof(ebe.PcgOpts) == 64
     assert ctypes.sizeof(ebe.PcgStats) == 40
+    fields = {"ebe_pcg_opts": ebe.PcgOpts, "ebe_pcg_stats": ebe.PcgStats}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "ebe.h"', "int main(void) {"]
+    for cname, py in fields.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for ln in out:
+        if not ln:
+            continue
+        cname, what, val = ln.split()
+        py = fields[cname]
+        if what == "size":
+            assert ctypes.sizeof(py) == int(val), (cname, "size")
+        else:
+            assert getattr(py, what).offset == int(val), (cname, what)
+        seen += 1
+    assert seen == sum(len(p._fields_) + 1 for p in fields.values())
 
 
 def create(m, **over):

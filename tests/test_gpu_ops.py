@@ -4,6 +4,8 @@ Small meshes span several workgroups with a ragged tail for every case
 count; the full-size matvec workload (64^3 hexes x 6) is checked on sampled
 nodes and by invariants.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -28,37 +30,78 @@ def small(gpu_lib):
     return m, ebe.Mesh.from_generated(m), oracle_K(m), oracle_K(m, order=1), kappa_max(m)
 
 
+FORMS = [ebe.FORM_GATHER, ebe.FORM_STAGED]
+
+
+class forced_form:
+    """Run the products of one (level, dtype, nrhs) in a given form."""
+
+    def __init__(self, gm, level, dtype, nrhs, form):
+        self.args = (gm, level, DT[dtype], nrhs, form)
+
+    def __enter__(self):
+        gm, level, dt, nrhs, form = self.args
+        gm.set_form(level, dt, nrhs, form)
+        assert gm.form(level, dt, nrhs) == form
+
+    def __exit__(self, *exc):
+        gm, level, dt, nrhs, _ = self.args
+        gm.set_form(level, dt, nrhs, ebe.FORM_AUTO)
+
+
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("nrhs", [1, 3, 4, 7, 16])
-def test_matvec_matches_oracle(small, dtype, nrhs):
+@pytest.mark.parametrize("nrhs", [1, 3, 4, 7, 9, 16])
+def test_matvec_matches_oracle(small, dtype, nrhs, form):
     m, gm, K, _, kap = small
     x = meshgen.rng_for(80, nrhs).standard_normal((m.n_nodes, 3, nrhs))
     xd = x.astype(dtype)
-    y = gm.matvec(to_dev(xd, dtype)).cpu().numpy().astype(np.float64)
+    with forced_form(gm, 0, dtype, nrhs, form):
+        y = gm.matvec(to_dev(xd, dtype)).cpu().numpy().astype(np.float64)
     ref = (K @ xd.astype(np.float64).reshape(-1, nrhs)).reshape(y.shape)
-    assert_close_bound(y, ref, abs(K), xd.astype(np.float64), dtype, kap, f"matvec {dtype.__name__} n={nrhs}")
+    assert_close_bound(y, ref, abs(K), xd.astype(np.float64), dtype, kap,
+                       f"matvec {dtype.__name__} n={nrhs} form={form}")
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_matvec_with_dirichlet_projection(small, dtype):
+def test_matvec_with_dirichlet_projection(small, dtype, form):
     m, gm, K, _, kap = small
     x = meshgen.rng_for(81, 0).standard_normal((m.n_nodes, 3, 5)).astype(dtype)
-    y = gm.matvec(to_dev(x, dtype), apply_bc=True).cpu().numpy().astype(np.float64)
+    with forced_form(gm, 0, dtype, 5, form):
+        y = gm.matvec(to_dev(x, dtype), apply_bc=True).cpu().numpy().astype(np.float64)
     ref = fem.matvec_bc(K, x.astype(np.float64), m.fixed)
     assert np.all(y[m.fixed.astype(bool)] == 0.0)
     assert_close_bound(y, ref, abs(K), x.astype(np.float64), dtype, kap, "matvec P K P")
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_linear_matvec_matches_oracle(small, dtype):
+def test_linear_matvec_matches_oracle(small, dtype, form):
     m, gm, _, K1, kap = small
     x = meshgen.rng_for(82, 0).standard_normal((m.n_vertices, 3, 4)).astype(dtype)
-    y = gm.matvec_p1(to_dev(x, dtype)).cpu().numpy().astype(np.float64)
+    with forced_form(gm, 1, dtype, 4, form):
+        y = gm.matvec_p1(to_dev(x, dtype)).cpu().numpy().astype(np.float64)
+        yb = gm.matvec_p1(to_dev(x, dtype), apply_bc=True).cpu().numpy().astype(np.float64)
     ref = (K1 @ x.astype(np.float64).reshape(-1, 4)).reshape(y.shape)
     assert_close_bound(y, ref, abs(K1), x.astype(np.float64), dtype, kap, "K1 x")
-    yb = gm.matvec_p1(to_dev(x, dtype), apply_bc=True).cpu().numpy().astype(np.float64)
     refb = fem.matvec_bc(K1, x.astype(np.float64), m.fixed[:m.n_vertices])
     assert_close_bound(yb, refb, abs(K1), x.astype(np.float64), dtype, kap, "P K1 P x")
+
+
+def test_autotune_keeps_the_faster_form(small):
+    m, gm, K, _, kap = small
+    for level, nrhs in ((0, 4), (1, 16)):
+        t_gather, t_staged = gm.autotune(level, torch.float32, nrhs)
+        print(f"[autotune level {level} n={nrhs}] gather {t_gather:.4f} ms, staged {t_staged:.4f} ms", flush=True)
+        assert t_gather > 0 and t_staged > 0
+        want = ebe.FORM_STAGED if t_staged < t_gather else ebe.FORM_GATHER
+        assert gm.form(level, torch.float32, nrhs) == want
+        gm.set_form(level, torch.float32, nrhs, ebe.FORM_AUTO)
+    with pytest.raises(ebe.EbeError):
+        gm.set_form(0, torch.float32, 4, 7)
+    with pytest.raises(ebe.EbeError):
+        gm.autotune(2, torch.float32, 4)
 
 
 def test_multi_rhs_equals_single_columns(small):
@@ -131,6 +174,13 @@ def test_argument_errors(small):
         gm.matvec(x, out=x)
     y = gm.matvec(x)
     assert float(y.abs().max()) == 0.0
+    # a vector that is not 16-byte aligned is refused before any launch
+    lib = ebe.load()
+    big = torch.zeros(m.n_nodes * 6 + 2, dtype=torch.float64, device="cuda")
+    st = lib.ebe_matvec(gm.handle, ebe.F64, 2, ctypes.c_void_p(big.data_ptr() + 8),
+                        ctypes.c_void_p(y.data_ptr()), 0, None)
+    assert st == ebe.ERR_ARG
+    assert b"aligned" in lib.ebe_last_error()
 
 
 def test_single_element_mesh(gpu_lib):

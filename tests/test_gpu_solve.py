@@ -56,6 +56,24 @@ def crust(gpu_lib):
     return m, ebe.Mesh.from_generated(m), f, K, solve.sparse_solve(K, f, m.fixed)
 
 
+@pytest.mark.parametrize("form", [ebe.FORM_GATHER, ebe.FORM_STAGED])
+def test_crust_mixed_mg2_in_each_product_form(crust, form):
+    """Every product of the solve (outer FP64, inner FP32 on both levels,
+    each also forming (p, K p)) in one given form."""
+    m, gm, f, K, ud = crust
+    keys = [(0, torch.float64), (0, torch.float32), (1, torch.float32)]
+    try:
+        for level, dt in keys:
+            gm.set_form(level, dt, 16, form)
+        u, st = gm.solve(dev(f), precond=ebe.PREC_MG2, mode=ebe.MODE_MIXED, tol=1e-8)
+    finally:
+        for level, dt in keys:
+            gm.set_form(level, dt, 16, ebe.FORM_AUTO)
+    print(f"[crust mixed MG2 form={form}] {st}", flush=True)
+    assert st["status"] == ebe.OK and st["max_rel_res"] <= 1e-8
+    assert rel_err(u.cpu().numpy(), ud) <= 1e-6
+
+
 @pytest.mark.parametrize("coarse_guess", [0, 1])
 def test_crust_mixed_mg2_within_1e6(crust, coarse_guess):
     m, gm, f, K, ud = crust
@@ -99,6 +117,32 @@ def test_initial_guess_and_iteration_cap(crust):
     assert st["status"] == ebe.NOT_CONVERGED and st["outer_iters"] == 3
 
 
+@pytest.mark.parametrize("precond,mode", [(ebe.PREC_MG2, ebe.MODE_MIXED), (ebe.PREC_PCGE, ebe.MODE_FP64)])
+def test_graph_replays_match_eager_solves(crust, precond, mode):
+    """On a non-default stream the fixed runs of steps between convergence
+    checks are captured once and replayed.  Three solves into the same output
+    (replaying the same graphs), with eager work and host synchronisation in
+    between, each reach the eager solve's answer."""
+    m, gm, f, K, ud = crust
+    fd = dev(f[:, :, :5])
+    ref = ud[:, :, :5]
+    s = torch.cuda.Stream()
+    opts_e = ebe.default_opts(precond=precond, mode=mode, tol=1e-9, graphs=0)
+    opts_g = ebe.default_opts(precond=precond, mode=mode, tol=1e-9, graphs=1)
+    with torch.cuda.stream(s):
+        ue, ste = gm.solve(fd, opts=opts_e, stream=s)
+        ug = torch.empty_like(fd)
+        for rep in range(3):
+            ug.fill_(float(rep + 1))  # eager work between replays
+            _, stg = gm.solve(fd, u=ug, opts=opts_g, stream=s)
+            s.synchronize()
+            print(f"[graphs precond={precond} rep={rep}] {stg} (eager {ste})", flush=True)
+            assert stg["status"] == ebe.OK and stg["max_rel_res"] <= 1e-9
+            assert abs(stg["outer_iters"] - ste["outer_iters"]) <= 1
+            assert float((ug - ue).norm() / ue.norm()) <= 1e-6
+            assert rel_err(ug.cpu().numpy(), ref) <= 1e-6
+
+
 def test_nonfinite_input_is_reported(crust):
     m, gm, f, K, ud = crust
     fb = f[:, :, :1].copy()
@@ -122,6 +166,32 @@ def test_batch_of_uneven_meshes(gpu_lib):
     for u, r, st in zip(us, refs, sts):
         assert st["status"] == ebe.OK
         assert rel_err(u.cpu().numpy(), r) <= 1e-6
+
+
+def test_batch_with_more_meshes_than_lanes_and_an_error(gpu_lib):
+    """Seven meshes over the batch's worker streams: each result equals that
+    mesh's own solve; a non-finite right-hand side fails with its mesh named."""
+    grids = [(3, 3, 2), (4, 3, 2), (4, 4, 2), (5, 4, 3), (3, 5, 2), (6, 5, 3), (4, 4, 4)]
+    gms, fs = [], []
+    for k, g in enumerate(grids):
+        m = meshgen.crust_mesh(*g)
+        f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(5, 20 + k), nrhs=1 + (5 * k) % 16)
+        gms.append(ebe.Mesh.from_generated(m))
+        fs.append(dev(f))
+    opts = ebe.default_opts(tol=1e-10)
+    us, sts = ebe.batch_solve(gms, fs, opts=opts)
+    for gm, f, u, st in zip(gms, fs, us, sts):
+        assert st["status"] == ebe.OK and st["max_rel_res"] <= 1e-10
+        u1, st1 = gm.solve(f, opts=opts)
+        assert st1["status"] == ebe.OK
+        assert float((u - u1).norm() / u1.norm()) <= 1e-6
+    bad = [f.clone() for f in fs]
+    free = int(np.nonzero(~meshgen.crust_mesh(*grids[4]).fixed.astype(bool).any(axis=1))[0][0])
+    bad[4][free, 1, 0] = float("nan")
+    with pytest.raises(ebe.EbeError) as ei:
+        ebe.batch_solve(gms, bad, opts=opts)
+    assert ei.value.status == ebe.ERR_NONFINITE
+    assert "mesh 4" in str(ei.value)
 
 
 # ---------------------------------------------------------------------------
