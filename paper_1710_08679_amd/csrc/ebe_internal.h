@@ -74,21 +74,32 @@ struct Workspace {
   std::vector<Graph> graphs;
 };
 
-// Element patches (patches.cpp): at most kPatchElems elements touching at
-// most kPatchNodes nodes, so a patch's node sums fit in LDS.
+// Element patches (patches.cpp): consecutive element ranges whose node sums
+// fit in LDS.  Quadratic level: at most kPatchElems elements touching at most
+// kPatchNodes nodes.  Linear level: at most kLinPatchElems elements touching
+// at most kLinPatchCorners corners (a linear element carries far less work,
+// so its patches are larger).
 #ifndef EBE_PATCH_ELEMS
 #define EBE_PATCH_ELEMS 64
 #endif
 #ifndef EBE_PATCH_NODES
 #define EBE_PATCH_NODES 192
 #endif
+#ifndef EBE_LIN_PATCH_ELEMS
+#define EBE_LIN_PATCH_ELEMS 256
+#endif
+#ifndef EBE_LIN_PATCH_CORNERS
+#define EBE_LIN_PATCH_CORNERS 128
+#endif
 #ifndef EBE_PATCH_THREADS
 #define EBE_PATCH_THREADS 512
 #endif
 constexpr int kPatchElems = EBE_PATCH_ELEMS;
 constexpr int kPatchNodes = EBE_PATCH_NODES;
-constexpr int kPatchCorners = 64;                 // corner nodes of a patch (the linear level)
+constexpr int kLinPatchElems = EBE_LIN_PATCH_ELEMS;
+constexpr int kLinPatchCorners = EBE_LIN_PATCH_CORNERS;  // local ids are bytes: at most 256
 constexpr int kPatchThreads = EBE_PATCH_THREADS;  // workgroup size cap of the patch kernels
+static_assert(kPatchNodes <= 256 && kLinPatchCorners <= 256, "patch-local node ids are bytes");
 // (x, K x) sums of the patch kernels: workgroup w adds its per-case sums to
 // slot w % kGammaSlots (one 128-byte line each), and the last workgroup to
 // finish folds the slots into the caller's result.
@@ -97,6 +108,8 @@ constexpr size_t kGammaBytes = size_t(kGammaSlots) * EBE_MAX_RHS * sizeof(double
 
 // Patch tables of one level (0: all nodes of the quadratic mesh, 1: corners).
 struct PatchLevel {
+  DBuf pelem;   // int32 [npatch+1] element offsets (patches are element ranges)
+  int64_t npatch = 0;
   DBuf poff;    // int32 [npatch+1] entry offsets
   DBuf pnode;   // int32 [entries] node id | fix bits << 28 | shared << 31
   DBuf pslot;   // int32 [entries] staging slot of a shared entry, -1 otherwise
@@ -123,11 +136,9 @@ struct ebe_mesh {
   ebe::DBuf edge_ends;  // int32 [N-Nv][2]
   ebe::DBuf v2e_off;    // int32 [Nv+1] corner -> incident edge nodes (CSR)
   ebe::DBuf v2e_idx;    // int32 [2 (N-Nv)]
-  // element patches
-  int64_t n_patch = 0;
-  ebe::DBuf pelem;      // int32 [n_patch+1] element offsets
-  ebe::DBuf lconn;      // uint8 [E][16] patch-local ids of the 10 nodes (padded to 16 bytes)
-  ebe::DBuf lconn1;     // uint8 [E][4]  patch-local ids of the 4 corners
+  // element patches of the two levels
+  ebe::DBuf lconn;      // uint8 [E][16] quadratic-patch-local ids of the 10 nodes (padded to 16 bytes)
+  ebe::DBuf lconn1;     // uint8 [E][4]  linear-patch-local ids of the 4 corners
   ebe::PatchLevel pl[2];
   ebe::DBuf gacc;       // kGammaBytes: (x, K x) slots, then the arrival counter; zero between products
   // EBE product form per [level][dtype F64, F32][nrhs]: EBE_FORM_GATHER,

@@ -2,7 +2,8 @@
 // quadratic mesh and y = K1 x for the linear (corner) mesh, n cases at once.
 //
 // Work decomposition (see patches.cpp).  One workgroup per element patch
-// (<= 64 elements, <= 192 nodes):
+// (quadratic level: <= 64 elements, <= 192 nodes; linear level: <= 256
+// elements, <= 128 corners):
 //   1. one work-item per element rebuilds the element geometry from the four
 //      corner coordinates and material (the element matrix is never stored,
 //      Section 2) and keeps it in LDS;
@@ -67,7 +68,8 @@ constexpr int chunk_for(int nr, int order, int value_bytes, bool stage) {
 
 // one work-item per (element, case) of a pass, at most kPatchThreads
 constexpr int threads_for(int nr, int order, int value_bytes, bool stage) {
-  const int want = (kPatchElems * chunk_for(nr, order, value_bytes, stage) + 63) / 64 * 64;
+  const int want = ((order == 2 ? kPatchElems : kLinPatchElems) * chunk_for(nr, order, value_bytes, stage) + 63) /
+                   64 * 64;
   return want > kPatchThreads ? kPatchThreads : want;
 }
 
@@ -78,9 +80,10 @@ constexpr int threads_for(int nr, int order, int value_bytes, bool stage) {
 // element) or 256 (quadratic FP64).
 template <typename T>
 constexpr int patch_lds_bytes(int nr, int order, bool stage) {
-  const int maxn = order == 2 ? kPatchNodes : kPatchCorners;
+  const int maxn = order == 2 ? kPatchNodes : kLinPatchCorners;
   const int wc = 3 * chunk_for(nr, order, int(sizeof(T)), stage);
-  return maxn * wc * 8 + (stage ? maxn * wc * int(sizeof(T)) : 0) + kPatchElems * 14 * int(sizeof(T)) +
+  return maxn * wc * 8 + (stage ? maxn * wc * int(sizeof(T)) : 0) +
+         (order == 2 ? kPatchElems : kLinPatchElems) * 14 * int(sizeof(T)) +
          8 * maxn + 8 * nr + 16;
 }
 template <typename T>
@@ -145,7 +148,8 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
   constexpr int W = 3 * NR;   // values of a node in x, y and the staging buffer
   constexpr int WC = 3 * CW;  // values of a node in one pass
   constexpr int TPB = threads_for(NR, ORDER, int(sizeof(T)), STAGE);
-  constexpr int MAXN = ORDER == 2 ? kPatchNodes : kPatchCorners;
+  constexpr int MAXN = ORDER == 2 ? kPatchNodes : kLinPatchCorners;
+  constexpr int PE = ORDER == 2 ? kPatchElems : kLinPatchElems;
   constexpr int VEC = pass_vec(NR, CW, int(sizeof(T)));  // values per vector access of a node row
   constexpr int NV = WC / VEC;                            // vectors of a node in one pass
   // Node-row staging: work-item t moves vector t % NV of nodes t / NV,
@@ -156,7 +160,7 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
   using V = VecT<T, VEC>;
   __shared__ double F[MAXN * WC];
   __shared__ __align__(16) T X[STAGE ? MAXN * WC : 1];
-  __shared__ T geo[kPatchElems][14];
+  __shared__ T geo[PE][14];
   __shared__ int32_t words[MAXN];
   __shared__ int32_t slots[MAXN];
   __shared__ double gsum[NR];
@@ -410,9 +414,9 @@ void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y
   using P = typename Pair<T>::type;
   const P* lame = (sizeof(T) == 8) ? reinterpret_cast<const P*>(m->lame64.as<void>())
                                    : reinterpret_cast<const P*>(m->lame32.as<void>());
-  hipLaunchKernelGGL((k_ebe_patch<T, NR, ORDER, STAGE>), dim3(unsigned(m->n_patch)),
+  hipLaunchKernelGGL((k_ebe_patch<T, NR, ORDER, STAGE>), dim3(unsigned(L.npatch)),
                      dim3(threads_for(NR, ORDER, int(sizeof(T)), STAGE)), 0, s, m->conn.as<int32_t>(),
-                     ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(), m->pelem.as<int32_t>(),
+                     ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(), L.pelem.as<int32_t>(),
                      L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(), m->xv.as<double4>(), lame,
                      static_cast<const T*>(x), static_cast<T*>(y), stage, int(mask_in), int(bc), int(add), gamma,
                      m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64),
@@ -481,7 +485,7 @@ hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt,
                            bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   const size_t need = size_t(L.nslots) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4);
-  if (L.stage.bytes() < need || m->n_patch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS ||
+  if (L.stage.bytes() < need || L.npatch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS ||
       (form != EBE_FORM_GATHER && form != EBE_FORM_STAGED))
     return hipErrorInvalidValue;  // staging not sized or bad form: host bug
   return dt == EBE_F64 ? ebe_dispatch<double>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma)

@@ -9,7 +9,9 @@
 // pass adds those partials in patch order.  No atomics reach global memory
 // and the result does not depend on scheduling.
 //
-// The same patches serve the linear level, restricted to corner nodes.
+// The linear level (corner nodes only) has patches of its own, larger in
+// elements: a linear element's product is a fraction of a quadratic one's,
+// so its workgroups need more elements to carry the fixed cost of a patch.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -78,6 +80,36 @@ void build_level(const std::vector<int32_t>& pelem, int nloc, int64_t n_nodes, c
   }
 }
 
+// Cut elements, in order, into ranges of at most max_elems elements touching
+// at most max_nodes distinct nodes (the nloc nodes of element e are
+// node_of(e, 0..nloc-1), distinct within an element).
+template <class NodeOf>
+std::vector<int32_t> cut_patches(int64_t E, int nloc, int64_t n_nodes, int max_elems, int max_nodes,
+                                 NodeOf node_of) {
+  std::vector<int32_t> pelem(1, 0), stamp(n_nodes, -1);
+  int32_t pid = 0, ne = 0, nn = 0;
+  for (int64_t e = 0; e < E; ++e) {
+    int fresh = 0;
+    for (int a = 0; a < nloc; ++a) fresh += stamp[node_of(e, a)] != pid;
+    if (ne == max_elems || nn + fresh > max_nodes) {
+      pelem.push_back(int32_t(e));
+      ++pid;
+      ne = 0;
+      nn = 0;
+    }
+    for (int a = 0; a < nloc; ++a) {
+      const int32_t v = node_of(e, a);
+      if (stamp[v] != pid) {
+        stamp[v] = pid;
+        ++nn;
+      }
+    }
+    ++ne;
+  }
+  pelem.push_back(int32_t(E));
+  return pelem;
+}
+
 template <class T>
 ebe_status up(DBuf& b, const std::vector<T>& h, hipStream_t s) {
   ebe_status st = b.alloc(std::max<size_t>(h.size(), 1) * sizeof(T));
@@ -91,66 +123,36 @@ ebe_status up(DBuf& b, const std::vector<T>& h, hipStream_t s) {
 
 ebe_status build_patches(ebe_mesh* m, const int32_t* conn10, const uint8_t* fix, hipStream_t s) {
   const int64_t E = m->n_elem;
-  // 1. cut elements into patches
-  std::vector<int32_t> pelem(1, 0);
-  {
-    std::vector<int32_t> stamp(m->n_nodes, -1);
-    int32_t pid = 0, ne = 0, nn = 0, nc = 0;
-    for (int64_t e = 0; e < E; ++e) {
-      const int32_t* c = conn10 + 10 * e;
-      int fresh = 0, fresh_c = 0;  // nodes (corners) of e not yet in the patch (an element's nodes are distinct)
-      for (int a = 0; a < 10; ++a)
-        if (stamp[c[a]] != pid) {
-          ++fresh;
-          if (a < 4) ++fresh_c;
-        }
-      if (ne == kPatchElems || nn + fresh > kPatchNodes || nc + fresh_c > kPatchCorners) {
-        pelem.push_back(int32_t(e));
-        ++pid;
-        ne = 0;
-        nn = 0;
-        nc = 0;
-      }
-      for (int a = 0; a < 10; ++a)
-        if (stamp[c[a]] != pid) {
-          stamp[c[a]] = pid;
-          ++nn;
-          if (a < 4) ++nc;
-        }
-      ++ne;
-    }
-    pelem.push_back(int32_t(E));
-  }
-  m->n_patch = int64_t(pelem.size()) - 1;
-
+  auto node_of = [&](int64_t e, int a) { return conn10[size_t(e) * 10 + a]; };
+  // 1. cut elements into patches, separately for each level
+  std::vector<int32_t> pelem[2] = {cut_patches(E, 10, m->n_nodes, kPatchElems, kPatchNodes, node_of),
+                                   cut_patches(E, 4, m->n_vertices, kLinPatchElems, kLinPatchCorners, node_of)};
   // 2. quadratic level (all 10 nodes) and linear level (corners)
   std::vector<uint8_t> lconn(size_t(E) * 16, 0), lconn1(size_t(E) * 4, 0);
-  LevelTables t2, t1;
-  build_level(pelem, 10, m->n_nodes, fix, [&](int32_t e, int a) { return conn10[size_t(e) * 10 + a]; }, lconn, 16,
-              t2);
-  build_level(pelem, 4, m->n_vertices, fix, [&](int32_t e, int a) { return conn10[size_t(e) * 10 + a]; }, lconn1,
-              4, t1);
-  if (t2.max_nodes > kPatchNodes || t1.max_nodes > kPatchCorners) {
-    set_error("build_patches: patch with %d nodes / %d corners exceeds %d / %d", t2.max_nodes, t1.max_nodes,
-              kPatchNodes, kPatchCorners);
+  LevelTables t[2];
+  build_level(pelem[0], 10, m->n_nodes, fix, node_of, lconn, 16, t[0]);
+  build_level(pelem[1], 4, m->n_vertices, fix, node_of, lconn1, 4, t[1]);
+  if (t[0].max_nodes > kPatchNodes || t[1].max_nodes > kLinPatchCorners) {
+    set_error("build_patches: patch with %d nodes / %d corners exceeds %d / %d", t[0].max_nodes, t[1].max_nodes,
+              kPatchNodes, kLinPatchCorners);
     return EBE_ERR_INDEX;
   }
   ebe_status st = EBE_OK;
-  PatchLevel* L[2] = {&m->pl[0], &m->pl[1]};
-  LevelTables* T[2] = {&t2, &t1};
-  if ((st = up(m->pelem, pelem, s)) != EBE_OK) return st;
   if ((st = up(m->lconn, lconn, s)) != EBE_OK) return st;
   if ((st = up(m->lconn1, lconn1, s)) != EBE_OK) return st;
   for (int l = 0; l < 2; ++l) {
-    if ((st = up(L[l]->poff, T[l]->poff, s)) != EBE_OK) return st;
-    if ((st = up(L[l]->pnode, T[l]->pnode, s)) != EBE_OK) return st;
-    if ((st = up(L[l]->pslot, T[l]->pslot, s)) != EBE_OK) return st;
-    if ((st = up(L[l]->snode, T[l]->snode, s)) != EBE_OK) return st;
-    if ((st = up(L[l]->soff, T[l]->soff, s)) != EBE_OK) return st;
-    L[l]->nslots = T[l]->nslots;
-    L[l]->nshared = int64_t(T[l]->snode.size());
-    L[l]->entries = int64_t(T[l]->pnode.size());
-    L[l]->max_nodes = T[l]->max_nodes;
+    PatchLevel& L = m->pl[l];
+    if ((st = up(L.pelem, pelem[l], s)) != EBE_OK) return st;
+    if ((st = up(L.poff, t[l].poff, s)) != EBE_OK) return st;
+    if ((st = up(L.pnode, t[l].pnode, s)) != EBE_OK) return st;
+    if ((st = up(L.pslot, t[l].pslot, s)) != EBE_OK) return st;
+    if ((st = up(L.snode, t[l].snode, s)) != EBE_OK) return st;
+    if ((st = up(L.soff, t[l].soff, s)) != EBE_OK) return st;
+    L.npatch = int64_t(pelem[l].size()) - 1;
+    L.nslots = t[l].nslots;
+    L.nshared = int64_t(t[l].snode.size());
+    L.entries = int64_t(t[l].pnode.size());
+    L.max_nodes = t[l].max_nodes;
   }
   return EBE_OK;
 }

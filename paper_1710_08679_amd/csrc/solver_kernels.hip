@@ -2,10 +2,10 @@
 //
 // Every CG loop in Algorithm 1 carries n cases with per-case scalars and
 // stops when the worst case meets its test (Section 3.1).  Here those scalars
-// never leave the GPU: a kernel that needs an inner product accumulates
-// per-case partial sums, the last workgroup to finish (arrival counter) adds
-// the partials in a fixed order and runs the scalar step (alpha, beta, rho,
-// the stopping test) for all cases.  Loop control is a device flag that
+// never leave the GPU: a kernel that needs an inner product leaves per-case
+// partial sums per workgroup, and a one-workgroup kernel after it adds them
+// in a fixed order and runs the scalar step (alpha, beta, rho, the stopping
+// test) for all cases.  Loop control is a device flag that
 // every later kernel of the loop reads first, so the host can enqueue
 // iterations ahead and only reads the flag now and then.
 //
@@ -37,9 +37,15 @@ __device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
 // ---------------------------------------------------------------------------
 // generic node-case kernel with NDOT per-case inner products and an epilogue
 // ---------------------------------------------------------------------------
-template <typename Acc, int NDOT, class Body, class Epi>
-__global__ __launch_bounds__(256) void k_nodecase(Body body, Epi epi, int64_t n_nodes, int nr,
-                                                  Acc* __restrict__ partials, unsigned* __restrict__ counter,
+// Each workgroup leaves its per-case sums in partials[output][workgroup]; a
+// one-workgroup kernel launched right after adds them in a fixed order and
+// runs the scalar step.  (A last-arriving-workgroup reduction inside the
+// first kernel needs a device-scope fence in every workgroup, which on this
+// multi-XCD part writes back the XCD's L2 each time: measured to cost about
+// as much as the vector work itself on the linear level.  The kernel
+// boundary makes the partials visible with one write-back.)
+template <typename Acc, int NDOT, class Body>
+__global__ __launch_bounds__(256) void k_nodecase(Body body, int64_t n_nodes, int nr, Acc* __restrict__ partials,
                                                   const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   // 256 work-items per workgroup; the first bd = (256 / nr) nr of them walk
@@ -56,7 +62,6 @@ __global__ __launch_bounds__(256) void k_nodecase(Body body, Epi epi, int64_t n_
       body(u / nr, col, acc);
   if constexpr (NDOT > 0) {
     __shared__ Acc sh[256 * NDOT];
-    __shared__ bool last;
 #pragma unroll
     for (int d = 0; d < NDOT; ++d) sh[d * 256 + threadIdx.x] = acc[d];
     __syncthreads();
@@ -65,35 +70,64 @@ __global__ __launch_bounds__(256) void k_nodecase(Body body, Epi epi, int64_t n_
       const int d = threadIdx.x / nr, c = threadIdx.x % nr;
       Acc s = Acc(0);
       for (int k = c; k < bd; k += nr) s += sh[d * 256 + k];
-      partials[size_t(blockIdx.x) * nsum + threadIdx.x] = s;
+      partials[size_t(threadIdx.x) * kMaxBlocks + blockIdx.x] = s;
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // Sum the per-workgroup partials with all 256 work-items: output o gets
-    // partials b = t, t + 256, ... from work-item t, then a fixed-order
-    // wavefront tree and a sum over the 4 wavefronts (deterministic).
-    __shared__ double tot[3 * EBE_MAX_RHS];
-    __shared__ double wsum[4][3 * EBE_MAX_RHS];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int o = 0; o < nsum; ++o) {
-      double s = 0.0;
-      for (unsigned b = threadIdx.x; b < gridDim.x; b += 256) s += double(partials[size_t(b) * nsum + o]);
+  }
+}
+
+// Sum the partials of `blocks` workgroups with 256 work-items: output o gets
+// partials b = t, t + 256, t + 512, t + 768 from work-item t (eight outputs'
+// loads in flight at once), then a fixed-order wavefront tree and a sum over
+// the 4 wavefronts (deterministic), and run the epilogue on the totals.
+template <typename Acc, int NDOT, class Epi>
+__global__ __launch_bounds__(256) void k_nodecase_epi(Epi epi, int nr, int blocks, const Acc* __restrict__ partials,
+                                                      const int* __restrict__ gate) {
+  static_assert(kMaxBlocks == 4 * 256, "four partials per work-item");
+  if (gate && *gate == 0) return;
+  __shared__ double tot[3 * EBE_MAX_RHS];
+  __shared__ double wsum[4][3 * EBE_MAX_RHS];
+  const int nsum = NDOT * nr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // Every load reads a written partial (indices clamped to the last output
+  // and workgroup), so all of them can be in flight together; the clamped
+  // duplicates are then weighted by zero.  (A duplicate can only be
+  // non-finite if an entry of the sum itself is, so the sum is unchanged.)
+  for (int o0 = 0; o0 < nsum; o0 += 8) {
+    double v[8][4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int b = int(threadIdx.x) + 256 * q;
+        const int o = o0 + j;
+        const double w = double(partials[size_t(o < nsum ? o : nsum - 1) * kMaxBlocks + (b < blocks ? b : blocks - 1)]);
+        v[j][q] = w * ((o < nsum && b < blocks) ? 1.0 : 0.0);
+      }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      double s = (v[j][0] + v[j][1]) + (v[j][2] + v[j][3]);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-      if (lane == 0) wsum[wave][o] = s;
+      if (lane == 0 && o0 + j < nsum) wsum[wave][o0 + j] = s;
     }
-    __syncthreads();
-    if (threadIdx.x < nsum) tot[threadIdx.x] = (wsum[0][threadIdx.x] + wsum[1][threadIdx.x]) +
-                                               (wsum[2][threadIdx.x] + wsum[3][threadIdx.x]);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      *counter = 0u;
-      epi(tot, nr);
+  }
+  __syncthreads();
+  if (int(threadIdx.x) < nsum)
+    tot[threadIdx.x] = (wsum[0][threadIdx.x] + wsum[1][threadIdx.x]) + (wsum[2][threadIdx.x] + wsum[3][threadIdx.x]);
+  __syncthreads();
+  // per-case scalar steps on wavefront 0, the loop test's maximum and the
+  // flags combined across it, then the shared step
+  if (threadIdx.x < 64) {
+    const int j = threadIdx.x;
+    double worst = 0.0;
+    int flags = 0;
+    if (j < nr) worst = epi.step(tot, nr, j, flags);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      worst = fmax(worst, __shfl_xor(worst, off, 64));
+      flags |= __shfl_xor(flags, off, 64);
     }
+    if (j == 0) epi.finish(worst, flags);
   }
 }
 
@@ -104,13 +138,20 @@ hipError_t run_nodecase(Body body, Epi epi, int64_t n_nodes, int nr, SolverState
   int64_t g = (n_nodes * nr + bd - 1) / bd;
   if (g > kMaxBlocks) g = kMaxBlocks;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL((k_nodecase<Acc, NDOT, Body, Epi>), dim3(unsigned(g)), dim3(256), 0, s, body, epi, n_nodes,
-                     nr, reinterpret_cast<Acc*>(st.partials), st.counter, gate);
+  Acc* partials = reinterpret_cast<Acc*>(st.partials);
+  hipLaunchKernelGGL((k_nodecase<Acc, NDOT, Body>), dim3(unsigned(g)), dim3(256), 0, s, body, n_nodes, nr, partials,
+                     gate);
+  if constexpr (NDOT > 0) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_nodecase_epi<Acc, NDOT, Epi>), dim3(1), dim3(256), 0, s, epi, nr, int(g), partials, gate);
+  }
   return hipGetLastError();
 }
 
 struct NoEpi {
-  __device__ void operator()(const double*, int) const {}
+  __device__ double step(const double*, int, int, int&) const { return 0.0; }
+  __device__ void finish(double, int) const {}
 };
 
 // ---------------------------------------------------------------------------
@@ -348,45 +389,53 @@ struct BodyInnerUpdate {
 // ---------------------------------------------------------------------------
 // epilogues (run by one thread of the last workgroup); see solver_state.h
 // ---------------------------------------------------------------------------
+// Epilogues run in two parts: step(tot, nr, j, flags) on work-item j for each
+// case j < nr (returns the case's value for the loop test's maximum and may
+// raise flag bits), then finish(worst, flags) once with the maximum and the
+// union of the flags.  kBreakdown / kNonfinite: (p, K p) <= 0 for a live
+// case, or a non-finite scalar (the latter takes precedence).
+constexpr int kBreakdown = 1, kNonfinite = 2;
+
+__device__ __forceinline__ int error_of(int flags) {
+  return (flags & kNonfinite) ? EBE_ERR_NONFINITE : ((flags & kBreakdown) ? EBE_ERR_BREAKDOWN : 0);
+}
+
 struct EpiOuterInit {
   SolverScalars* sc;
   double tol;
-  __device__ void operator()(const double* tot, int nr) const {
-    double worst = 0.0;
-    bool bad = false;
-    for (int j = 0; j < nr; ++j) {
-      const double ff = tot[j], rr = tot[nr + j];
-      sc->nf2[j] = ff;
-      sc->rr[j] = rr;
-      const double rel = ff > 0.0 ? sqrt(rr / ff) : 0.0;
-      sc->rel[j] = rel;
-      bad |= !finite_d(rel) || !finite_d(ff) || !finite_d(rr);
-      worst = fmax(worst, rel);
-      sc->alpha[j] = 0.0;
-      sc->beta[j] = 0.0;
-      sc->rho[j] = 0.0;
-    }
+  __device__ double step(const double* tot, int nr, int j, int& flags) const {
+    const double ff = tot[j], rr = tot[nr + j];
+    sc->nf2[j] = ff;
+    sc->rr[j] = rr;
+    const double rel = ff > 0.0 ? sqrt(rr / ff) : 0.0;
+    sc->rel[j] = rel;
+    if (!finite_d(rel) || !finite_d(ff) || !finite_d(rr)) flags |= kNonfinite;
+    sc->alpha[j] = 0.0;
+    sc->beta[j] = 0.0;
+    sc->rho[j] = 0.0;
+    return rel;
+  }
+  __device__ void finish(double worst, int flags) const {
     sc->max_rel = worst;
     sc->outer_iter = 0;
-    if (bad) sc->err = EBE_ERR_NONFINITE;
-    sc->outer_active = (!bad && worst > tol) ? 1 : 0;
+    if (flags) sc->err = error_of(flags);
+    sc->outer_active = (!flags && worst > tol) ? 1 : 0;
   }
 };
 
 struct EpiOuterBeta {
   SolverScalars* sc;
-  __device__ void operator()(const double* tot, int nr) const {
-    const bool first = sc->outer_iter == 0;
-    for (int j = 0; j < nr; ++j) {
-      const double zq = tot[j], zr = tot[nr + j];
-      // flexible CG: beta_i = -alpha_{i-1} (z_i, q_{i-1}) / rho_{i-1}
-      double b = 0.0;
-      if (!first && sc->rho[j] != 0.0) b = -sc->alpha[j] * zq / sc->rho[j];
-      if (!finite_d(b)) b = 0.0;
-      sc->beta[j] = b;
-      sc->rho[j] = zr;
-    }
+  __device__ double step(const double* tot, int nr, int j, int&) const {
+    const double zq = tot[j], zr = tot[nr + j];
+    // flexible CG: beta_i = -alpha_{i-1} (z_i, q_{i-1}) / rho_{i-1}
+    double b = 0.0;
+    if (sc->outer_iter != 0 && sc->rho[j] != 0.0) b = -sc->alpha[j] * zq / sc->rho[j];
+    if (!finite_d(b)) b = 0.0;
+    sc->beta[j] = b;
+    sc->rho[j] = zr;
+    return 0.0;
   }
+  __device__ void finish(double, int) const {}
 };
 
 // scalar step after r -= alpha q, u += alpha p: record alpha (used by the next
@@ -395,28 +444,24 @@ struct EpiOuterConv {
   SolverScalars* sc;
   double tol;
   int max_outer;
-  __device__ void operator()(const double* tot, int nr) const {
-    double worst = 0.0;
-    bool bad = false;
-    for (int j = 0; j < nr; ++j) {
-      const double g = sc->gamma[j];
-      if (g < 0.0 || (g == 0.0 && sc->rr[j] > 0.0 && sc->rho[j] != 0.0)) sc->err = EBE_ERR_BREAKDOWN;
-      if (!finite_d(g)) sc->err = EBE_ERR_NONFINITE;
-      sc->alpha[j] = outer_alpha(sc->rho[j], g);
-      sc->gamma[j] = 0.0;
-    }
-    for (int j = 0; j < nr; ++j) {
-      const double rr = tot[j];
-      sc->rr[j] = rr;
-      const double rel = sc->nf2[j] > 0.0 ? sqrt(rr / sc->nf2[j]) : 0.0;
-      sc->rel[j] = rel;
-      bad |= !finite_d(rel);
-      worst = fmax(worst, rel);
-    }
+  __device__ double step(const double* tot, int nr, int j, int& flags) const {
+    const double g = sc->gamma[j];
+    if (g < 0.0 || (g == 0.0 && sc->rr[j] > 0.0 && sc->rho[j] != 0.0)) flags |= kBreakdown;
+    if (!finite_d(g)) flags |= kNonfinite;
+    sc->alpha[j] = outer_alpha(sc->rho[j], g);
+    sc->gamma[j] = 0.0;
+    const double rr = tot[j];
+    sc->rr[j] = rr;
+    const double rel = sc->nf2[j] > 0.0 ? sqrt(rr / sc->nf2[j]) : 0.0;
+    sc->rel[j] = rel;
+    if (!finite_d(rel)) flags |= kNonfinite;
+    return rel;
+  }
+  __device__ void finish(double worst, int flags) const {
     sc->max_rel = worst;
     sc->outer_iter += 1;
-    if (bad) sc->err = EBE_ERR_NONFINITE;
-    sc->outer_active = (!bad && !sc->err && worst > tol && sc->outer_iter < max_outer) ? 1 : 0;
+    if (flags) sc->err = error_of(flags);
+    sc->outer_active = (!flags && !sc->err && worst > tol && sc->outer_iter < max_outer) ? 1 : 0;
   }
 };
 
@@ -425,20 +470,19 @@ struct EpiInnerStart {
   InnerScalars* in;
   double eps;
   int nmax;
-  __device__ void operator()(const double* tot, int nr) const {
-    double worst = 0.0;
-    for (int j = 0; j < nr; ++j) {
-      const double ee = tot[j], ze = tot[nr + j], rr = tot[2 * nr + j];
-      in->nr2[j] = rr;
-      const double ratio = rr > 0.0 ? ee / rr : 0.0;
-      if (isfinite(ratio)) worst = fmax(worst, ratio);
-      in->rho_a[j] = ze;
-      in->beta[j] = 0.0;
-      in->alpha[j] = 0.0;
-      in->gamma[j] = 0.0;
-    }
+  __device__ double step(const double* tot, int nr, int j, int&) const {
+    const double ee = tot[j], ze = tot[nr + j], rr = tot[2 * nr + j];
+    in->nr2[j] = rr;
+    const double ratio = rr > 0.0 ? ee / rr : 0.0;
+    in->rho_a[j] = ze;
+    in->beta[j] = 0.0;
+    in->alpha[j] = 0.0;
+    in->gamma[j] = 0.0;
+    return isfinite(ratio) ? ratio : 0.0;
+  }
+  __device__ void finish(double worst, int) const {
     in->i = 1;
-    in->active = (worst > eps && in->i < nmax) ? 1 : 0;
+    in->active = (worst > eps && 1 < nmax) ? 1 : 0;
   }
 };
 
@@ -449,23 +493,23 @@ struct EpiInnerStep {
   InnerScalars* in;
   double eps;
   int nmax;
-  __device__ void operator()(const double* tot, int nr) const {
-    double worst = 0.0;
-    for (int j = 0; j < nr; ++j) {
-      const double ee = tot[j], ze = tot[nr + j];
-      const double ratio = in->nr2[j] > 0.0 ? ee / in->nr2[j] : 0.0;
-      if (isfinite(ratio)) worst = fmax(worst, ratio);
-      const double rho_old = in->rho_a[j];
-      in->alpha[j] = inner_alpha(rho_old, in->gamma[j]);
-      in->gamma[j] = 0.0;
-      double b = (rho_old != 0.0) ? ze / rho_old : 0.0;
-      if (!isfinite(b)) b = 0.0;
-      in->beta[j] = b;
-      in->rho_a[j] = ze;
-    }
-    in->i += 1;
+  __device__ double step(const double* tot, int nr, int j, int&) const {
+    const double ee = tot[j], ze = tot[nr + j];
+    const double ratio = in->nr2[j] > 0.0 ? ee / in->nr2[j] : 0.0;
+    const double rho_old = in->rho_a[j];
+    in->alpha[j] = inner_alpha(rho_old, in->gamma[j]);
+    in->gamma[j] = 0.0;
+    double b = (rho_old != 0.0) ? ze / rho_old : 0.0;
+    if (!isfinite(b)) b = 0.0;
+    in->beta[j] = b;
+    in->rho_a[j] = ze;
+    return isfinite(ratio) ? ratio : 0.0;
+  }
+  __device__ void finish(double worst, int) const {
+    const int i = in->i + 1;
+    in->i = i;
     in->steps += 1;
-    in->active = (worst > eps && in->i < nmax) ? 1 : 0;
+    in->active = (worst > eps && i < nmax) ? 1 : 0;
   }
 };
 
