@@ -138,7 +138,7 @@ def solver_block(torch, ebe, meshgen, modes=("mixed_mg2", "fp64_mg2", "fp64_pcge
     return out
 
 
-FORM_NAMES = {0: "gather", 1: "staged"}
+FORM_NAMES = {0: "gather", 1: "staged", 2: "pipelined"}
 
 
 def batch_block(torch, ebe, meshgen, n_mesh, with_big):
@@ -223,18 +223,18 @@ def main():
         dt, p = tdt[name]
         vec_bytes = 3 * N * n * p
         sets = max(3, int(np.ceil(1.1e9 / (2 * vec_bytes))))  # > 1 GB of x/y: no reuse through the 256 MB MALL
-        tg, tst = gm.autotune(0, dt, n)  # keeps the faster product form for (dtype, n) on this mesh
+        tms = gm.autotune(0, dt, n)  # keeps the fastest product form for (dtype, n) on this mesh
         xs = [torch.randn((N, 3, n), dtype=torch.float64, device="cuda").to(dt) for _ in range(sets)]
         ys = [torch.empty((N, 3, n), dtype=dt, device="cuda") for _ in range(sets)]
         t_op = time_launches(lambda i: gm.matvec(xs[i % sets], out=ys[i % sets]), args.steps, args.warmup, torch)
         B = product_bytes(N, Nv, E, n, p)
         rec = {"dtype": name, "nrhs": n, "ms": t_op, "form": FORM_NAMES[gm.form(0, dt, n)],
-               "autotune_ms": {"gather": tg, "staged": tst},
+               "autotune_ms": {FORM_NAMES[f]: t for f, t in enumerate(tms)},
                "gdof_rhs_per_s": 3 * N * n / (t_op * 1e-3) / 1e9,
                "hbm_frac": B / (t_op * 1e-3) / 1e9 / HBM_PEAK_GBS,
                "alu_frac": E * n * FLOPS_PER_ELEM_RHS / (t_op * 1e-3) / 1e12 / ALU_PEAK_TFLOPS}
         variants.append(rec)
-        print(f"# {name} n={n} ({rec['form']}; tuning: gather {tg:.3f} / staged {tst:.3f} ms): "
+        print(f"# {name} n={n} ({rec['form']}; tuning ms: " + " / ".join(f"{FORM_NAMES[f]} {t:.3f}" for f, t in enumerate(tms)) + "): "
               f"{t_op:.3f} ms, {rec['gdof_rhs_per_s']:.1f} GDOF*RHS/s, "
               f"HBM {rec['hbm_frac']:.2%}, ALU {rec['alu_frac']:.2%}", file=sys.stderr, flush=True)
         del xs, ys
@@ -285,8 +285,9 @@ def main():
     roof, alt = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
     traffic = load_traffic(f"f32:16:{form}")
     roof["traffic"] = traffic
-    roof["kernel"] = (f"EBE product FP32 n=16, {form} form: k_ebe_patch<float,16,2,{str(form == 'staged').lower()}>"
-                      " + k_reduce_shared<float,16>")
+    roof["kernel"] = (f"EBE product FP32 n=16, {form} form: "
+                      + {"gather": "k_ebe_patch<float,16,2,false>", "staged": "k_ebe_patch<float,16,2,true>",
+                         "pipelined": "k_ebe_patch_pipe<float,16,2>"}[form] + " + k_reduce_shared<float,16>")
     roof["ms_per_launch"] = ms_events
     roof["algorithmic_bytes"] = B
     roof["algorithmic_flops"] = F

@@ -1,6 +1,6 @@
 // Per-mesh choice of the EBE product form.  Which form of the patch kernel
 // is faster depends on the dtype, the number of cases and the mesh (patch
-// node counts, how many nodes are shared), so it is measured: both forms run
+// node counts, how many nodes are shared), so it is measured: all forms run
 // the same product a few times on the mesh itself and the faster is kept for
 // that (level, dtype, nrhs).  Search over implementation parameters, as the
 // paper does for its own kernels (Section 4), only automated.
@@ -30,15 +30,16 @@ bool valid_args(const ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, co
 namespace ebe {
 
 ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const void* x, void* y, hipStream_t s,
-                        double ms[2]) {
+                        double ms[EBE_NUM_FORMS]) {
   const int order = level == 0 ? 2 : 1;
   ebe_status st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4);
   if (st != EBE_OK) return st;
   hipEvent_t a = nullptr, b = nullptr;
   EBE_TRY_HIP(hipEventCreate(&a));
   hipError_t e = hipEventCreate(&b);
-  double best[2] = {DBL_MAX, DBL_MAX};
-  for (int form = 0; form < 2 && e == hipSuccess; ++form) {
+  double best[EBE_NUM_FORMS];
+  for (int f = 0; f < EBE_NUM_FORMS; ++f) best[f] = DBL_MAX;
+  for (int form = 0; form < EBE_NUM_FORMS && e == hipSuccess; ++form) {
     e = launch_ebe_form(m, order, form, dt, nrhs, x, y, false, m->has_bc, false, nullptr, s);  // warm-up
     for (int r = 0; r < kRuns && e == hipSuccess; ++r) {
       e = hipEventRecord(a, s);
@@ -56,11 +57,12 @@ ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const vo
     set_error("autotune: %s", hipGetErrorString(e));
     return EBE_ERR_HIP;
   }
-  m->form[level][dt == EBE_F64 ? 0 : 1][nrhs] = int8_t(best[1] < best[0] ? EBE_FORM_STAGED : EBE_FORM_GATHER);
-  if (ms) {
-    ms[0] = best[0];
-    ms[1] = best[1];
-  }
+  int pick = 0;
+  for (int f = 1; f < EBE_NUM_FORMS; ++f)
+    if (best[f] < best[pick]) pick = f;
+  m->form[level][dt == EBE_F64 ? 0 : 1][nrhs] = int8_t(pick);
+  if (ms)
+    for (int f = 0; f < EBE_NUM_FORMS; ++f) ms[f] = best[f];
   return EBE_OK;
 }
 
@@ -78,20 +80,18 @@ ebe_status ebe_autotune(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, 
   if (st != EBE_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   EBE_TRY_HIP(launch_fill_zero(x.as<void>(), bytes, s));
-  double ms[2];
+  double ms[EBE_NUM_FORMS];
   st = tune_product(m, level, dt, nrhs, x.as<void>(), y.as<void>(), s, ms);
-  if (st == EBE_OK && ms_out) {
-    ms_out[0] = ms[0];
-    ms_out[1] = ms[1];
-  }
+  if (st == EBE_OK && ms_out)
+    for (int f = 0; f < EBE_NUM_FORMS; ++f) ms_out[f] = ms[f];
   EBE_TRY_HIP(hipStreamSynchronize(s));  // the temporaries are freed on return
   return st;
 }
 
 ebe_status ebe_set_product_form(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, int32_t form) {
   if (!valid_args(m, level, dt, nrhs, "ebe_set_product_form")) return EBE_ERR_ARG;
-  if (form != EBE_FORM_AUTO && form != EBE_FORM_GATHER && form != EBE_FORM_STAGED) {
-    set_error("ebe_set_product_form: form %d is not EBE_FORM_AUTO, _GATHER or _STAGED", form);
+  if (form < EBE_FORM_AUTO || form >= EBE_NUM_FORMS) {
+    set_error("ebe_set_product_form: form %d is not EBE_FORM_AUTO or a form below EBE_NUM_FORMS", form);
     return EBE_ERR_ARG;
   }
   m->form[level][dt == EBE_F64 ? 0 : 1][nrhs] = int8_t(form);

@@ -141,8 +141,8 @@ struct ebe_mesh {
   ebe::DBuf lconn1;     // uint8 [E][4]  linear-patch-local ids of the 4 corners
   ebe::PatchLevel pl[2];
   ebe::DBuf gacc;       // kGammaBytes: (x, K x) slots, then the arrival counter; zero between products
-  // EBE product form per [level][dtype F64, F32][nrhs]: EBE_FORM_GATHER,
-  // EBE_FORM_STAGED, or EBE_FORM_AUTO (untuned: a fixed default)
+  // EBE product form per [level][dtype F64, F32][nrhs]: one of the forms, or
+  // EBE_FORM_AUTO (untuned: a fixed default)
   int8_t form[2][2][EBE_MAX_RHS + 1];
   ebe_mesh() { std::memset(form, EBE_FORM_AUTO, sizeof(form)); }
   // 3x3 block Jacobi: inverted symmetric blocks (xx yy zz yz zx xy), per level
@@ -167,15 +167,15 @@ hipError_t launch_ebe_p1(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* 
 // ensure_stage.
 hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in,
                       bool bc, bool add, const int* gate, hipStream_t s, double* gamma = nullptr);
-// the same with the product form given (EBE_FORM_GATHER or EBE_FORM_STAGED)
+// the same with the product form given (0 <= form < EBE_NUM_FORMS)
 hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt, int nrhs, const void* x, void* y,
                            bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma = nullptr);
 // the form launch_ebe uses for (order, dtype, nrhs)
 int product_form(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs);
-// time both forms of y = K x on this mesh (x, y: device vectors of the
-// level's size; y is overwritten) and record the faster; synchronous.
+// time every form of y = K x on this mesh (x, y: device vectors of the
+// level's size; y is overwritten) and record the fastest; synchronous.
 ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const void* x, void* y, hipStream_t s,
-                        double ms[2]);
+                        double ms[EBE_NUM_FORMS]);
 hipError_t launch_diag_blocks(const ebe_mesh* m, int level, double* blk6, hipStream_t s);
 hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6, double* inv64,
                                 float* inv32, hipStream_t s);

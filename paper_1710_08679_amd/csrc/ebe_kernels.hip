@@ -26,6 +26,9 @@
 // result does not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "ebe_internal.h"
 #include "p2_element.h"
 
@@ -128,6 +131,58 @@ __device__ __forceinline__ int spread_element(int j, int ne) {
   }
 }
 
+// Element geometry into LDS: barycentric gradients G (rows 0..3), then
+// lambda s and mu s with s = V / 20 (quadratic: int L_k L_l dV = V (1 +
+// delta_kl) / 20) or s = V (linear).
+template <typename T, int ORDER>
+__device__ __forceinline__ void store_geometry(T* __restrict__ g, const double4& p0, const double4& p1,
+                                               const double4& p2, const double4& p3,
+                                               const typename Pair<T>::type& lm) {
+  T G[4][3];
+  const T V = tet_geometry<T>(p0, p1, p2, p3, G);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[3 * k + d] = G[k][d];
+  const T s = ORDER == 2 ? V * T(0.05) : V;
+  g[12] = T(lm.x) * s;
+  g[13] = T(lm.y) * s;
+}
+
+// End of a patch kernel that formed (x, K x): gsum[NR] (LDS, complete) holds
+// this workgroup's per-case sums.  The device-scope additions are spread over
+// kGammaSlots lines (thousands of workgroups adding to one line serialise on
+// it); the last workgroup to arrive folds the slots into gamma, clearing them
+// as it reads.  Every access of this protocol is a device-scope atomic, so no
+// fence is needed (an agent-scope fence writes back the XCD's L2, which costs
+// far more than the product when every workgroup does it): a work-item waits
+// for the value its addition returns, which proves the addition done, before
+// the workgroup arrives at the counter.  Called by every work-item.
+template <int NR, int TPB>
+__device__ void fold_gamma(double* __restrict__ gsum, double* __restrict__ gamma, double* __restrict__ gslot,
+                           unsigned* __restrict__ gcount) {
+  __shared__ bool last;
+  const int tid = threadIdx.x;
+  if (tid < NR) {
+    const double old = __hip_atomic_fetch_add(gslot + (blockIdx.x % kGammaSlots) * EBE_MAX_RHS + tid, gsum[tid],
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("" ::"v"(old));
+  }
+  __syncthreads();
+  if (tid == 0) last = atomicAdd(gcount, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  if (tid < NR) gsum[tid] = 0.0;
+  __syncthreads();
+  for (int i = tid; i < kGammaSlots * NR; i += TPB) {
+    const int sl = i / NR, r = i - sl * NR;
+    atomicAdd(&gsum[r], atomicExch(gslot + sl * EBE_MAX_RHS + r, 0.0));
+  }
+  __syncthreads();
+  if (tid < NR) unsafeAtomicAdd(gamma + tid, gsum[tid]);
+  if (tid == 0) atomicExch(gcount, 0u);
+}
+
 // STAGE: the staged form (else the gather form).  mask_in: zero the fixed
 // DOFs of x while reading it (y = P K P x); callers whose x is already zero
 // there (the solver) skip it.  bc: zero the fixed DOFs of y.  add: y += K x
@@ -176,17 +231,8 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
   if (tid < NR) gsum[tid] = 0.0;
   for (int el = tid; el < ne; el += TPB) {
     const int64_t e = int64_t(e0) + el;
-    T G[4][3];
-    const T V = tet_geometry<T>(xv[conn[e * 10 + 0] & kIdxMask], xv[conn[e * 10 + 1] & kIdxMask],
-                                xv[conn[e * 10 + 2] & kIdxMask], xv[conn[e * 10 + 3] & kIdxMask], G);
-    const auto lm = lame[e];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) geo[el][3 * k + d] = G[k][d];
-    const T s = ORDER == 2 ? V * T(0.05) : V;  // int L_k L_l dV = V (1 + delta_kl) / 20
-    geo[el][12] = T(lm.x) * s;
-    geo[el][13] = T(lm.y) * s;
+    store_geometry<T, ORDER>(geo[el], xv[conn[e * 10 + 0] & kIdxMask], xv[conn[e * 10 + 1] & kIdxMask],
+                             xv[conn[e * 10 + 2] & kIdxMask], xv[conn[e * 10 + 3] & kIdxMask], lame[e]);
   }
   // (x, K x) contributions: when the pass width divides 64 a work-item keeps
   // one case for all its items, so it sums them in a register and the lanes
@@ -321,34 +367,233 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
     }
     if (pass + 1 < NPASS) __syncthreads();  // X and F are refilled by the next pass
   }
-  if (!gamma) return;
-  // Spread the device-scope additions over kGammaSlots lines (thousands of
-  // workgroups adding to one line serialise on it), then let the last
-  // workgroup to arrive fold the slots into gamma, clearing them as it reads.
-  // Every access of this protocol is a device-scope atomic, so no fence is
-  // needed (an agent-scope fence writes back the XCD's L2, which costs far
-  // more than the product when every workgroup does it): a work-item waits
-  // for the value its addition returns, which proves the addition done,
-  // before the workgroup arrives at the counter.
-  __shared__ bool last;
-  if (tid < NR) {
-    const double old = __hip_atomic_fetch_add(gslot + (blockIdx.x % kGammaSlots) * EBE_MAX_RHS + tid, gsum[tid],
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    asm volatile("" ::"v"(old));
-  }
-  __syncthreads();
-  if (tid == 0) last = atomicAdd(gcount, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
+  if (gamma) fold_gamma<NR, TPB>(gsum, gamma, gslot, gcount);
+}
+
+// Pipelined gather form: a persistent workgroup works through a sequence of
+// patches (those of its XCD's contiguous range, in steps of the number of
+// workgroups on that XCD) and keeps the next patch's metadata in flight
+// while it computes the current one, so the chain of dependent loads (patch
+// bounds -> node words, connectivity -> coordinates, local ids) leaves the
+// critical path.  Per patch:
+//   A. commit the prefetched node words and slots to LDS, build the element
+//      geometry from the prefetched coordinates, clear F;
+//   B. issue the next patch's bounds, node words, slots, connectivity and
+//      material;
+//   C. element phase (as the gather form);
+//   D. issue the next patch's coordinates and this work-item's local ids;
+//   E. write back (exclusive nodes to y, shared ones to their staging slot).
+template <typename T, int NR, int ORDER>
+__global__ __launch_bounds__(threads_for(NR, ORDER, int(sizeof(T)), false))
+__attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) void k_ebe_patch_pipe(
+    const int32_t* __restrict__ conn, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
+    const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
+    const double4* __restrict__ xv, const typename Pair<T>::type* __restrict__ lame, const T* __restrict__ x,
+    T* __restrict__ y, T* __restrict__ stage, int npatch, int mask_in, int bc, int add, double* __restrict__ gamma,
+    double* __restrict__ gslot, unsigned* __restrict__ gcount, const int* __restrict__ gate) {
+  using P2 = typename Pair<T>::type;
+  using LW = typename std::conditional<ORDER == 2, uint4, uint32_t>::type;  // an element's local ids
+  constexpr int NLOC = ORDER == 2 ? 10 : 4;
+  constexpr int W = 3 * NR;
+  constexpr int TPB = threads_for(NR, ORDER, int(sizeof(T)), false);
+  constexpr int MAXN = ORDER == 2 ? kPatchNodes : kLinPatchCorners;
+  constexpr int PE = ORDER == 2 ? kPatchElems : kLinPatchElems;
+  constexpr int KW = (MAXN + TPB - 1) / TPB;           // node entries per work-item
+  constexpr int KE = (PE + TPB - 1) / TPB;             // elements per work-item (geometry)
+  constexpr int GW = 64 / NR > 1 ? 64 / NR : 1;        // elements per wave in the element phase
+  constexpr int KI = ((PE + GW - 1) / GW * GW * NR + TPB - 1) / TPB;  // element-phase items per work-item
+  constexpr int VEC = pass_vec(NR, NR, int(sizeof(T)));
+  constexpr int NV = W / VEC;
+  constexpr int EPK = TPB / NV;
+  constexpr int KIT = (MAXN + EPK - 1) / EPK;
+  using V = VecT<T, VEC>;
+  __shared__ double F[MAXN * W];
+  __shared__ T geo[PE][14];
+  __shared__ int32_t words[MAXN];
+  __shared__ int32_t slots[MAXN];
+  __shared__ double gsum[NR];
+  if (gate && *gate == 0) return;
+  const int tid = threadIdx.x;
+  // this workgroup's patches: XCD x owns [start, start + count); its g-th
+  // workgroup takes start + g, start + g + wx, ...
+  const int G = gridDim.x, xcd = blockIdx.x % kXcds;
+  const int wx = (G - xcd + kXcds - 1) / kXcds;  // workgroups on this XCD
+  const int q = npatch / kXcds, rr = npatch % kXcds;
+  const int start = xcd * q + (xcd < rr ? xcd : rr), stop = start + q + (xcd < rr ? 1 : 0);
+  int p = start + int(blockIdx.x) / kXcds;
   if (tid < NR) gsum[tid] = 0.0;
-  __syncthreads();
-  for (int i = tid; i < kGammaSlots * NR; i += TPB) {
-    const int sl = i / NR, r = i - sl * NR;
-    atomicAdd(&gsum[r], atomicExch(gslot + sl * EBE_MAX_RHS + r, 0.0));
+  const int sv = tid % NV, sent = tid < EPK * NV ? tid / NV : MAXN, sq = sv * VEC, sc = sq / NR, scc = sq - sc * NR;
+
+  // prefetched state of patch p
+  int e0 = 0, ne = 0, o0 = 0, nn = 0;
+  int pw[KW], ps[KW], pc[KE][4];
+  P2 plm[KE];
+  double4 pxv[KE][4];
+  LW pl[KI];
+  auto fetch_meta = [&](int pp) {  // bounds, node words, slots, connectivity, material of patch pp
+    e0 = pelem[pp];
+    ne = pelem[pp + 1] - e0;
+    o0 = poff[pp];
+    nn = poff[pp + 1] - o0;
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      const int i = tid + k * TPB;
+      pw[k] = i < nn ? pnode[o0 + i] : 0;
+      ps[k] = i < nn ? pslot[o0 + i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+      const int el = tid + k * TPB;
+      if (el < ne) {
+        const int64_t e = int64_t(e0) + el;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) pc[k][a] = conn[e * 10 + a] & kIdxMask;
+        plm[k] = lame[e];
+      }
+    }
+  };
+  auto fetch_late = [&]() {  // coordinates of the prefetched connectivity, local ids of this work-item's items
+#pragma unroll
+    for (int k = 0; k < KE; ++k)
+      if (tid + k * TPB < ne) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) pxv[k][a] = xv[pc[k][a]];
+      }
+    const int nj = spread_count<NR>(ne);
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+      const int w = tid + k * TPB, j = w / NR, el = spread_element<NR>(j, ne);
+      if (w < nj * NR && el < ne) pl[k] = *reinterpret_cast<const LW*>(lconn + (int64_t(e0) + el) * (ORDER == 2 ? 16 : 4));
+    }
+  };
+  if (p < stop) {
+    fetch_meta(p);
+    fetch_late();
+  }
+  double en_acc = 0.0;
+  constexpr bool kLaneCase = (64 % NR) == 0 && (TPB % NR) == 0;
+#pragma unroll 1
+  for (; p < stop; p += wx) {
+    // A. commit this patch
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      const int i = tid + k * TPB;
+      if (i < nn) {
+        words[i] = pw[k];
+        slots[i] = ps[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+      const int el = tid + k * TPB;
+      if (el < ne) store_geometry<T, ORDER>(geo[el], pxv[k][0], pxv[k][1], pxv[k][2], pxv[k][3], plm[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < KIT; ++k) {
+      const int ent = sent + k * EPK;
+      if (ent < nn) {
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) F[ent * W + sq + t] = 0.0;
+      }
+    }
+    const int cne = ne, cnn = nn;
+    LW cl[KI];
+#pragma unroll
+    for (int k = 0; k < KI; ++k) cl[k] = pl[k];
+    __syncthreads();
+    // B. the next patch's metadata
+    const int pn = p + wx;
+    if (pn < stop) fetch_meta(pn);
+    // C. element phase of this patch
+    const int nj = spread_count<NR>(cne);
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+      const int w = tid + k * TPB;
+      const int j = w / NR, r = w - j * NR;
+      const int el = spread_element<NR>(j, cne);
+      if (w >= nj * NR || el >= cne) continue;
+      int lid[NLOC], gw[NLOC];
+      if constexpr (ORDER == 2) {
+        const uint32_t qw[3] = {cl[k].x, cl[k].y, cl[k].z};
+#pragma unroll
+        for (int a = 0; a < NLOC; ++a) lid[a] = (qw[a >> 2] >> (8 * (a & 3))) & 0xff;
+      } else {
+#pragma unroll
+        for (int a = 0; a < NLOC; ++a) lid[a] = (cl[k] >> (8 * a)) & 0xff;
+      }
+#pragma unroll
+      for (int a = 0; a < NLOC; ++a) {
+        gw[a] = words[lid[a]];
+        lid[a] = lid[a] * W + r;
+      }
+      T Gm[4][3];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Gm[kk][d] = geo[el][3 * kk + d];
+      const T clam = geo[el][12], cmu = geo[el][13];
+      T en = T(0);
+      auto u = [&](int a, int c) -> T {
+        const T v = x[size_t(uint32_t(gw[a]) & uint32_t(kIdxMask)) * W + c * NR + r];
+        return (mask_in && ((gw[a] >> (kIdxBits + c)) & 1)) ? T(0) : v;
+      };
+      auto emit = [&](int a, const T f[3]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(F + lid[a] + c * NR, double(f[c]));
+      };
+      if constexpr (ORDER == 2) p2_apply<T>(Gm, clam, cmu, u, emit, gamma != nullptr, en);
+      else p1_apply<T>(Gm, clam, cmu, u, emit, gamma != nullptr, en);
+      if (gamma) {
+        if constexpr (kLaneCase) en_acc += double(en);
+        else atomicAdd(&gsum[r], double(en));
+      }
+    }
+    __syncthreads();
+    // D. the next patch's coordinates and local ids (in flight during E)
+    if (pn < stop) fetch_late();
+    // E. write back this patch
+#pragma unroll
+    for (int k = 0; k < KIT; ++k) {
+      const int ent = sent + k * EPK;
+      if (ent < cnn) {
+        const int32_t wd = words[ent];
+        const int col = sc * NR + scc;
+        V v;
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) v.v[t] = T(F[ent * W + sq + t]);
+        if (wd < 0) {
+          *reinterpret_cast<V*>(stage + size_t(slots[ent]) * W + col) = v;
+        } else {
+          V* yp = reinterpret_cast<V*>(y + size_t(wd & kIdxMask) * W + col);
+          const bool fixed = bc && ((wd >> (kIdxBits + sc)) & 1);
+          if (add) {
+            if (!fixed) {
+              V o = *yp;
+#pragma unroll
+              for (int t = 0; t < VEC; ++t) o.v[t] += v.v[t];
+              *yp = o;
+            }
+          } else {
+            if (fixed) {
+#pragma unroll
+              for (int t = 0; t < VEC; ++t) v.v[t] = T(0);
+            }
+            *yp = v;
+          }
+        }
+      }
+    }
+    __syncthreads();  // words, slots, geometry and F are refilled by the next patch
+  }
+  if constexpr (kLaneCase) {
+    if (gamma) {
+#pragma unroll
+      for (int off = 32; off >= NR; off >>= 1) en_acc += __shfl_xor(en_acc, off, 64);
+      if ((tid & 63) < NR) atomicAdd(&gsum[tid & 63], en_acc);
+    }
   }
   __syncthreads();
-  if (tid < NR) unsafeAtomicAdd(gamma + tid, gsum[tid]);
-  if (tid == 0) atomicExch(gcount, 0u);
+  if (gamma) fold_gamma<NR, TPB>(gsum, gamma, gslot, gcount);
 }
 
 // y[shared node] (=|+=) sum of its consecutive staged partials (patch order).
@@ -423,6 +668,34 @@ void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y
                      gate);
 }
 
+// Pipelined form: as many persistent workgroups as fit on the device at once
+// (measured occupancy x CUs), at most one per patch.
+template <typename T, int NR, int ORDER>
+void launch_patch_pipe(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool mask_in,
+                       bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
+  using P = typename Pair<T>::type;
+  constexpr int TPB = threads_for(NR, ORDER, int(sizeof(T)), false);
+  static const int per_cu = [] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ebe_patch_pipe<T, NR, ORDER>, TPB, 0) != hipSuccess ||
+        n < 1)
+      n = 1;
+    return n;
+  }();
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess || cus < 1)
+    cus = 256;
+  const int64_t grid = std::min<int64_t>(L.npatch, int64_t(per_cu) * cus);
+  const P* lame = (sizeof(T) == 8) ? reinterpret_cast<const P*>(m->lame64.as<void>())
+                                   : reinterpret_cast<const P*>(m->lame32.as<void>());
+  hipLaunchKernelGGL((k_ebe_patch_pipe<T, NR, ORDER>), dim3(unsigned(grid)), dim3(TPB), 0, s, m->conn.as<int32_t>(),
+                     ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(), L.pelem.as<int32_t>(),
+                     L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(), m->xv.as<double4>(), lame,
+                     static_cast<const T*>(x), static_cast<T*>(y), stage, int(L.npatch), int(mask_in), int(bc),
+                     int(add), gamma, m->gacc.as<double>(),
+                     reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64), gate);
+}
+
 template <typename T, int NR>
 hipError_t ebe_dispatch_p(int order, int form, const ebe_mesh* m, const void* x, void* y, bool mask_in, bool bc,
                           bool add, const int* gate, hipStream_t s, double* gamma) {
@@ -430,9 +703,13 @@ hipError_t ebe_dispatch_p(int order, int form, const ebe_mesh* m, const void* x,
   T* stage = L.stage.as<T>();
   if (order == 2) {
     if (form == EBE_FORM_STAGED) launch_patch<T, NR, 2, true>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
+    else if (form == EBE_FORM_PIPELINED)
+      launch_patch_pipe<T, NR, 2>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
     else launch_patch<T, NR, 2, false>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
   } else {
     if (form == EBE_FORM_STAGED) launch_patch<T, NR, 1, true>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
+    else if (form == EBE_FORM_PIPELINED)
+      launch_patch_pipe<T, NR, 1>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
     else launch_patch<T, NR, 1, false>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
   }
   hipError_t e = hipGetLastError();
@@ -476,9 +753,8 @@ ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes) {
 
 int product_form(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs) {
   const int f = m->form[order == 2 ? 0 : 1][dt == EBE_F64 ? 0 : 1][nrhs];
-  if (f == EBE_FORM_GATHER || f == EBE_FORM_STAGED) return f;
-  // untuned: the form measured faster on the reference workloads
-  return dt == EBE_F64 && order == 2 ? EBE_FORM_STAGED : EBE_FORM_GATHER;
+  if (f >= 0 && f < EBE_NUM_FORMS) return f;
+  return EBE_FORM_GATHER;  // untuned: the form measured fastest on the reference workloads
 }
 
 hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt, int nrhs, const void* x, void* y,
@@ -486,7 +762,7 @@ hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt,
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   const size_t need = size_t(L.nslots) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4);
   if (L.stage.bytes() < need || L.npatch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS ||
-      (form != EBE_FORM_GATHER && form != EBE_FORM_STAGED))
+      form < 0 || form >= EBE_NUM_FORMS)
     return hipErrorInvalidValue;  // staging not sized or bad form: host bug
   return dt == EBE_F64 ? ebe_dispatch<double>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma)
                        : ebe_dispatch<float>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma);

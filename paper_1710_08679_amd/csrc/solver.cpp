@@ -280,7 +280,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
     const Tune& k = tunes[t];
     if (m->form[k.level][k.dt == EBE_F64 ? 0 : 1][nr] != EBE_FORM_AUTO) continue;
     EBE_K(launch_fill_zero(k.x, k.bytes, s));
-    double ms[2];
+    double ms[EBE_NUM_FORMS];
     if ((st_ = tune_product(m, k.level, k.dt, nr, k.x, k.y, s, ms)) != EBE_OK) return st_;
   }
 

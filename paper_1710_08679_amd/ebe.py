@@ -22,7 +22,8 @@ F64, F32 = 0, 1
 PREC_PCGE, PREC_MG2 = 0, 1
 MODE_FP64, MODE_MIXED = 0, 1
 MAX_RHS = 16
-FORM_AUTO, FORM_GATHER, FORM_STAGED = -1, 0, 1
+FORM_AUTO, FORM_GATHER, FORM_STAGED, FORM_PIPELINED = -1, 0, 1, 2
+NUM_FORMS = 3
 
 EXPORTED = (
     "ebe_mesh_create", "ebe_mesh_set_material", "ebe_mesh_info", "ebe_mesh_destroy", "ebe_matvec",
@@ -233,11 +234,11 @@ class Mesh:
         return out
 
     def autotune(self, level, dtype, nrhs, stream=None):
-        """Time both product forms for (level, dtype, nrhs) and keep the faster;
-        returns (gather ms, staged ms)."""
-        ms = (ctypes.c_double * 2)()
+        """Time every product form for (level, dtype, nrhs) and keep the fastest;
+        returns the times in ms, indexed by form."""
+        ms = (ctypes.c_double * NUM_FORMS)()
         _check(load().ebe_autotune(self.handle, int(level), _dtype_code(dtype), int(nrhs), _stream(stream), ms))
-        return float(ms[0]), float(ms[1])
+        return tuple(float(v) for v in ms)
 
     def set_form(self, level, dtype, nrhs, form):
         _check(load().ebe_set_product_form(self.handle, int(level), _dtype_code(dtype), int(nrhs), int(form)))

@@ -30,7 +30,7 @@ def small(gpu_lib):
     return m, ebe.Mesh.from_generated(m), oracle_K(m), oracle_K(m, order=1), kappa_max(m)
 
 
-FORMS = [ebe.FORM_GATHER, ebe.FORM_STAGED]
+FORMS = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED]
 
 
 class forced_form:
@@ -92,11 +92,10 @@ def test_linear_matvec_matches_oracle(small, dtype, form):
 def test_autotune_keeps_the_faster_form(small):
     m, gm, K, _, kap = small
     for level, nrhs in ((0, 4), (1, 16)):
-        t_gather, t_staged = gm.autotune(level, torch.float32, nrhs)
-        print(f"[autotune level {level} n={nrhs}] gather {t_gather:.4f} ms, staged {t_staged:.4f} ms", flush=True)
-        assert t_gather > 0 and t_staged > 0
-        want = ebe.FORM_STAGED if t_staged < t_gather else ebe.FORM_GATHER
-        assert gm.form(level, torch.float32, nrhs) == want
+        ts = gm.autotune(level, torch.float32, nrhs)
+        print(f"[autotune level {level} n={nrhs}] ms by form: {ts}", flush=True)
+        assert len(ts) == ebe.NUM_FORMS and min(ts) > 0
+        assert gm.form(level, torch.float32, nrhs) == ts.index(min(ts))
         gm.set_form(level, torch.float32, nrhs, ebe.FORM_AUTO)
     with pytest.raises(ebe.EbeError):
         gm.set_form(0, torch.float32, 4, 7)

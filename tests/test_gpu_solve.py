@@ -56,7 +56,7 @@ def crust(gpu_lib):
     return m, ebe.Mesh.from_generated(m), f, K, solve.sparse_solve(K, f, m.fixed)
 
 
-@pytest.mark.parametrize("form", [ebe.FORM_GATHER, ebe.FORM_STAGED])
+@pytest.mark.parametrize("form", [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED])
 def test_crust_mixed_mg2_in_each_product_form(crust, form):
     """Every product of the solve (outer FP64, inner FP32 on both levels,
     each also forming (p, K p)) in one given form."""
