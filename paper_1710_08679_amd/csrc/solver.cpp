@@ -293,6 +293,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   EBE_K(launch_ebe(m, 2, EBE_F64, nr, u, b.q, false, true, false, nullptr, s));
   EBE_K(sk_outer_init(m, f, b.q, b.r, nr, o.tol, st, s));
 
+  if (!mg) EBE_K(sk_outer_z_bj(m, b.r, b.q, nr, st, s));  // first z = M^-1 r: rho (beta = 0 at iteration 0)
   SolverScalars* h = nullptr;
   ebe_status rs = read_scalars(m, s, &h);
   if (rs != EBE_OK) return rs;
@@ -321,10 +322,11 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
                           uintptr_t(o.max_outer)},
                          o.graphs != 0, s, [&]() -> ebe_status {
                            for (int c = 0; c < k; ++c) {
-                             EBE_K(sk_outer_z_bj(m, b.r, b.q, nr, st, s));  // z = M^-1 r: (z,q), (z,r), beta
-                             EBE_K(sk_outer_p_bj(m, b.r, b.p, nr, st, s));  // p <= z + beta p
-                             ebe_status r2 = product_and_update();
-                             if (r2 != EBE_OK) return r2;
+                             EBE_K(sk_outer_p_bj(m, b.r, b.p, nr, st, s));  // p <= z + beta p, z = M^-1 r
+                             // q <= K p, gamma <= (p, K p); alpha; r, u updates; next (z,q), (z,r), beta
+                             EBE_K(launch_ebe(m, 2, EBE_F64, nr, b.p, b.q, false, true, false, &st.sc->outer_active,
+                                              s, st.sc->gamma));
+                             EBE_K(sk_outer_update_z_bj(m, b.r, u, b.q, b.p, nr, o.tol, o.max_outer, st, s));
                            }
                            return EBE_OK;
                          });

@@ -265,22 +265,35 @@ __device__ __forceinline__ double inner_alpha(double rho, double gamma) {
 
 // r -= alpha q ; u += alpha p ; sums: ||r||^2   (alpha = rho / gamma per case;
 // gamma = (p, K p) was accumulated by the product that formed q)
+// WITH_Z (PCGE): also z = M^-1 r of the new residual, and the next step's
+// sums (z, q) and (z, r), while r and q are at hand (sums: ||r||^2, (z, q),
+// (z, r)); the separate z pass of the next iteration is then not needed.
+template <bool WITH_Z>
 struct BodyOuterUpdate {
   double* r;
   double* u;
   const double* q;
   const double* p;
+  const double* minv;  // WITH_Z
   const SolverScalars* sc;
   int nr;
   __device__ void operator()(int64_t node, int col, double* acc) const {
     const double a = outer_alpha(sc->rho[col], sc->gamma[col]);
+    double rv[3], qv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t i = NC_IDX(node, c, col);
-      const double rv = r[i] - a * q[i];
-      r[i] = rv;
+      qv[c] = q[i];
+      rv[c] = r[i] - a * qv[c];
+      r[i] = rv[c];
       u[i] += a * p[i];
-      acc[0] += rv * rv;
+      acc[0] += rv[c] * rv[c];
+    }
+    if constexpr (WITH_Z) {
+      double z0, z1, z2;
+      bj_apply(minv + 6 * node, rv[0], rv[1], rv[2], z0, z1, z2);
+      acc[1] += z0 * qv[0] + z1 * qv[1] + z2 * qv[2];
+      acc[2] += z0 * rv[0] + z1 * rv[1] + z2 * rv[2];
     }
   }
 };
@@ -465,6 +478,24 @@ struct EpiOuterConv {
   }
 };
 
+// EpiOuterConv followed by the next iteration's EpiOuterBeta (PCGE with the
+// z sums formed in the update): beta_{i+1} = -alpha_i (z_{i+1}, q_i) / rho_i
+// with the alpha just recorded, rho_{i+1} = (z_{i+1}, r_{i+1}).
+struct EpiOuterConvBeta {
+  EpiOuterConv conv;
+  __device__ double step(const double* tot, int nr, int j, int& flags) const {
+    const double rel = conv.step(tot, nr, j, flags);
+    SolverScalars* sc = conv.sc;
+    const double zq = tot[nr + j], zr = tot[2 * nr + j];
+    double b = sc->rho[j] != 0.0 ? -sc->alpha[j] * zq / sc->rho[j] : 0.0;
+    if (!finite_d(b)) b = 0.0;
+    sc->beta[j] = b;
+    sc->rho[j] = zr;
+    return rel;
+  }
+  __device__ void finish(double worst, int flags) const { conv.finish(worst, flags); }
+};
+
 template <typename T>
 struct EpiInnerStart {
   InnerScalars* in;
@@ -561,8 +592,15 @@ template hipError_t sk_outer_p_cast<double>(const ebe_mesh*, const double*, doub
 
 hipError_t sk_outer_update(const ebe_mesh* m, double* r, double* u, const double* q, const double* p, int nr,
                            double tol, int max_outer, SolverState& st, hipStream_t s) {
-  return run_nodecase<double, 1>(BodyOuterUpdate{r, u, q, p, st.sc, nr}, EpiOuterConv{st.sc, tol, max_outer},
-                                 m->n_nodes, nr, st, &st.sc->outer_active, s);
+  return run_nodecase<double, 1>(BodyOuterUpdate<false>{r, u, q, p, nullptr, st.sc, nr},
+                                 EpiOuterConv{st.sc, tol, max_outer}, m->n_nodes, nr, st, &st.sc->outer_active, s);
+}
+
+hipError_t sk_outer_update_z_bj(const ebe_mesh* m, double* r, double* u, const double* q, const double* p, int nr,
+                                double tol, int max_outer, SolverState& st, hipStream_t s) {
+  return run_nodecase<double, 3>(BodyOuterUpdate<true>{r, u, q, p, m->minv64[0].as<double>(), st.sc, nr},
+                                 EpiOuterConvBeta{EpiOuterConv{st.sc, tol, max_outer}}, m->n_nodes, nr, st,
+                                 &st.sc->outer_active, s);
 }
 
 template <typename T>

@@ -58,6 +58,9 @@ template <typename T>
 hipError_t sk_outer_p_cast(const ebe_mesh* m, const T* ub, double* p, int nr, SolverState& st, hipStream_t s);
 hipError_t sk_outer_update(const ebe_mesh* m, double* r, double* u, const double* q, const double* p, int nr,
                            double tol, int max_outer, SolverState& st, hipStream_t s);
+// the same, also forming the next PCGE step's z sums and beta (z = M^-1 r)
+hipError_t sk_outer_update_z_bj(const ebe_mesh* m, double* r, double* u, const double* q, const double* p, int nr,
+                                double tol, int max_outer, SolverState& st, hipStream_t s);
 template <typename T>
 hipError_t sk_cast_bj(const ebe_mesh* m, const double* r, T* rb, T* ub, int nr, SolverState& st, hipStream_t s);
 template <typename T>
