@@ -212,13 +212,22 @@ def big(gpu_lib):
     return m, ebe.Mesh.from_generated(m), kappa_max(m)
 
 
+@pytest.mark.parametrize("form", FORMS + ["tuned"])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nrhs", [1, 16])
-def test_full_size_matvec_sampled_nodes(big, dtype, nrhs):
+def test_full_size_matvec_sampled_nodes(big, dtype, nrhs, form):
+    """The 64^3 workload in every product form and in the form the autotuner
+    picks (the configuration bench.py times), on sampled nodes."""
     m, gm, kap = big
     x = meshgen.random_vectors(meshgen.rng_for(2, 10 + nrhs), m.n_nodes, nrhs)
     xd = x.astype(dtype)
-    y = gm.matvec(to_dev(xd, dtype)).cpu().numpy().astype(np.float64)
+    if form == "tuned":
+        gm.autotune(0, DT[dtype], nrhs)
+        y = gm.matvec(to_dev(xd, dtype)).cpu().numpy().astype(np.float64)
+        gm.set_form(0, DT[dtype], nrhs, ebe.FORM_AUTO)
+    else:
+        with forced_form(gm, 0, dtype, nrhs, form):
+            y = gm.matvec(to_dev(xd, dtype)).cpu().numpy().astype(np.float64)
     nodes = meshgen.rng_for(2, 50).choice(m.n_nodes, size=96, replace=False)
     nodes = np.concatenate([nodes, [0, m.n_vertices - 1, m.n_vertices, m.n_nodes - 1]])
     ref, bnd = sampled_matvec(m, xd.astype(np.float64), nodes)

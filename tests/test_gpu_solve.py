@@ -143,6 +143,36 @@ def test_graph_replays_match_eager_solves(crust, precond, mode):
             assert rel_err(ug.cpu().numpy(), ref) <= 1e-6
 
 
+def test_full_size_crust_mixed_solve(gpu_lib):
+    """The 96x96x48 crust workload (10.8M DOF, 16 cases) as bench.py solves it:
+    the FP64 residual of the mixed solution meets the tolerance, and that
+    residual agrees with the oracle's element products at sampled nodes."""
+    from tests.helpers import kappa_max, sampled_matvec, tol_factor
+    m = meshgen.crust_mesh(96, 96, 48)
+    f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(3, 2), nrhs=16)
+    gm = ebe.Mesh.from_generated(m)
+    fd = dev(f)
+    print(f"[crust 96x96x48] DOF={m.n_dof}", flush=True)
+    u, st = gm.solve(fd, precond=ebe.PREC_MG2, mode=ebe.MODE_MIXED, tol=1e-8)
+    print(f"[crust 96x96x48 mixed MG2] {st}", flush=True)
+    assert st["status"] == ebe.OK and st["max_rel_res"] <= 1e-8
+    fixed = torch.from_numpy(m.fixed.astype(bool)).cuda()
+    fb = fd.clone()
+    fb[fixed] = 0
+    r = fb - gm.matvec(u, apply_bc=True)
+    rel = (torch.linalg.vector_norm(r.reshape(-1, 16), dim=0) / torch.linalg.vector_norm(fb.reshape(-1, 16), dim=0))
+    assert float(rel.max()) <= 2e-8, rel
+    # oracle K u at sampled free nodes (and the nodes carrying the loads)
+    free = np.nonzero(~m.fixed.astype(bool).any(axis=1))[0]
+    loaded = np.unique(np.nonzero(np.abs(f).sum(axis=(1, 2)))[0])
+    nodes = np.concatenate([meshgen.rng_for(3, 90).choice(free, size=48, replace=False), loaded[:16]])
+    un = u.cpu().numpy()
+    ref, bnd = sampled_matvec(m, un, nodes)
+    Ku = gm.matvec(u).cpu().numpy()[nodes]
+    tol = tol_factor(np.float64, kappa_max(m)) * bnd
+    assert np.all(np.abs(Ku - ref) <= tol), float(np.max(np.abs(Ku - ref) / tol))
+
+
 def test_nonfinite_input_is_reported(crust):
     m, gm, f, K, ud = crust
     fb = f[:, :, :1].copy()
