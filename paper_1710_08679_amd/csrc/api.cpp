@@ -44,6 +44,16 @@ ebe_status hip_status(const char* fn, hipError_t e) {
 
 namespace ebe {
 
+ebe_status ensure_geometry(ebe_mesh* m, ebe_dtype dt, hipStream_t s) {
+  const int k = dt == EBE_F64 ? 0 : 1;
+  if (m->geo_ready[k]) return EBE_OK;
+  ebe_status st = m->geo[k].alloc(size_t(m->n_elem) * 16 * (dt == EBE_F64 ? 8 : 4));
+  if (st != EBE_OK) return st;
+  EBE_TRY_HIP(launch_geometry(m, dt, m->geo[k].as<void>(), s));
+  m->geo_ready[k] = true;
+  return EBE_OK;
+}
+
 // Form and invert the 3x3 block-Jacobi blocks of both levels (once per material).
 ebe_status ensure_blocks(ebe_mesh* m, hipStream_t s) {
   if (m->minv_ready) return EBE_OK;
@@ -73,6 +83,7 @@ ebe_status ebe_matvec(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, vo
   ebe_status st = check_common("ebe_matvec", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
   if ((st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4)) != EBE_OK) return st;
+  if ((st = ensure_geometry(m, dt, static_cast<hipStream_t>(stream))) != EBE_OK) return st;
   return hip_status("ebe_matvec", launch_ebe_p2(m, dt, nrhs, x, y, apply_bc && m->has_bc,
                                                 static_cast<hipStream_t>(stream)));
 }
@@ -82,6 +93,7 @@ ebe_status ebe_matvec_add(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x
   ebe_status st = check_common("ebe_matvec_add", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
   if ((st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4)) != EBE_OK) return st;
+  if ((st = ensure_geometry(m, dt, static_cast<hipStream_t>(stream))) != EBE_OK) return st;
   const bool bc = apply_bc && m->has_bc;
   return hip_status("ebe_matvec_add",
                     launch_ebe(m, 2, dt, nrhs, x, y, bc, bc, true, nullptr, static_cast<hipStream_t>(stream)));
@@ -92,6 +104,7 @@ ebe_status ebe_matvec_p1(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x,
   ebe_status st = check_common("ebe_matvec_p1", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
   if ((st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4)) != EBE_OK) return st;
+  if ((st = ensure_geometry(m, dt, static_cast<hipStream_t>(stream))) != EBE_OK) return st;
   return hip_status("ebe_matvec_p1", launch_ebe_p1(m, dt, nrhs, x, y, apply_bc && m->has_bc,
                                                    static_cast<hipStream_t>(stream)));
 }

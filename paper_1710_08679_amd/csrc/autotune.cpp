@@ -33,6 +33,7 @@ ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const vo
                         double ms[EBE_NUM_FORMS]) {
   const int order = level == 0 ? 2 : 1;
   ebe_status st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4);
+  if (st == EBE_OK) st = ensure_geometry(m, dt, s);
   if (st != EBE_OK) return st;
   hipEvent_t a = nullptr, b = nullptr;
   EBE_TRY_HIP(hipEventCreate(&a));

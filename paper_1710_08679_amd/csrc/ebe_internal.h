@@ -148,6 +148,10 @@ struct ebe_mesh {
   // 3x3 block Jacobi: inverted symmetric blocks (xx yy zz yz zx xy), per level
   ebe::DBuf minv64[2], minv32[2];
   bool minv_ready = false;
+  // geometry cache [E][16] per dtype (F64, F32): G, V, lambda, mu; filled on
+  // first use by an entry point, dropped when the material changes
+  ebe::DBuf geo[2];
+  bool geo_ready[2] = {false, false};
   ebe::Workspace ws;
 };
 
@@ -181,6 +185,7 @@ hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6
                                 float* inv32, hipStream_t s);
 hipError_t launch_expand_blocks(int64_t n, const double* blk6, double* out9, hipStream_t s);
 hipError_t launch_lame(const ebe_mesh* m, hipStream_t s);
+hipError_t launch_geometry(const ebe_mesh* m, ebe_dtype dt, void* out, hipStream_t s);
 hipError_t launch_check_material(const double* young, const double* poisson, int64_t n, int* bad,
                                  hipStream_t s);
 
@@ -197,6 +202,9 @@ hipError_t launch_adjoint(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void*
                           const void* lam, void* g, hipStream_t s);
 
 ebe_status ensure_blocks(ebe_mesh* m, hipStream_t s);
+// fill the geometry cache of dtype dt if needed (allocates: call before any
+// graph capture; every entry point that launches products does)
+ebe_status ensure_geometry(ebe_mesh* m, ebe_dtype dt, hipStream_t s);
 ebe_status build_patches(ebe_mesh* m, const int32_t* conn10, const uint8_t* fix, hipStream_t s);
 // grow the staging buffers for products with up to nrhs cases of the given element size
 ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes);

@@ -374,25 +374,26 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
 // patches (those of its XCD's contiguous range, in steps of the number of
 // workgroups on that XCD) and keeps the next patch's metadata in flight
 // while it computes the current one, so the chain of dependent loads (patch
-// bounds -> node words, connectivity -> coordinates, local ids) leaves the
-// critical path.  Per patch:
-//   A. commit the prefetched node words and slots to LDS, build the element
-//      geometry from the prefetched coordinates, clear F;
-//   B. issue the next patch's bounds, node words, slots, connectivity and
-//      material;
+// bounds -> node words, geometry, local ids) leaves the critical path.  The
+// element geometry comes from the mesh's geometry cache (gradients, volume,
+// lambda, mu per element, formed from the corner coordinates exactly as the
+// other forms form them), one coalesced row per element.  Per patch:
+//   A. commit the prefetched node words, slots and geometry to LDS, clear F;
+//   B. issue the next patch's bounds, node words, slots and geometry rows;
 //   C. element phase (as the gather form);
-//   D. issue the next patch's coordinates and this work-item's local ids;
+//   D. issue this work-item's local ids of the next patch;
 //   E. write back (exclusive nodes to y, shared ones to their staging slot).
 template <typename T, int NR, int ORDER>
 __global__ __launch_bounds__(threads_for(NR, ORDER, int(sizeof(T)), false))
 __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) void k_ebe_patch_pipe(
-    const int32_t* __restrict__ conn, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
+    const T* __restrict__ gcache, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
     const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
-    const double4* __restrict__ xv, const typename Pair<T>::type* __restrict__ lame, const T* __restrict__ x,
+    const T* __restrict__ x,
     T* __restrict__ y, T* __restrict__ stage, int npatch, int mask_in, int bc, int add, double* __restrict__ gamma,
     double* __restrict__ gslot, unsigned* __restrict__ gcount, const int* __restrict__ gate) {
-  using P2 = typename Pair<T>::type;
   using LW = typename std::conditional<ORDER == 2, uint4, uint32_t>::type;  // an element's local ids
+  constexpr int GV = 16 / int(sizeof(T));   // values per 16-byte piece of a geometry row
+  using GR = VecT<T, GV>;
   constexpr int NLOC = ORDER == 2 ? 10 : 4;
   constexpr int W = 3 * NR;
   constexpr int TPB = threads_for(NR, ORDER, int(sizeof(T)), false);
@@ -426,11 +427,10 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
 
   // prefetched state of patch p
   int e0 = 0, ne = 0, o0 = 0, nn = 0;
-  int pw[KW], ps[KW], pc[KE][4];
-  P2 plm[KE];
-  double4 pxv[KE][4];
+  int pw[KW], ps[KW];
+  GR pg[KE][16 / GV];
   LW pl[KI];
-  auto fetch_meta = [&](int pp) {  // bounds, node words, slots, connectivity, material of patch pp
+  auto fetch_meta = [&](int pp) {  // bounds, node words, slots, geometry rows of patch pp
     e0 = pelem[pp];
     ne = pelem[pp + 1] - e0;
     o0 = poff[pp];
@@ -445,20 +445,13 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
     for (int k = 0; k < KE; ++k) {
       const int el = tid + k * TPB;
       if (el < ne) {
-        const int64_t e = int64_t(e0) + el;
+        const GR* row = reinterpret_cast<const GR*>(gcache + (int64_t(e0) + el) * 16);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) pc[k][a] = conn[e * 10 + a] & kIdxMask;
-        plm[k] = lame[e];
+        for (int v = 0; v < 16 / GV; ++v) pg[k][v] = row[v];
       }
     }
   };
-  auto fetch_late = [&]() {  // coordinates of the prefetched connectivity, local ids of this work-item's items
-#pragma unroll
-    for (int k = 0; k < KE; ++k)
-      if (tid + k * TPB < ne) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) pxv[k][a] = xv[pc[k][a]];
-      }
+  auto fetch_late = [&]() {  // local ids of this work-item's items of the prefetched patch
     const int nj = spread_count<NR>(ne);
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
@@ -486,7 +479,18 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
 #pragma unroll
     for (int k = 0; k < KE; ++k) {
       const int el = tid + k * TPB;
-      if (el < ne) store_geometry<T, ORDER>(geo[el], pxv[k][0], pxv[k][1], pxv[k][2], pxv[k][3], plm[k]);
+      if (el < ne) {
+        T g[16];
+#pragma unroll
+        for (int v = 0; v < 16 / GV; ++v)
+#pragma unroll
+          for (int t = 0; t < GV; ++t) g[v * GV + t] = pg[k][v].v[t];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) geo[el][i] = g[i];
+        const T sv = ORDER == 2 ? g[12] * T(0.05) : g[12];  // as store_geometry
+        geo[el][12] = g[13] * sv;
+        geo[el][13] = g[14] * sv;
+      }
     }
 #pragma unroll
     for (int k = 0; k < KIT; ++k) {
@@ -549,7 +553,7 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
       }
     }
     __syncthreads();
-    // D. the next patch's coordinates and local ids (in flight during E)
+    // D. the next patch's local ids (in flight during E)
     if (pn < stop) fetch_late();
     // E. write back this patch
 #pragma unroll
@@ -673,7 +677,6 @@ void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y
 template <typename T, int NR, int ORDER>
 void launch_patch_pipe(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool mask_in,
                        bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
-  using P = typename Pair<T>::type;
   constexpr int TPB = threads_for(NR, ORDER, int(sizeof(T)), false);
   static const int per_cu = [] {
     int n = 0;
@@ -686,11 +689,10 @@ void launch_patch_pipe(const ebe_mesh* m, const PatchLevel& L, const void* x, vo
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess || cus < 1)
     cus = 256;
   const int64_t grid = std::min<int64_t>(L.npatch, int64_t(per_cu) * cus);
-  const P* lame = (sizeof(T) == 8) ? reinterpret_cast<const P*>(m->lame64.as<void>())
-                                   : reinterpret_cast<const P*>(m->lame32.as<void>());
-  hipLaunchKernelGGL((k_ebe_patch_pipe<T, NR, ORDER>), dim3(unsigned(grid)), dim3(TPB), 0, s, m->conn.as<int32_t>(),
+  hipLaunchKernelGGL((k_ebe_patch_pipe<T, NR, ORDER>), dim3(unsigned(grid)), dim3(TPB), 0, s,
+                     m->geo[sizeof(T) == 8 ? 0 : 1].as<T>(),
                      ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(), L.pelem.as<int32_t>(),
-                     L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(), m->xv.as<double4>(), lame,
+                     L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(),
                      static_cast<const T*>(x), static_cast<T*>(y), stage, int(L.npatch), int(mask_in), int(bc),
                      int(add), gamma, m->gacc.as<double>(),
                      reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64), gate);
@@ -761,9 +763,9 @@ hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt,
                            bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   const size_t need = size_t(L.nslots) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4);
-  if (L.stage.bytes() < need || L.npatch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS ||
-      form < 0 || form >= EBE_NUM_FORMS)
-    return hipErrorInvalidValue;  // staging not sized or bad form: host bug
+  if (L.stage.bytes() < need || L.npatch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS || form < 0 ||
+      form >= EBE_NUM_FORMS || (form == EBE_FORM_PIPELINED && !m->geo_ready[dt == EBE_F64 ? 0 : 1]))
+    return hipErrorInvalidValue;  // staging or geometry cache not prepared, or bad form: host bug
   return dt == EBE_F64 ? ebe_dispatch<double>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma)
                        : ebe_dispatch<float>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma);
 }

@@ -306,6 +306,7 @@ ebe_status ebe_mesh_set_material(ebe_mesh* m, const double* young_dev, const dou
   EBE_TRY_HIP(hipMemcpyAsync(m->poisson.as<void>(), poisson_dev, bytes, hipMemcpyDeviceToDevice, s));
   EBE_TRY_HIP(launch_lame(m, s));
   m->minv_ready = false;
+  m->geo_ready[0] = m->geo_ready[1] = false;
   return EBE_OK;
 }
 

@@ -149,6 +149,30 @@ __global__ __launch_bounds__(kBlock) void k_lame(const double* __restrict__ E,
   l32[i] = make_float2(float(lam), float(mu));
 }
 
+// Geometry cache row of element i: barycentric gradients G (4 x 3), volume
+// V, lambda, mu (then padding to 16 values), formed exactly as the patch
+// kernels form them from the corner coordinates.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_geometry(const int32_t* __restrict__ conn, const double4* __restrict__ xv,
+                                                     const double2* __restrict__ lame, T* __restrict__ out,
+                                                     int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  T G[4][3];
+  const T V = tet_geometry<T>(xv[conn[i * 10 + 0] & kIdxMask], xv[conn[i * 10 + 1] & kIdxMask],
+                              xv[conn[i * 10 + 2] & kIdxMask], xv[conn[i * 10 + 3] & kIdxMask], G);
+  T* o = out + i * 16;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) o[3 * k + d] = G[k][d];
+  const double2 lm = lame[i];
+  o[12] = V;
+  o[13] = T(lm.x);
+  o[14] = T(lm.y);
+  o[15] = T(0);
+}
+
 __global__ __launch_bounds__(kBlock) void k_check_material(const double* __restrict__ E,
                                                            const double* __restrict__ nu,
                                                            int* __restrict__ bad, int64_t n) {
@@ -204,6 +228,16 @@ hipError_t launch_expand_blocks(int64_t n, const double* blk6, double* out9, hip
 hipError_t launch_lame(const ebe_mesh* m, hipStream_t s) {
   hipLaunchKernelGGL(k_lame, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s, m->young.as<double>(),
                      m->poisson.as<double>(), m->lame64.as<double2>(), m->lame32.as<float2>(), m->n_elem);
+  return hipGetLastError();
+}
+
+hipError_t launch_geometry(const ebe_mesh* m, ebe_dtype dt, void* out, hipStream_t s) {
+  if (dt == EBE_F64)
+    hipLaunchKernelGGL(k_geometry<double>, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s, m->conn.as<int32_t>(),
+                       m->xv.as<double4>(), m->lame64.as<double2>(), static_cast<double*>(out), m->n_elem);
+  else
+    hipLaunchKernelGGL(k_geometry<float>, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s, m->conn.as<int32_t>(),
+                       m->xv.as<double4>(), m->lame64.as<double2>(), static_cast<float*>(out), m->n_elem);
   return hipGetLastError();
 }
 

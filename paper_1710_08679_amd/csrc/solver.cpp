@@ -254,6 +254,8 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   if ((st_ = ensure_blocks(m, s)) != EBE_OK) return st_;
   if ((st_ = ensure_stage(m, nr, sizeof(double))) != EBE_OK) return st_;
   if ((st_ = ensure_workspace(m, nr)) != EBE_OK) return st_;
+  if ((st_ = ensure_geometry(m, EBE_F64, s)) != EBE_OK) return st_;
+  if (o.mode == EBE_MODE_MIXED && (st_ = ensure_geometry(m, EBE_F32, s)) != EBE_OK) return st_;
 
   Workspace& w = m->ws;
   SolverState st;
