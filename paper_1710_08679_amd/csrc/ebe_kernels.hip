@@ -4,9 +4,11 @@
 // Work decomposition (see patches.cpp).  One workgroup per element patch
 // (quadratic level: <= 64 elements, <= 192 nodes; linear level: <= 256
 // elements, <= 128 corners):
-//   1. one work-item per element rebuilds the element geometry from the four
-//      corner coordinates and material (the element matrix is never stored,
-//      Section 2) and keeps it in LDS;
+//   1. one work-item per element puts the element geometry (gradients,
+//      volume, Lame constants: from the four corner coordinates and the
+//      material, or from the mesh's cache of exactly those values) into LDS;
+//      the element matrix itself is never stored but rebuilt from it at
+//      every product (Section 2);
 //   2. one work-item per (element, case) streams the element's nodal values
 //      through K_e (p2_element.h) and adds each nodal force into an FP64 LDS
 //      accumulator F[node][component][case] (FP32 LDS atomics are much slower
@@ -196,7 +198,8 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
     const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
     const double4* __restrict__ xv, const typename Pair<T>::type* __restrict__ lame, const T* __restrict__ x,
     T* __restrict__ y, T* __restrict__ stage, int mask_in, int bc, int add, double* __restrict__ gamma,
-    double* __restrict__ gslot, unsigned* __restrict__ gcount, const int* __restrict__ gate) {
+    double* __restrict__ gslot, unsigned* __restrict__ gcount, const int* __restrict__ gate,
+    const T* __restrict__ gcache) {
   constexpr int NLOC = ORDER == 2 ? 10 : 4;
   constexpr int CW = chunk_for(NR, ORDER, int(sizeof(T)), STAGE);  // cases per pass
   constexpr int NPASS = (NR + CW - 1) / CW;
@@ -231,6 +234,15 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
   if (tid < NR) gsum[tid] = 0.0;
   for (int el = tid; el < ne; el += TPB) {
     const int64_t e = int64_t(e0) + el;
+    if (gcache) {  // the mesh's geometry cache: one row per element, formed exactly as below
+      const T* g = gcache + e * 16;
+#pragma unroll
+      for (int i = 0; i < 12; ++i) geo[el][i] = g[i];
+      const T sv = ORDER == 2 ? g[12] * T(0.05) : g[12];
+      geo[el][12] = g[13] * sv;
+      geo[el][13] = g[14] * sv;
+      continue;
+    }
     store_geometry<T, ORDER>(geo[el], xv[conn[e * 10 + 0] & kIdxMask], xv[conn[e * 10 + 1] & kIdxMask],
                              xv[conn[e * 10 + 2] & kIdxMask], xv[conn[e * 10 + 3] & kIdxMask], lame[e]);
   }
@@ -669,7 +681,7 @@ void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y
                      L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(), m->xv.as<double4>(), lame,
                      static_cast<const T*>(x), static_cast<T*>(y), stage, int(mask_in), int(bc), int(add), gamma,
                      m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64),
-                     gate);
+                     gate, m->geo_ready[sizeof(T) == 8 ? 0 : 1] ? m->geo[sizeof(T) == 8 ? 0 : 1].as<T>() : nullptr);
 }
 
 // Pipelined form: as many persistent workgroups as fit on the device at once
