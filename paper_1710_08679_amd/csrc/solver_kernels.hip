@@ -57,9 +57,16 @@ __global__ __launch_bounds__(256) void k_nodecase(Body body, int64_t n_nodes, in
 #pragma unroll
   for (int d = 0; d < (NDOT > 0 ? NDOT : 1); ++d) acc[d] = Acc(0);
   const int64_t units = n_nodes * nr;
-  if (int(threadIdx.x) < bd)
-    for (int64_t u = int64_t(blockIdx.x) * bd + threadIdx.x; u < units; u += int64_t(gridDim.x) * bd)
-      body(u / nr, col, acc);
+  if (int(threadIdx.x) < bd) {
+    // four units per trip, so each work-item has four units' loads in flight
+    const int64_t stride = int64_t(gridDim.x) * bd;
+    int64_t u = int64_t(blockIdx.x) * bd + threadIdx.x;
+    for (; u + 3 * stride < units; u += 4 * stride) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) body((u + k * stride) / nr, col, acc);
+    }
+    for (; u < units; u += stride) body(u / nr, col, acc);
+  }
   if constexpr (NDOT > 0) {
     __shared__ Acc sh[256 * NDOT];
 #pragma unroll
