@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Published MI355X vector ALU peaks: FP32 157.3 TFLOP/s (256 CU x 4 SIMD x 16
 # lanes x 2 flop x 2.4 GHz x 2, the last factor being packed two-wide FP32
-# FMA), FP64 78.6 TFLOP/s.  This build keeps packed FP32 instructions off, so
+# FMA), FP64 78.6 TFLOP/s.  The library is compiled with packed FP32 instructions off, so
 # plain FP32 FMA peaks at 78.6 as well; both fractions are reported.
 ALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 ALU_PEAK_UNPACKED_TFLOPS = 78.6

@@ -1,6 +1,6 @@
 """Build the gfx950 HIP library ``libebe.so`` in-tree with hipcc.
 
-Usage: ``python -m paper_1710_08679_amd.build`` (or ``__graft_entry__.build()``).
+Usage: ``python -m paper_1710_08679_amd.build``.
 Every call recompiles; objects go to ``paper_1710_08679_amd/_build/``.
 """
 from __future__ import annotations
