@@ -77,16 +77,41 @@ def test_matvec_with_dirichlet_projection(small, dtype, form):
 
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_linear_matvec_matches_oracle(small, dtype, form):
+@pytest.mark.parametrize("nrhs", [4, 7, 16])
+def test_linear_matvec_matches_oracle(small, dtype, form, nrhs):
     m, gm, _, K1, kap = small
-    x = meshgen.rng_for(82, 0).standard_normal((m.n_vertices, 3, 4)).astype(dtype)
-    with forced_form(gm, 1, dtype, 4, form):
+    x = meshgen.rng_for(82, nrhs).standard_normal((m.n_vertices, 3, nrhs)).astype(dtype)
+    with forced_form(gm, 1, dtype, nrhs, form):
         y = gm.matvec_p1(to_dev(x, dtype)).cpu().numpy().astype(np.float64)
         yb = gm.matvec_p1(to_dev(x, dtype), apply_bc=True).cpu().numpy().astype(np.float64)
-    ref = (K1 @ x.astype(np.float64).reshape(-1, 4)).reshape(y.shape)
+    ref = (K1 @ x.astype(np.float64).reshape(-1, nrhs)).reshape(y.shape)
     assert_close_bound(y, ref, abs(K1), x.astype(np.float64), dtype, kap, "K1 x")
     refb = fem.matvec_bc(K1, x.astype(np.float64), m.fixed[:m.n_vertices])
     assert_close_bound(yb, refb, abs(K1), x.astype(np.float64), dtype, kap, "P K1 P x")
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("apply_bc", [False, True])
+def test_matvec_add_accumulates(small, dtype, form, apply_bc):
+    """y += K x (or P K P x): exclusive nodes add in the patch kernel, shared
+    nodes in the shared-node pass; fixed DOFs of y keep their value."""
+    m, gm, K, _, kap = small
+    x = meshgen.rng_for(84, 0).standard_normal((m.n_nodes, 3, 6)).astype(dtype)
+    y0 = meshgen.rng_for(84, 1).standard_normal((m.n_nodes, 3, 6)).astype(dtype)
+    yd = to_dev(y0, dtype)
+    with forced_form(gm, 0, dtype, 6, form):
+        gm.matvec_add(to_dev(x, dtype), yd, apply_bc=apply_bc)
+    y = yd.cpu().numpy().astype(np.float64)
+    xr = x.astype(np.float64)
+    Kx = fem.matvec_bc(K, xr, m.fixed) if apply_bc else (K @ xr.reshape(-1, 6)).reshape(y.shape)
+    ref = y0.astype(np.float64) + Kx
+    if apply_bc:
+        fixed = m.fixed.astype(bool)
+        assert np.array_equal(y[fixed], y0.astype(np.float64)[fixed])
+    u = np.finfo(dtype).eps / 2
+    bound = tol_factor(dtype, kap) * (abs(K) @ np.abs(xr).reshape(-1, 6)).reshape(y.shape) + 4 * u * np.abs(ref)
+    assert np.all(np.abs(y - ref) <= bound), float(np.max(np.abs(y - ref) / bound))
 
 
 def test_autotune_keeps_the_faster_form(small):
