@@ -134,3 +134,9 @@ def test_null_arguments_are_rejected(lib):
     assert lib.ebe_pcg_solve(None, 1, None, None, None, None, None) == ebe.ERR_ARG
     b = ctypes.c_void_p()
     assert lib.ebe_batch_create(None, 0, None, ctypes.byref(b)) == ebe.ERR_ARG
+    assert lib.ebe_autotune(None, 0, ebe.F32, 4, None, None) == ebe.ERR_ARG
+    assert lib.ebe_set_product_form(None, 0, ebe.F32, 4, ebe.FORM_GATHER) == ebe.ERR_ARG
+    f = ctypes.c_int32()
+    assert lib.ebe_get_product_form(None, 0, ebe.F32, 4, ctypes.byref(f)) == ebe.ERR_ARG
+    assert lib.ebe_batch_solve(None, None, None, None, None, None) == ebe.ERR_ARG
+    assert lib.ebe_adjoint_grad(None, ebe.F64, 1, None, None, None, None) == ebe.ERR_ARG
