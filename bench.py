@@ -141,7 +141,7 @@ def solver_block(torch, ebe, meshgen, modes=("mixed_mg2", "fp64_mg2", "fp64_pcge
     return out
 
 
-FORM_NAMES = {0: "gather", 1: "staged", 2: "pipelined"}
+FORM_NAMES = {0: "gather", 1: "staged", 2: "pipelined", 3: "assembled"}
 
 
 def batch_block(torch, ebe, meshgen, n_mesh, with_big):
@@ -232,12 +232,12 @@ def main():
         t_op = time_launches(lambda i: gm.matvec(xs[i % sets], out=ys[i % sets]), args.steps, args.warmup, torch)
         B = product_bytes(N, Nv, E, n, p)
         rec = {"dtype": name, "nrhs": n, "ms": t_op, "form": FORM_NAMES[gm.form(0, dt, n)],
-               "autotune_ms": {FORM_NAMES[f]: t for f, t in enumerate(tms)},
+               "autotune_ms": {FORM_NAMES[f]: t for f, t in enumerate(tms) if t >= 0},
                "gdof_rhs_per_s": 3 * N * n / (t_op * 1e-3) / 1e9,
                "hbm_frac": B / (t_op * 1e-3) / 1e9 / HBM_PEAK_GBS,
                "alu_frac": E * n * FLOPS_PER_ELEM_RHS / (t_op * 1e-3) / 1e12 / ALU_PEAK_TFLOPS[name]}
         variants.append(rec)
-        print(f"# {name} n={n} ({rec['form']}; tuning ms: " + " / ".join(f"{FORM_NAMES[f]} {t:.3f}" for f, t in enumerate(tms)) + "): "
+        print(f"# {name} n={n} ({rec['form']}; tuning ms: " + " / ".join(f"{FORM_NAMES[f]} {t:.3f}" for f, t in enumerate(tms) if t >= 0) + "): "
               f"{t_op:.3f} ms, {rec['gdof_rhs_per_s']:.1f} GDOF*RHS/s, "
               f"HBM {rec['hbm_frac']:.2%}, ALU {rec['alu_frac']:.2%}", file=sys.stderr, flush=True)
         del xs, ys

@@ -68,17 +68,23 @@ typedef int32_t ebe_dtype;
 #define EBE_MODE_FP64 0
 #define EBE_MODE_MIXED 1 /* preconditioner (inner loops, EBE products) in FP32 */
 
-/* Forms of the EBE product kernel (same result, different speed): GATHER
- * reads each element's nodal values straight from x; STAGED copies a patch's
- * node rows into LDS first, a few cases at a time; PIPELINED is GATHER in
- * persistent workgroups that fetch the next patch's metadata while computing
- * the current one.  AUTO: the mesh's tuned choice, else a fixed default. */
+/* Forms of the product kernel (same result up to rounding, different
+ * speed): GATHER reads each element's nodal values straight from x; STAGED
+ * copies a patch's node rows into LDS first, a few cases at a time;
+ * PIPELINED is GATHER in persistent workgroups that fetch the next patch's
+ * metadata while computing the current one; ASSEMBLED (linear level only)
+ * applies K1 assembled once (per material) into 3x3 blocks over the corner
+ * graph instead of forming element products, so a product reads each block
+ * once for all cases: a departure from the paper's element-by-element
+ * coarse level, chosen only where it measures faster.
+ * AUTO: the mesh's tuned choice, else a fixed default. */
 typedef enum {
   EBE_FORM_AUTO = -1,
   EBE_FORM_GATHER = 0,
   EBE_FORM_STAGED = 1,
   EBE_FORM_PIPELINED = 2,
-  EBE_NUM_FORMS = 3
+  EBE_FORM_ASSEMBLED = 3,
+  EBE_NUM_FORMS = 4
 } ebe_form;
 
 typedef struct ebe_mesh ebe_mesh;   /* opaque; owns device copies of the mesh and workspace */
@@ -209,13 +215,15 @@ ebe_status ebe_adjoint_grad(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const
 /* Time every product form of y = K x (level 0: quadratic mesh, level 1:
  * linear mesh) for (dtype, nrhs) on this mesh and keep the fastest for
  * every later product with these parameters; ms_out[EBE_NUM_FORMS] (or
- * NULL) receives the times in milliseconds, indexed by form.  Synchronous;
+ * NULL) receives the times in milliseconds, indexed by form, -1 for a form
+ * that does not exist at this level.  Synchronous;
  * allocates temporary vectors.  ebe_pcg_solve tunes the products it uses by
  * itself. */
 ebe_status ebe_autotune(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, void* stream,
                         double* ms_out);
 
-/* Force (EBE_FORM_GATHER / _STAGED / _PIPELINED) or reset (EBE_FORM_AUTO) the form used
+/* Force (EBE_FORM_GATHER / _STAGED / _PIPELINED, or _ASSEMBLED for level 1)
+ * or reset (EBE_FORM_AUTO) the form used
  * for (level, dtype, nrhs), and read the form that would be used. */
 ebe_status ebe_set_product_form(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, int32_t form);
 ebe_status ebe_get_product_form(const ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs,

@@ -54,6 +54,27 @@ ebe_status ensure_geometry(ebe_mesh* m, ebe_dtype dt, hipStream_t s) {
   return EBE_OK;
 }
 
+ebe_status ensure_assembled(ebe_mesh* m, ebe_dtype dt, hipStream_t s) {
+  const int k = dt == EBE_F64 ? 0 : 1;
+  if (m->k1_ready[k]) return EBE_OK;
+  const size_t n = size_t(m->k1_slots) * 9 * kSliceRows;
+  ebe_status st = m->k1_val[0].alloc(n * sizeof(double));  // FP64 values are formed first in any case
+  if (st == EBE_OK && k == 1) st = m->k1_val[1].alloc(n * sizeof(float));
+  if (st != EBE_OK) return st;
+  EBE_TRY_HIP(launch_assemble_p1(m, !m->k1_ready[0], k == 1, s));
+  m->k1_ready[0] = true;
+  m->k1_ready[k] = true;
+  return EBE_OK;
+}
+
+ebe_status prepare_products(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, hipStream_t s) {
+  ebe_status st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4);
+  if (st == EBE_OK) st = ensure_geometry(m, dt, s);
+  if (st == EBE_OK && level == 1 && product_form(m, 1, dt, nrhs) == EBE_FORM_ASSEMBLED)
+    st = ensure_assembled(m, dt, s);
+  return st;
+}
+
 // Form and invert the 3x3 block-Jacobi blocks of both levels (once per material).
 ebe_status ensure_blocks(ebe_mesh* m, hipStream_t s) {
   if (m->minv_ready) return EBE_OK;
@@ -82,8 +103,7 @@ ebe_status ebe_matvec(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, vo
                       void* stream) {
   ebe_status st = check_common("ebe_matvec", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
-  if ((st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4)) != EBE_OK) return st;
-  if ((st = ensure_geometry(m, dt, static_cast<hipStream_t>(stream))) != EBE_OK) return st;
+  if ((st = prepare_products(m, 0, dt, nrhs, static_cast<hipStream_t>(stream))) != EBE_OK) return st;
   return hip_status("ebe_matvec", launch_ebe_p2(m, dt, nrhs, x, y, apply_bc && m->has_bc,
                                                 static_cast<hipStream_t>(stream)));
 }
@@ -92,8 +112,7 @@ ebe_status ebe_matvec_add(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x
                           void* stream) {
   ebe_status st = check_common("ebe_matvec_add", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
-  if ((st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4)) != EBE_OK) return st;
-  if ((st = ensure_geometry(m, dt, static_cast<hipStream_t>(stream))) != EBE_OK) return st;
+  if ((st = prepare_products(m, 0, dt, nrhs, static_cast<hipStream_t>(stream))) != EBE_OK) return st;
   const bool bc = apply_bc && m->has_bc;
   return hip_status("ebe_matvec_add",
                     launch_ebe(m, 2, dt, nrhs, x, y, bc, bc, true, nullptr, static_cast<hipStream_t>(stream)));
@@ -103,8 +122,7 @@ ebe_status ebe_matvec_p1(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x,
                          void* stream) {
   ebe_status st = check_common("ebe_matvec_p1", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
-  if ((st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4)) != EBE_OK) return st;
-  if ((st = ensure_geometry(m, dt, static_cast<hipStream_t>(stream))) != EBE_OK) return st;
+  if ((st = prepare_products(m, 1, dt, nrhs, static_cast<hipStream_t>(stream))) != EBE_OK) return st;
   return hip_status("ebe_matvec_p1", launch_ebe_p1(m, dt, nrhs, x, y, apply_bc && m->has_bc,
                                                    static_cast<hipStream_t>(stream)));
 }

@@ -34,6 +34,7 @@ ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const vo
   const int order = level == 0 ? 2 : 1;
   ebe_status st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4);
   if (st == EBE_OK) st = ensure_geometry(m, dt, s);
+  if (st == EBE_OK && level == 1) st = ensure_assembled(m, dt, s);
   if (st != EBE_OK) return st;
   hipEvent_t a = nullptr, b = nullptr;
   EBE_TRY_HIP(hipEventCreate(&a));
@@ -41,6 +42,7 @@ ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const vo
   double best[EBE_NUM_FORMS];
   for (int f = 0; f < EBE_NUM_FORMS; ++f) best[f] = DBL_MAX;
   for (int form = 0; form < EBE_NUM_FORMS && e == hipSuccess; ++form) {
+    if (!form_available(order, form)) continue;
     e = launch_ebe_form(m, order, form, dt, nrhs, x, y, false, m->has_bc, false, nullptr, s);  // warm-up
     for (int r = 0; r < kRuns && e == hipSuccess; ++r) {
       e = hipEventRecord(a, s);
@@ -63,7 +65,7 @@ ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const vo
     if (best[f] < best[pick]) pick = f;
   m->form[level][dt == EBE_F64 ? 0 : 1][nrhs] = int8_t(pick);
   if (ms)
-    for (int f = 0; f < EBE_NUM_FORMS; ++f) ms[f] = best[f];
+    for (int f = 0; f < EBE_NUM_FORMS; ++f) ms[f] = form_available(order, f) ? best[f] : -1.0;
   return EBE_OK;
 }
 
@@ -91,8 +93,8 @@ ebe_status ebe_autotune(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, 
 
 ebe_status ebe_set_product_form(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, int32_t form) {
   if (!valid_args(m, level, dt, nrhs, "ebe_set_product_form")) return EBE_ERR_ARG;
-  if (form < EBE_FORM_AUTO || form >= EBE_NUM_FORMS) {
-    set_error("ebe_set_product_form: form %d is not EBE_FORM_AUTO or a form below EBE_NUM_FORMS", form);
+  if (form != EBE_FORM_AUTO && !form_available(level == 0 ? 2 : 1, form)) {
+    set_error("ebe_set_product_form: form %d is not EBE_FORM_AUTO or a form of level %d", form, level);
     return EBE_ERR_ARG;
   }
   m->form[level][dt == EBE_F64 ? 0 : 1][nrhs] = int8_t(form);

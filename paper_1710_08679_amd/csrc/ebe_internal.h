@@ -94,6 +94,7 @@ struct Workspace {
 #ifndef EBE_PATCH_THREADS
 #define EBE_PATCH_THREADS 512
 #endif
+constexpr int kSliceRows = 64;  // rows per slice of the assembled linear-level operator
 constexpr int kPatchElems = EBE_PATCH_ELEMS;
 constexpr int kPatchNodes = EBE_PATCH_NODES;
 constexpr int kLinPatchElems = EBE_LIN_PATCH_ELEMS;
@@ -152,6 +153,16 @@ struct ebe_mesh {
   // first use by an entry point, dropped when the material changes
   ebe::DBuf geo[2];
   bool geo_ready[2] = {false, false};
+  // assembled linear-level operator (values on demand): the 3x3 blocks of
+  // K1 over the corner graph (its edges are the quadratic mesh's edge
+  // nodes) in slices of kSliceRows rows; slice s has k1_soff[s+1] - k1_soff[s]
+  // slots (its longest row), slot j of row r at entry j * kSliceRows + r,
+  // short rows padded with zero blocks whose column is the row itself
+  ebe::DBuf k1_soff;    // int32 [nslices+1]
+  ebe::DBuf k1_col;     // int32 [slots][kSliceRows] column id | fix bits
+  ebe::DBuf k1_val[2];  // [slots][9][kSliceRows] block values row-major, per dtype (F64, F32)
+  int64_t k1_slots = 0;
+  bool k1_ready[2] = {false, false};
   ebe::Workspace ws;
 };
 
@@ -175,6 +186,8 @@ hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, cons
 hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt, int nrhs, const void* x, void* y,
                            bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma = nullptr);
 // the form launch_ebe uses for (order, dtype, nrhs)
+// form is one of the EBE_FORM_* values and exists at this order (assembled: linear only)
+bool form_available(int order, int form);
 int product_form(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs);
 // time every form of y = K x on this mesh (x, y: device vectors of the
 // level's size; y is overwritten) and record the fastest; synchronous.
@@ -186,6 +199,10 @@ hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6
 hipError_t launch_expand_blocks(int64_t n, const double* blk6, double* out9, hipStream_t s);
 hipError_t launch_lame(const ebe_mesh* m, hipStream_t s);
 hipError_t launch_geometry(const ebe_mesh* m, ebe_dtype dt, void* out, hipStream_t s);
+// K1 of the linear (corner) mesh into k1_val[0] (FP64, atomics into zeroed
+// blocks), and its FP32 copy into k1_val[1] when f32 is set
+// assemble: form the FP64 values (zeroed first); f32: copy them to the FP32 values
+hipError_t launch_assemble_p1(const ebe_mesh* m, bool assemble, bool f32, hipStream_t s);
 hipError_t launch_check_material(const double* young, const double* poisson, int64_t n, int* bad,
                                  hipStream_t s);
 
@@ -205,6 +222,11 @@ ebe_status ensure_blocks(ebe_mesh* m, hipStream_t s);
 // fill the geometry cache of dtype dt if needed (allocates: call before any
 // graph capture; every entry point that launches products does)
 ebe_status ensure_geometry(ebe_mesh* m, ebe_dtype dt, hipStream_t s);
+// build the assembled linear-level operator of dtype dt if needed (allocates)
+ebe_status ensure_assembled(ebe_mesh* m, ebe_dtype dt, hipStream_t s);
+// everything products of (level, dtype, nrhs) in their current form need:
+// staging, geometry cache, assembled operator (allocates: before any capture)
+ebe_status prepare_products(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, hipStream_t s);
 ebe_status build_patches(ebe_mesh* m, const int32_t* conn10, const uint8_t* fix, hipStream_t s);
 // grow the staging buffers for products with up to nrhs cases of the given element size
 ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes);

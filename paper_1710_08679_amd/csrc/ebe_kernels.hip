@@ -669,6 +669,182 @@ __global__ __launch_bounds__(256) void k_reduce_shared(const int32_t* __restrict
   *yp = out;
 }
 
+// Assembled linear-level form: y = K1 x with the 3x3 blocks of K1 in slices
+// of kSliceRows rows (slot j of row r at entry j * kSliceRows + r, values
+// value-major within the slot, so the rows of a wavefront read each value
+// and column word from one contiguous run).  A work-item forms the three
+// rows of block row v for CPL consecutive cases (NR / CPL work-items per
+// row, RPB rows per workgroup, rows grid-strided): a block value it reads
+// serves CPL cases and its x reads are whole vectors.  mask_in, bc, add and
+// gamma as in the patch forms; gamma takes (x_v, (K x)_v) before the
+// projection of y.
+#ifndef EBE_ASM_CPL_F32
+#define EBE_ASM_CPL_F32 4
+#endif
+#ifndef EBE_ASM_CPL_F64
+#define EBE_ASM_CPL_F64 4
+#endif
+#ifndef EBE_ASM_UNROLL_F32
+#define EBE_ASM_UNROLL_F32 4
+#endif
+#ifndef EBE_ASM_UNROLL_F64
+#define EBE_ASM_UNROLL_F64 1
+#endif
+#ifndef EBE_ASM_WG_PER_CU
+#define EBE_ASM_WG_PER_CU 8
+#endif
+template <typename T, int NR>
+constexpr int asm_cpl() {
+  int c = sizeof(T) == 4 ? EBE_ASM_CPL_F32 : EBE_ASM_CPL_F64;
+  while (c > 1 && NR % c != 0) c /= 2;
+  return c;
+}
+template <typename T, int NR>
+constexpr int asm_rows() { return 256 / (NR / asm_cpl<T, NR>()); }
+template <typename T, int NR>
+constexpr int asm_threads() { return asm_rows<T, NR>() * (NR / asm_cpl<T, NR>()); }
+
+template <typename T, int NR>
+__global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
+    const int32_t* __restrict__ soff, const int32_t* __restrict__ col, const T* __restrict__ val,
+    const uint8_t* __restrict__ fix, const T* __restrict__ x, T* __restrict__ y, int64_t nv, int mask_in, int bc,
+    int add, double* __restrict__ gamma, double* __restrict__ gslot, unsigned* __restrict__ gcount,
+    const int* __restrict__ gate) {
+  constexpr int W = 3 * NR;
+  constexpr int CPL = asm_cpl<T, NR>();
+  constexpr int LPR = NR / CPL;  // work-items per row
+  constexpr int RPB = asm_rows<T, NR>();
+  constexpr int VW = CPL * int(sizeof(T)) > 16 ? 16 / int(sizeof(T)) : CPL;  // values per (<= 16-byte) vector
+  constexpr int NVEC = CPL / VW;
+  constexpr int S = kSliceRows;
+  constexpr int U = sizeof(T) == 4 ? EBE_ASM_UNROLL_F32 : EBE_ASM_UNROLL_F64;  // slots per trip
+  using V = VecT<T, VW>;
+  __shared__ double gsum[NR];
+  if (gate && *gate == 0) return;
+  const int tid = threadIdx.x;
+  if (gamma) {
+    if (tid < NR) gsum[tid] = 0.0;
+    __syncthreads();
+  }
+  const int lr = tid / LPR;
+  const int j0 = (tid - lr * LPR) * CPL;
+  double en[CPL];
+#pragma unroll
+  for (int t = 0; t < CPL; ++t) en[t] = 0.0;
+  // chunks of RPB rows: XCD x owns a contiguous chunk range (so the x rows a
+  // chunk's neighbours share are read through one L2); its g-th workgroup
+  // takes start + g, start + g + wx, ...  Every XCD has a workgroup whenever
+  // the range is not empty (the grid is at least 8, or one per chunk).
+  const int64_t nch = (nv + RPB - 1) / RPB;
+  const int xcd = int(blockIdx.x) % kXcds;
+  const int64_t wx = (int64_t(gridDim.x) - xcd + kXcds - 1) / kXcds;
+  const int64_t cq = nch / kXcds, cr = nch % kXcds;
+  const int64_t stop = xcd * cq + (xcd < cr ? xcd : cr) + cq + (xcd < cr ? 1 : 0);
+  for (int64_t ch = stop - cq - (xcd < cr ? 1 : 0) + int64_t(blockIdx.x) / kXcds; ch < stop; ch += wx) {
+    const int64_t v = ch * RPB + lr;
+    if (v >= nv) continue;
+    const int64_t sl = v / S;
+    const int r = int(v - sl * S);
+    T acc[3][CPL];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) acc[q][t] = T(0);
+    // U slots per trip, their column words loaded one trip ahead, so a trip
+    // waits for one round of loads (x rows and values) instead of two.  Slot
+    // indices past the row are clamped to its last slot (always present: the
+    // diagonal) and their blocks skipped.
+    const int32_t kb = soff[sl], k1 = soff[sl + 1];
+    const int32_t* cp = col + r;
+    int32_t wn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) wn[u] = cp[size_t(min(kb + u, k1 - 1)) * S];
+    for (int32_t k = kb; k < k1; k += U) {
+      int32_t w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) w[u] = wn[u];
+      if (k + U < k1) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) wn[u] = cp[size_t(min(k + U + u, k1 - 1)) * S];
+      }
+      T xc[U][3][CPL];
+      T b[U][9];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const T* xp = x + size_t(uint32_t(w[u]) & uint32_t(kIdxMask)) * W + j0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+          for (int q = 0; q < NVEC; ++q) {
+            const V xv = *reinterpret_cast<const V*>(xp + c * NR + q * VW);
+#pragma unroll
+            for (int t = 0; t < VW; ++t) xc[u][c][q * VW + t] = xv.v[t];
+          }
+        }
+        const T* a = val + size_t(min(k + u, k1 - 1)) * 9 * S + r;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) b[u][i] = a[i * S];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (k + u >= k1) break;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          if (mask_in && ((w[u] >> (kIdxBits + c)) & 1)) {
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) xc[u][c][t] = T(0);
+          }
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int t = 0; t < CPL; ++t)
+            acc[q][t] += b[u][3 * q] * xc[u][0][t] + b[u][3 * q + 1] * xc[u][1][t] + b[u][3 * q + 2] * xc[u][2][t];
+      }
+    }
+    const int fb = fix[v];
+    if (gamma) {
+      const T* xo = x + size_t(v) * W + j0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const bool zero = mask_in && ((fb >> c) & 1);
+#pragma unroll
+        for (int q = 0; q < NVEC; ++q) {
+          const V xv = *reinterpret_cast<const V*>(xo + c * NR + q * VW);
+#pragma unroll
+          for (int t = 0; t < VW; ++t) en[q * VW + t] += zero ? 0.0 : double(xv.v[t]) * double(acc[c][q * VW + t]);
+        }
+      }
+    }
+    T* yp = y + size_t(v) * W + j0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const bool fixed = bc && ((fb >> c) & 1);
+#pragma unroll
+      for (int q = 0; q < NVEC; ++q) {
+        V* vp = reinterpret_cast<V*>(yp + c * NR + q * VW);
+        V o;
+        if (add) {
+          o = *vp;
+          if (!fixed) {
+#pragma unroll
+            for (int t = 0; t < VW; ++t) o.v[t] += acc[c][q * VW + t];
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < VW; ++t) o.v[t] = fixed ? T(0) : acc[c][q * VW + t];
+        }
+        *vp = o;
+      }
+    }
+  }
+  if (gamma) {
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) atomicAdd(&gsum[j0 + t], en[t]);
+    __syncthreads();
+    fold_gamma<NR, (asm_threads<T, NR>())>(gsum, gamma, gslot, gcount);
+  }
+}
+
 template <typename T, int NR, int ORDER, bool STAGE>
 void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool mask_in, bool bc,
                   bool add, const int* gate, hipStream_t s, double* gamma) {
@@ -715,6 +891,20 @@ hipError_t ebe_dispatch_p(int order, int form, const ebe_mesh* m, const void* x,
                           bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   T* stage = L.stage.as<T>();
+  if (form == EBE_FORM_ASSEMBLED) {  // linear level only (checked by the caller)
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess || cus < 1)
+      cus = 256;
+    constexpr int RPB = asm_rows<T, NR>();
+    const int64_t grid = std::max<int64_t>(
+        1, std::min<int64_t>((m->n_vertices + RPB - 1) / RPB, int64_t(EBE_ASM_WG_PER_CU) * cus));
+    hipLaunchKernelGGL((k_assembled<T, NR>), dim3(unsigned(grid)), dim3(asm_threads<T, NR>()), 0, s,
+                       m->k1_soff.as<int32_t>(), m->k1_col.as<int32_t>(), m->k1_val[sizeof(T) == 8 ? 0 : 1].as<T>(),
+                       m->fix.as<uint8_t>(), static_cast<const T*>(x), static_cast<T*>(y), m->n_vertices,
+                       int(mask_in), int(bc), int(add), gamma, m->gacc.as<double>(),
+                       reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64), gate);
+    return hipGetLastError();
+  }
   if (order == 2) {
     if (form == EBE_FORM_STAGED) launch_patch<T, NR, 2, true>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
     else if (form == EBE_FORM_PIPELINED)
@@ -765,9 +955,13 @@ ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes) {
   return EBE_OK;
 }
 
+bool form_available(int order, int form) {
+  return form >= 0 && form < EBE_NUM_FORMS && (form != EBE_FORM_ASSEMBLED || order == 1);
+}
+
 int product_form(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs) {
   const int f = m->form[order == 2 ? 0 : 1][dt == EBE_F64 ? 0 : 1][nrhs];
-  if (f >= 0 && f < EBE_NUM_FORMS) return f;
+  if (form_available(order, f)) return f;
   return EBE_FORM_GATHER;  // untuned: the form measured fastest on the reference workloads
 }
 
@@ -775,9 +969,10 @@ hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt,
                            bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   const size_t need = size_t(L.nslots) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4);
-  if (L.stage.bytes() < need || L.npatch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS || form < 0 ||
-      form >= EBE_NUM_FORMS || (form == EBE_FORM_PIPELINED && !m->geo_ready[dt == EBE_F64 ? 0 : 1]))
-    return hipErrorInvalidValue;  // staging or geometry cache not prepared, or bad form: host bug
+  const int k = dt == EBE_F64 ? 0 : 1;
+  if (L.stage.bytes() < need || L.npatch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS || !form_available(order, form) ||
+      (form == EBE_FORM_PIPELINED && !m->geo_ready[k]) || (form == EBE_FORM_ASSEMBLED && !m->k1_ready[k]))
+    return hipErrorInvalidValue;  // staging, geometry or assembled values not prepared, or bad form: host bug
   return dt == EBE_F64 ? ebe_dispatch<double>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma)
                        : ebe_dispatch<float>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma);
 }

@@ -173,6 +173,51 @@ __global__ __launch_bounds__(kBlock) void k_geometry(const int32_t* __restrict__
   o[15] = T(0);
 }
 
+// K1_e of element i added into the assembled K1: block (a, b) of the linear
+// tetrahedron is V [lambda G_a G_b^T + mu (G_a . G_b) I + mu G_b G_a^T]
+// (f_a = V sigma G_a with sigma from the constant strain; the same operator
+// p1_forces applies), found in row a by a scan of its slice's (short) slots;
+// the first match is the row's own entry, padding comes after it.
+__global__ __launch_bounds__(kBlock) void k_assemble_p1(const int32_t* __restrict__ conn, const double4* __restrict__ xv,
+                                                        const double2* __restrict__ lame,
+                                                        const int32_t* __restrict__ soff,
+                                                        const int32_t* __restrict__ col, double* __restrict__ val,
+                                                        int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int v[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) v[a] = conn[i * 10 + a] & kIdxMask;
+  double G[4][3];
+  const double V = tet_geometry<double>(xv[v[0]], xv[v[1]], xv[v[2]], xv[v[3]], G);
+  const double2 lm = lame[i];
+  const double cl = lm.x * V, cm = lm.y * V;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int sl = v[a] / kSliceRows, r = v[a] - sl * kSliceRows;
+    const int j0 = soff[sl], j1 = soff[sl + 1];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int j = j0;
+      while (j < j1 && (col[size_t(j) * kSliceRows + r] & kIdxMask) != v[b]) ++j;
+      if (j == j1) continue;  // cannot happen for a consistent structure
+      const double gg = G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2];
+      double* blk = val + size_t(j) * 9 * kSliceRows + r;
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          unsafeAtomicAdd(blk + (3 * p + q) * kSliceRows,
+                          cl * G[a][p] * G[b][q] + cm * G[a][q] * G[b][p] + (p == q ? cm * gg : 0.0));
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    b[i] = float(a[i]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_check_material(const double* __restrict__ E,
                                                            const double* __restrict__ nu,
                                                            int* __restrict__ bad, int64_t n) {
@@ -238,6 +283,25 @@ hipError_t launch_geometry(const ebe_mesh* m, ebe_dtype dt, void* out, hipStream
   else
     hipLaunchKernelGGL(k_geometry<float>, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s, m->conn.as<int32_t>(),
                        m->xv.as<double4>(), m->lame64.as<double2>(), static_cast<float*>(out), m->n_elem);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_p1(const ebe_mesh* m, bool assemble, bool f32, hipStream_t s) {
+  const int64_t nval = m->k1_slots * 9 * kSliceRows;
+  if (assemble) {
+    hipError_t e = launch_fill_zero(m->k1_val[0].as<void>(), size_t(nval) * sizeof(double), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_assemble_p1, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s, m->conn.as<int32_t>(),
+                       m->xv.as<double4>(), m->lame64.as<double2>(), m->k1_soff.as<int32_t>(),
+                       m->k1_col.as<int32_t>(), m->k1_val[0].as<double>(), m->n_elem);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (!f32) return hipSuccess;
+  int64_t g = (nval + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_to_f32, dim3(unsigned(g < 1 ? 1 : g)), dim3(kBlock), 0, s, m->k1_val[0].as<double>(),
+                     m->k1_val[1].as<float>(), nval);
   return hipGetLastError();
 }
 

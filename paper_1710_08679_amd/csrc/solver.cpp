@@ -285,6 +285,8 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
     double ms[EBE_NUM_FORMS];
     if ((st_ = tune_product(m, k.level, k.dt, nr, k.x, k.y, s, ms)) != EBE_OK) return st_;
   }
+  for (int t = 0; t < (mg ? 3 : 1); ++t)
+    if ((st_ = prepare_products(m, tunes[t].level, tunes[t].dt, nr, s)) != EBE_OK) return st_;
 
   EBE_K(launch_fill_zero(st.sc, sizeof(SolverScalars), s));
   EBE_K(launch_fill_zero(st.counter, 64, s));

@@ -22,8 +22,8 @@ F64, F32 = 0, 1
 PREC_PCGE, PREC_MG2 = 0, 1
 MODE_FP64, MODE_MIXED = 0, 1
 MAX_RHS = 16
-FORM_AUTO, FORM_GATHER, FORM_STAGED, FORM_PIPELINED = -1, 0, 1, 2
-NUM_FORMS = 3
+FORM_AUTO, FORM_GATHER, FORM_STAGED, FORM_PIPELINED, FORM_ASSEMBLED = -1, 0, 1, 2, 3
+NUM_FORMS = 4
 
 EXPORTED = (
     "ebe_mesh_create", "ebe_mesh_set_material", "ebe_mesh_info", "ebe_mesh_destroy", "ebe_matvec",
@@ -235,7 +235,8 @@ class Mesh:
 
     def autotune(self, level, dtype, nrhs, stream=None):
         """Time every product form for (level, dtype, nrhs) and keep the fastest;
-        returns the times in ms, indexed by form."""
+        returns the times in ms, indexed by form (-1: no such form at this level;
+        FORM_ASSEMBLED exists at the linear level only)."""
         ms = (ctypes.c_double * NUM_FORMS)()
         _check(load().ebe_autotune(self.handle, int(level), _dtype_code(dtype), int(nrhs), _stream(stream), ms))
         return tuple(float(v) for v in ms)
