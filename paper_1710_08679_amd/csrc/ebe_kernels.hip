@@ -185,19 +185,19 @@ __device__ void fold_gamma(double* __restrict__ gsum, double* __restrict__ gamma
   if (tid == 0) atomicExch(gcount, 0u);
 }
 
-// STAGE: the staged form (else the gather form).  mask_in: zero the fixed
+// STAGE: the staged form (else the gather form).  MASK: zero the fixed
 // DOFs of x while reading it (y = P K P x); callers whose x is already zero
-// there (the solver) skip it.  bc: zero the fixed DOFs of y.  add: y += K x
+// there (the solver) skip it, and the kernel then has no masking code.  bc: zero the fixed DOFs of y.  add: y += K x
 // instead of y = K x.  gamma (optional): gamma[r] += (x_r, K x_r) formed
 // element by element as sum_e x_eᵀ K_e x_e, which is what CG needs from
 // q = K p without a separate inner-product pass.
-template <typename T, int NR, int ORDER, bool STAGE>
+template <typename T, int NR, int ORDER, bool STAGE, bool MASK>
 __global__ __launch_bounds__(threads_for(NR, ORDER, int(sizeof(T)), STAGE))
 __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) void k_ebe_patch(
     const int32_t* __restrict__ conn, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
     const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
     const double4* __restrict__ xv, const typename Pair<T>::type* __restrict__ lame, const T* __restrict__ x,
-    T* __restrict__ y, T* __restrict__ stage, int mask_in, int bc, int add, double* __restrict__ gamma,
+    T* __restrict__ y, T* __restrict__ stage, int bc, int add, double* __restrict__ gamma,
     double* __restrict__ gslot, unsigned* __restrict__ gcount, const int* __restrict__ gate,
     const T* __restrict__ gcache) {
   constexpr int NLOC = ORDER == 2 ? 10 : 4;
@@ -272,7 +272,7 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
         if constexpr (STAGE) {
           const int32_t wd = words[ent];
           V v;
-          if (cc < cw && !(mask_in && ((wd >> (kIdxBits + c)) & 1))) {
+          if (cc < cw && !(MASK && ((wd >> (kIdxBits + c)) & 1))) {
             v = *reinterpret_cast<const V*>(x + size_t(uint32_t(wd) & uint32_t(kIdxMask)) * W + c * NR + c0 + cc);
           } else {
 #pragma unroll
@@ -321,7 +321,7 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
           return X[lid[a] + c * CW];
         } else {
           const T v = x[size_t(uint32_t(gw[a]) & uint32_t(kIdxMask)) * W + c * NR + r];
-          return (mask_in && ((gw[a] >> (kIdxBits + c)) & 1)) ? T(0) : v;
+          return (MASK && ((gw[a] >> (kIdxBits + c)) & 1)) ? T(0) : v;
         }
       };
       auto emit = [&](int a, const T f[3]) {
@@ -395,13 +395,13 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
 //   C. element phase (as the gather form);
 //   D. issue this work-item's local ids of the next patch;
 //   E. write back (exclusive nodes to y, shared ones to their staging slot).
-template <typename T, int NR, int ORDER>
+template <typename T, int NR, int ORDER, bool MASK>
 __global__ __launch_bounds__(threads_for(NR, ORDER, int(sizeof(T)), false))
 __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) void k_ebe_patch_pipe(
     const T* __restrict__ gcache, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
     const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
     const T* __restrict__ x,
-    T* __restrict__ y, T* __restrict__ stage, int npatch, int mask_in, int bc, int add, double* __restrict__ gamma,
+    T* __restrict__ y, T* __restrict__ stage, int npatch, int bc, int add, double* __restrict__ gamma,
     double* __restrict__ gslot, unsigned* __restrict__ gcount, const int* __restrict__ gate) {
   using LW = typename std::conditional<ORDER == 2, uint4, uint32_t>::type;  // an element's local ids
   constexpr int GV = 16 / int(sizeof(T));   // values per 16-byte piece of a geometry row
@@ -551,7 +551,7 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
       T en = T(0);
       auto u = [&](int a, int c) -> T {
         const T v = x[size_t(uint32_t(gw[a]) & uint32_t(kIdxMask)) * W + c * NR + r];
-        return (mask_in && ((gw[a] >> (kIdxBits + c)) & 1)) ? T(0) : v;
+        return (MASK && ((gw[a] >> (kIdxBits + c)) & 1)) ? T(0) : v;
       };
       auto emit = [&](int a, const T f[3]) {
 #pragma unroll
@@ -845,30 +845,38 @@ __global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
   }
 }
 
-template <typename T, int NR, int ORDER, bool STAGE>
-void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool mask_in, bool bc,
-                  bool add, const int* gate, hipStream_t s, double* gamma) {
+template <typename T, int NR, int ORDER, bool STAGE, bool MASK>
+void launch_patch_m(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool bc, bool add,
+                    const int* gate, hipStream_t s, double* gamma) {
   using P = typename Pair<T>::type;
   const P* lame = (sizeof(T) == 8) ? reinterpret_cast<const P*>(m->lame64.as<void>())
                                    : reinterpret_cast<const P*>(m->lame32.as<void>());
-  hipLaunchKernelGGL((k_ebe_patch<T, NR, ORDER, STAGE>), dim3(unsigned(L.npatch)),
+  hipLaunchKernelGGL((k_ebe_patch<T, NR, ORDER, STAGE, MASK>), dim3(unsigned(L.npatch)),
                      dim3(threads_for(NR, ORDER, int(sizeof(T)), STAGE)), 0, s, m->conn.as<int32_t>(),
                      ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(), L.pelem.as<int32_t>(),
                      L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(), m->xv.as<double4>(), lame,
-                     static_cast<const T*>(x), static_cast<T*>(y), stage, int(mask_in), int(bc), int(add), gamma,
+                     static_cast<const T*>(x), static_cast<T*>(y), stage, int(bc), int(add), gamma,
                      m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64),
                      gate, m->geo_ready[sizeof(T) == 8 ? 0 : 1] ? m->geo[sizeof(T) == 8 ? 0 : 1].as<T>() : nullptr);
 }
 
+template <typename T, int NR, int ORDER, bool STAGE>
+void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool mask_in, bool bc,
+                  bool add, const int* gate, hipStream_t s, double* gamma) {
+  if (mask_in) launch_patch_m<T, NR, ORDER, STAGE, true>(m, L, x, y, stage, bc, add, gate, s, gamma);
+  else launch_patch_m<T, NR, ORDER, STAGE, false>(m, L, x, y, stage, bc, add, gate, s, gamma);
+}
+
 // Pipelined form: as many persistent workgroups as fit on the device at once
 // (measured occupancy x CUs), at most one per patch.
-template <typename T, int NR, int ORDER>
-void launch_patch_pipe(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool mask_in,
-                       bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
+template <typename T, int NR, int ORDER, bool MASK>
+void launch_patch_pipe_m(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool bc,
+                         bool add, const int* gate, hipStream_t s, double* gamma) {
   constexpr int TPB = threads_for(NR, ORDER, int(sizeof(T)), false);
   static const int per_cu = [] {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ebe_patch_pipe<T, NR, ORDER>, TPB, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ebe_patch_pipe<T, NR, ORDER, MASK>, TPB, 0) !=
+            hipSuccess ||
         n < 1)
       n = 1;
     return n;
@@ -877,13 +885,19 @@ void launch_patch_pipe(const ebe_mesh* m, const PatchLevel& L, const void* x, vo
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess || cus < 1)
     cus = 256;
   const int64_t grid = std::min<int64_t>(L.npatch, int64_t(per_cu) * cus);
-  hipLaunchKernelGGL((k_ebe_patch_pipe<T, NR, ORDER>), dim3(unsigned(grid)), dim3(TPB), 0, s,
+  hipLaunchKernelGGL((k_ebe_patch_pipe<T, NR, ORDER, MASK>), dim3(unsigned(grid)), dim3(TPB), 0, s,
                      m->geo[sizeof(T) == 8 ? 0 : 1].as<T>(),
                      ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(), L.pelem.as<int32_t>(),
                      L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(),
-                     static_cast<const T*>(x), static_cast<T*>(y), stage, int(L.npatch), int(mask_in), int(bc),
-                     int(add), gamma, m->gacc.as<double>(),
-                     reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64), gate);
+                     static_cast<const T*>(x), static_cast<T*>(y), stage, int(L.npatch), int(bc), int(add), gamma,
+                     m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64), gate);
+}
+
+template <typename T, int NR, int ORDER>
+void launch_patch_pipe(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool mask_in,
+                       bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
+  if (mask_in) launch_patch_pipe_m<T, NR, ORDER, true>(m, L, x, y, stage, bc, add, gate, s, gamma);
+  else launch_patch_pipe_m<T, NR, ORDER, false>(m, L, x, y, stage, bc, add, gate, s, gamma);
 }
 
 template <typename T, int NR>
