@@ -88,7 +88,7 @@ constexpr int patch_lds_bytes(int nr, int order, bool stage) {
   const int maxn = order == 2 ? kPatchNodes : kLinPatchCorners;
   const int wc = 3 * chunk_for(nr, order, int(sizeof(T)), stage);
   return maxn * wc * 8 + (stage ? maxn * wc * int(sizeof(T)) : 0) +
-         (order == 2 ? kPatchElems : kLinPatchElems) * 14 * int(sizeof(T)) +
+         (order == 2 ? kPatchElems : kLinPatchElems) * (14 * int(sizeof(T)) + (order == 2 ? 16 : 4)) +
          8 * maxn + 8 * nr + 16;
 }
 template <typename T>
@@ -390,7 +390,8 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
 // element geometry comes from the mesh's geometry cache (gradients, volume,
 // lambda, mu per element, formed from the corner coordinates exactly as the
 // other forms form them), one coalesced row per element.  Per patch:
-//   A. commit the prefetched node words, slots and geometry to LDS, clear F;
+//   A. commit the prefetched node words, slots, geometry and local ids to LDS,
+//      clear F;
 //   B. issue the next patch's bounds, node words, slots and geometry rows;
 //   C. element phase (as the gather form);
 //   D. issue this work-item's local ids of the next patch;
@@ -422,6 +423,7 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
   using V = VecT<T, VEC>;
   __shared__ double F[MAXN * W];
   __shared__ T geo[PE][14];
+  __shared__ LW lids[PE];  // the elements' local ids (registers are the scarce resource here)
   __shared__ int32_t words[MAXN];
   __shared__ int32_t slots[MAXN];
   __shared__ double gsum[NR];
@@ -441,7 +443,7 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
   int e0 = 0, ne = 0, o0 = 0, nn = 0;
   int pw[KW], ps[KW];
   GR pg[KE][16 / GV];
-  LW pl[KI];
+  LW pl[KE];
   auto fetch_meta = [&](int pp) {  // bounds, node words, slots, geometry rows of patch pp
     e0 = pelem[pp];
     ne = pelem[pp + 1] - e0;
@@ -463,12 +465,11 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
       }
     }
   };
-  auto fetch_late = [&]() {  // local ids of this work-item's items of the prefetched patch
-    const int nj = spread_count<NR>(ne);
+  auto fetch_late = [&]() {  // local ids of this work-item's elements of the prefetched patch
 #pragma unroll
-    for (int k = 0; k < KI; ++k) {
-      const int w = tid + k * TPB, j = w / NR, el = spread_element<NR>(j, ne);
-      if (w < nj * NR && el < ne) pl[k] = *reinterpret_cast<const LW*>(lconn + (int64_t(e0) + el) * (ORDER == 2 ? 16 : 4));
+    for (int k = 0; k < KE; ++k) {
+      const int el = tid + k * TPB;
+      if (el < ne) pl[k] = *reinterpret_cast<const LW*>(lconn + (int64_t(e0) + el) * (ORDER == 2 ? 16 : 4));
     }
   };
   if (p < stop) {
@@ -502,6 +503,7 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
         const T sv = ORDER == 2 ? g[12] * T(0.05) : g[12];  // as store_geometry
         geo[el][12] = g[13] * sv;
         geo[el][13] = g[14] * sv;
+        lids[el] = pl[k];
       }
     }
 #pragma unroll
@@ -513,9 +515,6 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
       }
     }
     const int cne = ne, cnn = nn;
-    LW cl[KI];
-#pragma unroll
-    for (int k = 0; k < KI; ++k) cl[k] = pl[k];
     __syncthreads();
     // B. the next patch's metadata
     const int pn = p + wx;
@@ -529,13 +528,14 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
       const int el = spread_element<NR>(j, cne);
       if (w >= nj * NR || el >= cne) continue;
       int lid[NLOC], gw[NLOC];
+      const LW cl = lids[el];
       if constexpr (ORDER == 2) {
-        const uint32_t qw[3] = {cl[k].x, cl[k].y, cl[k].z};
+        const uint32_t qw[3] = {cl.x, cl.y, cl.z};
 #pragma unroll
         for (int a = 0; a < NLOC; ++a) lid[a] = (qw[a >> 2] >> (8 * (a & 3))) & 0xff;
       } else {
 #pragma unroll
-        for (int a = 0; a < NLOC; ++a) lid[a] = (cl[k] >> (8 * a)) & 0xff;
+        for (int a = 0; a < NLOC; ++a) lid[a] = (cl >> (8 * a)) & 0xff;
       }
 #pragma unroll
       for (int a = 0; a < NLOC; ++a) {
