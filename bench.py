@@ -290,8 +290,8 @@ def main():
     traffic = load_traffic(f"f32:16:{form}")
     roof["traffic"] = traffic
     roof["kernel"] = (f"EBE product FP32 n=16, {form} form: "
-                      + {"gather": "k_ebe_patch<float,16,2,false>", "staged": "k_ebe_patch<float,16,2,true>",
-                         "pipelined": "k_ebe_patch_pipe<float,16,2>"}[form] + " + k_reduce_shared<float,16>")
+                      + {"gather": "k_ebe_patch<float,16,2,false,false>", "staged": "k_ebe_patch<float,16,2,true,false>",
+                         "pipelined": "k_ebe_patch_pipe<float,16,2,false>"}[form] + " + k_reduce_shared<float,16>")
     roof["ms_per_launch"] = ms_events
     roof["algorithmic_bytes"] = B
     roof["algorithmic_flops"] = F
