@@ -14,6 +14,9 @@ fem      element stiffness by isoparametric B-matrix quadrature (Eq. (1), Eq. (2
          global assembly K = sum_i Q_i K_i Q_i^T (Eq. (3)), EBE product by definition.
 solve    Dirichlet elimination, dense Cholesky, sparse direct, block-Jacobi PCG,
          the paper's adaptive (flexible) CG of Algorithm 1.
+alg1     Algorithm 1 (outer flexible CG, inner CG levels 0, 1 and optionally 2).
+amg      level 2: aggregation of the corner graph, P2, A2 = P2^T K1 P2 (Section 2,
+         "inner loop level 2"; the coarsening itself is a reading, see the module).
 adjoint  misfit, adjoint solve and dL/dE_e (extension beyond the paper).
 material Lame parameters; (Vp, Vs, rho) -> (E, nu) for Table 3.
 

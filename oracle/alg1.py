@@ -1,6 +1,7 @@
 """The paper's adaptive (flexible) conjugate-gradient solver, Algorithm 1,
-restricted to the two geometric levels (second-order mesh, level 0, and the
-same mesh without edge nodes, level 1), plain NumPy/SciPy.
+on the two geometric levels (second-order mesh, level 0, and the same mesh
+without edge nodes, level 1) and optionally the algebraic level 2
+(``oracle/amg.py``), plain NumPy/SciPy.
 
 Test infrastructure only (see ``oracle/__init__.py``).
 
@@ -21,6 +22,9 @@ Readings of the text (it is garbled or silent on these points):
 * The coarse initial guess u1 <- P1^T u is literal by default ("restrict");
   "inject" takes the vertex values instead.
 * Inner loops run while i < N with i starting at 1, i.e. at most N - 1 steps.
+* Level 2 (three levels): r2 = P2^T r1 and u2 = P2^T u1 taken literally as
+  for level 1; then u1 <- P2 u2 after the level-2 solve replaces the
+  restricted u1.
 * A column whose denominators vanish is frozen (alpha = beta = 0).
 
 Iteration counts and intermediate preconditioner values are "parity
@@ -29,6 +33,7 @@ what the tests pin (against a direct solve).
 """
 import numpy as np
 
+from .amg import level2
 from .fem import assemble, prolongation_p1, apply_scalar_op
 from .solve import block_jacobi_inverse
 
@@ -92,9 +97,16 @@ def inner_cg(lv, r, u, eps, nmax):
     return u, i - 1
 
 
-def adaptive_cg(xyz, conn, n_vertices, E, nu, fixed, f, tol=1e-8, eps=(0.1, 0.05), nmax=(30, 300),
-                max_outer=5000, coarse_guess="restrict", u0=None):
-    """Algorithm 1(a) with levels 0 and 1.  Returns (u, stats dict)."""
+def _dof_op(P, v):
+    """(3 Nrow) x (3 Ncol) DOF matrix applied to (Ncol, 3, n) columns."""
+    M, _, n = v.shape
+    return (P @ v.reshape(3 * M, n)).reshape(P.shape[0] // 3, 3, n)
+
+
+def adaptive_cg(xyz, conn, n_vertices, E, nu, fixed, f, tol=1e-8, eps=(0.1, 0.05, 0.025), nmax=(30, 300, 3000),
+                max_outer=5000, coarse_guess="restrict", u0=None, levels=2):
+    """Algorithm 1(a) with levels 0 and 1 (levels=2) or 0, 1 and 2 (levels=3).
+    Returns (u, stats dict)."""
     f = np.asarray(f, dtype=np.float64)
     N, _, n = f.shape
     fixed = np.asarray(fixed).astype(bool)
@@ -104,6 +116,10 @@ def adaptive_cg(xyz, conn, n_vertices, E, nu, fixed, f, tol=1e-8, eps=(0.1, 0.05
     lv0 = _Level(K, fixed, N, np.float32)
     lv1 = _Level(K1, fixed[:n_vertices], n_vertices, np.float32)
     outer = _Level(K, fixed, N, np.float64)
+    if levels == 3:
+        _, na, P2, A2, cfx = level2(conn, n_vertices, K1, fixed)
+        lv2 = _Level(A2, cfx, na, np.float32)
+        P2 = P2.astype(np.float32)
 
     f = f.copy()
     f[fixed] = 0.0
@@ -117,7 +133,7 @@ def adaptive_cg(xyz, conn, n_vertices, E, nu, fixed, f, tol=1e-8, eps=(0.1, 0.05
     alpha = np.zeros(n)
     rho = np.ones(n)
     it = 0
-    inner = [0, 0]
+    inner = [0, 0, 0]
     while True:
         rel = _safe_div(np.sqrt(_cdot(r, r)), nf)
         if not (rel.max() > tol) or it >= max_outer:
@@ -131,6 +147,14 @@ def adaptive_cg(xyz, conn, n_vertices, E, nu, fixed, f, tol=1e-8, eps=(0.1, 0.05
         else:
             u1 = ub[:n_vertices].copy()
         u1[lv1.fx] = 0
+        if levels == 3:
+            r2 = _dof_op(P2.T, r1)
+            u2 = _dof_op(P2.T, u1)
+            r2[lv2.fx] = 0
+            u2[lv2.fx] = 0
+            u2, k2 = inner_cg(lv2, r2, u2, eps[2], nmax[2])
+            inner[2] += k2
+            u1 = _dof_op(P2, u2).astype(np.float32)
         u1, k1 = inner_cg(lv1, r1, u1, eps[1], nmax[1])
         ub = apply_scalar_op(P1, u1).astype(np.float32)
         ub[lv0.fx] = 0
@@ -150,4 +174,4 @@ def adaptive_cg(xyz, conn, n_vertices, E, nu, fixed, f, tol=1e-8, eps=(0.1, 0.05
         u = u + alpha * p
         it += 1
     rel = _safe_div(np.sqrt(_cdot(r, r)), nf)
-    return u, {"outer": it, "inner": inner, "max_rel_res": float(rel.max())}
+    return u, {"outer": it, "inner": inner[:levels], "max_rel_res": float(rel.max())}
