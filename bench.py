@@ -104,7 +104,7 @@ def cpu_baseline(mesh, n, n_elem_sample):
             "host_cpus": os.cpu_count()}
 
 
-def solver_block(torch, ebe, meshgen, modes=("mixed_mg2", "fp64_mg2", "fp64_pcge")):
+def solver_block(torch, ebe, meshgen, modes=("mixed_mg3", "mixed_mg2", "fp64_mg2", "fp64_pcge")):
     """Solves per second of the multi-case crust workload: 96x96x48 hexes x 6
     = 2,654,208 tetrahedra, 16 dislocation-pair cases, to 1e-8."""
     m = meshgen.crust_mesh(96, 96, 48)
@@ -115,7 +115,8 @@ def solver_block(torch, ebe, meshgen, modes=("mixed_mg2", "fp64_mg2", "fp64_pcge
     out = {"workload": "crust 96x96x48 hexes x 6 tets, 3 layers, 16 cases, tol 1e-8 (unsquared, max over cases)",
            "elements": m.n_elem, "dof": m.n_dof, "runs": []}
     ref = None
-    table = {"mixed_mg2": (ebe.PREC_MG2, ebe.MODE_MIXED), "fp64_mg2": (ebe.PREC_MG2, ebe.MODE_FP64),
+    table = {"mixed_mg3": (ebe.PREC_MG3, ebe.MODE_MIXED), "fp64_mg3": (ebe.PREC_MG3, ebe.MODE_FP64),
+             "mixed_mg2": (ebe.PREC_MG2, ebe.MODE_MIXED), "fp64_mg2": (ebe.PREC_MG2, ebe.MODE_FP64),
              "fp64_pcge": (ebe.PREC_PCGE, ebe.MODE_FP64)}
     for name in modes:
         precond, mode = table[name]
@@ -135,7 +136,7 @@ def solver_block(torch, ebe, meshgen, modes=("mixed_mg2", "fp64_mg2", "fp64_pcge
         if ref is None:
             ref = u.clone()
         else:
-            entry["rel_diff_vs_mixed"] = float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(u))
+            entry["rel_diff_vs_first"] = float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(u))
         out["runs"].append(entry)
         print(f"# solver {name}: {dt:.3f} s, {st}", file=sys.stderr, flush=True)
     return out
@@ -192,7 +193,7 @@ def main():
     ap.add_argument("--variants", default="f64:1,f64:4,f64:16,f32:1,f32:4,f32:16",
                     help="comma list of dtype:n products to time")
     ap.add_argument("--no-solver", action="store_true")
-    ap.add_argument("--solver-modes", default="mixed_mg2,fp64_mg2,fp64_pcge")
+    ap.add_argument("--solver-modes", default="mixed_mg3,mixed_mg2,fp64_mg2,fp64_pcge")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=100000)
     ap.add_argument("--batch", type=int, default=0, metavar="N_MESH",

@@ -63,6 +63,8 @@ typedef int32_t ebe_dtype;
 /* Preconditioner of the outer loop (Algorithm 1(a)). */
 #define EBE_PREC_PCGE 0  /* plain CG with 3x3 block Jacobi ("PCGE", Section 4) */
 #define EBE_PREC_MG2 1   /* adaptive CG: inner CG on the linear mesh, then on the quadratic mesh */
+#define EBE_PREC_MG3 2   /* adaptive CG: inner CG on the level-2 aggregates, the linear mesh, the
+                            quadratic mesh (the paper's three inner loops) */
 
 /* Arithmetic of the preconditioner; the outer loop is always FP64. */
 #define EBE_MODE_FP64 0
@@ -99,8 +101,8 @@ typedef struct {
   double tol;           /* stop when max_j ||f_j - K u_j|| / ||f_j|| <= tol (unsquared) */
   int32_t max_outer;    /* outer iteration cap */
   int32_t check_every;  /* host reads the device convergence flag every k outer iterations */
-  double inner_eps[2];  /* squared relative-residual tolerance of inner level 0 and level 1 */
-  int32_t inner_max[2]; /* inner loops run while i < N, i from 1: at most N-1 steps */
+  double inner_eps[3];  /* squared relative-residual tolerance of inner levels 0, 1, 2 (Table 2) */
+  int32_t inner_max[3]; /* inner loops run while i < N, i from 1: at most N-1 steps */
   int32_t use_x0;       /* 1: u_dev holds the initial guess on entry; 0: start from zero */
   int32_t coarse_guess; /* 0: u1 = P1^T u as printed; 1: u1 = corner values of u */
   int32_t graphs;       /* 1 (default): replay captured HIP graphs of the fixed runs of
@@ -113,7 +115,7 @@ typedef struct {
 typedef struct {
   int32_t outer_iters;
   int32_t status;          /* same as the return value of the solve */
-  int64_t inner_iters[2];  /* total inner steps on level 0 and level 1 */
+  int64_t inner_iters[3];  /* total inner steps on levels 0, 1 and 2 */
   double max_rel_res;      /* max_j ||r_j|| / ||f_j|| of the recursive residual at exit */
   double seconds;          /* wall time of the solve, host clock */
 } ebe_pcg_stats;
@@ -179,13 +181,41 @@ ebe_status ebe_restrict_p1(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const 
                            void* y_dev, int32_t apply_bc, void* stream);
 
 /* 3x3 block Jacobi of Algorithm 1 ("diag[ ]"): level 0 = quadratic K, level 1
- * = linear K1.  Blocks are the nodal 3x3 diagonal blocks of P K P with fixed
- * rows/columns set to identity, formed and inverted in FP64.
+ * = linear K1, level 2 = A2.  Blocks are the nodal 3x3 diagonal blocks of
+ * P K P with fixed rows/columns set to identity, formed and inverted in FP64.
  *   ebe_diag_blocks: writes the (uninverted) blocks, row-major [N][9] double.
  *   ebe_block_jacobi: y = M^-1 x, x/y [N][3][nrhs] of dtype. */
 ebe_status ebe_diag_blocks(ebe_mesh* mesh, int32_t level, double* blocks_dev, void* stream);
 ebe_status ebe_block_jacobi(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs,
                             const void* x_dev, void* y_dev, void* stream);
+
+/* ---- level 2: algebraic coarsening of the linear mesh ------------------- */
+
+/* Inner loop level 2 of Algorithm 1(a) runs on a coarsening of the corner
+ * mesh: corners grouped into aggregates (three greedy passes over the corner
+ * graph in increasing id: a corner whose neighbours are all free roots an
+ * aggregate of itself and its neighbours; a corner left joins the lowest
+ * neighbouring aggregate; leftovers root their own), one 3-DOF node per
+ * aggregate.  P2 copies an aggregate's value to its members' free DOFs;
+ * A2 = P2^T K1 P2, kept as 3x3 blocks (Section 2: "3 x 3 block compressed row
+ * storage"); a coarse DOF whose members are all fixed in that component is
+ * fixed.  Built with the mesh (structure) and on first use (values, per
+ * material).
+ *   ebe_level2_info: number of aggregates, and (agg_host [n_vertices] or
+ *     NULL) each corner's aggregate; synchronous.
+ *   ebe_matvec_l2: y = A2 x, x/y [n_agg][3][nrhs] of dtype (apply_bc: P A2 P).
+ *   ebe_prolong_l2: y[n_vertices] = P2 x[n_agg] (zero at fixed DOFs).
+ *   ebe_restrict_l2: y[n_agg] = P2^T x[n_vertices] (members' free DOFs
+ *     summed; zero at fixed coarse DOFs).
+ * The vector entry points are asynchronous except the first call after a
+ * material change, which forms A2 and synchronises the stream. */
+ebe_status ebe_level2_info(const ebe_mesh* mesh, int64_t* n_agg, int32_t* agg_host);
+ebe_status ebe_matvec_l2(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* x_dev, void* y_dev,
+                         int32_t apply_bc, void* stream);
+ebe_status ebe_prolong_l2(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* x_dev, void* y_dev,
+                          void* stream);
+ebe_status ebe_restrict_l2(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* x_dev, void* y_dev,
+                           void* stream);
 
 /* ---- solver ----------------------------------------------------------- */
 

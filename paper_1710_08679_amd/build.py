@@ -31,7 +31,7 @@ COMMON = [
 ]
 
 SOURCES = [
-    "mesh.cpp", "patches.cpp", "api.cpp", "solver.cpp", "batch.cpp", "autotune.cpp",
+    "mesh.cpp", "patches.cpp", "assembled.cpp", "api.cpp", "solver.cpp", "batch.cpp", "autotune.cpp",
     "ebe_kernels.hip", "setup_kernels.hip", "ebe_vec.hip", "ebe_adjoint.hip", "solver_kernels.hip",
 ]
 

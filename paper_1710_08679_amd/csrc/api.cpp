@@ -3,6 +3,8 @@
 // the kernels assume checked arguments.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ebe_internal.h"
 
 using namespace ebe;
@@ -56,14 +58,41 @@ ebe_status ensure_geometry(ebe_mesh* m, ebe_dtype dt, hipStream_t s) {
 
 ebe_status ensure_assembled(ebe_mesh* m, ebe_dtype dt, hipStream_t s) {
   const int k = dt == EBE_F64 ? 0 : 1;
-  if (m->k1_ready[k]) return EBE_OK;
-  const size_t n = size_t(m->k1_slots) * 9 * kSliceRows;
-  ebe_status st = m->k1_val[0].alloc(n * sizeof(double));  // FP64 values are formed first in any case
-  if (st == EBE_OK && k == 1) st = m->k1_val[1].alloc(n * sizeof(float));
+  if (m->k1.ready[k]) return EBE_OK;
+  const size_t n = size_t(m->k1.slots) * 9 * kSliceRows;
+  ebe_status st = m->k1.val[0].alloc(n * sizeof(double));  // FP64 values are formed first in any case
+  if (st == EBE_OK && k == 1) st = m->k1.val[1].alloc(n * sizeof(float));
   if (st != EBE_OK) return st;
-  EBE_TRY_HIP(launch_assemble_p1(m, !m->k1_ready[0], k == 1, s));
-  m->k1_ready[0] = true;
-  m->k1_ready[k] = true;
+  EBE_TRY_HIP(launch_assemble_p1(m, !m->k1.ready[0], k == 1, s));
+  m->k1.ready[0] = true;
+  m->k1.ready[k] = true;
+  return EBE_OK;
+}
+
+ebe_status ensure_level2(ebe_mesh* m, ebe_dtype dt, hipStream_t s) {
+  const int k = dt == EBE_F64 ? 0 : 1;
+  if (m->a2.ready[k]) return EBE_OK;
+  ebe_status st = ensure_assembled(m, EBE_F64, s);  // A2 is summed from the FP64 K1 blocks
+  const size_t n = std::max<size_t>(size_t(m->a2.slots) * 9 * kSliceRows, 1);
+  if (st == EBE_OK) st = m->a2.val[0].alloc(n * sizeof(double));
+  if (st == EBE_OK && k == 1) st = m->a2.val[1].alloc(n * sizeof(float));
+  if (st != EBE_OK) return st;
+  const bool fresh = !m->a2.ready[0];
+  EBE_TRY_HIP(launch_assemble_a2(m, fresh, k == 1, s));
+  if (fresh) {  // the level-2 block Jacobi goes with the FP64 values
+    const size_t na = size_t(std::max<int64_t>(m->n_agg, 1));
+    DBuf tmp;
+    st = tmp.alloc(na * 6 * sizeof(double));
+    if (st == EBE_OK) st = m->minv64[2].alloc(na * 6 * sizeof(double));
+    if (st == EBE_OK) st = m->minv32[2].alloc(na * 6 * sizeof(float));
+    if (st != EBE_OK) return st;
+    EBE_TRY_HIP(launch_asm_diag(m->a2, tmp.as<double>(), s));
+    EBE_TRY_HIP(launch_invert_blocks(m, 2, tmp.as<double>(), m->minv64[2].as<double>(), m->minv32[2].as<float>(),
+                                     s));
+    EBE_TRY_HIP(hipStreamSynchronize(s));  // tmp is freed at scope exit
+  }
+  m->a2.ready[0] = true;
+  m->a2.ready[k] = true;
   return EBE_OK;
 }
 
@@ -143,17 +172,56 @@ ebe_status ebe_restrict_p1(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* 
                                                        static_cast<hipStream_t>(stream)));
 }
 
+ebe_status ebe_level2_info(const ebe_mesh* m, int64_t* n_agg, int32_t* agg_host) {
+  if (!m) {
+    set_error("ebe_level2_info: null mesh");
+    return EBE_ERR_ARG;
+  }
+  if (n_agg) *n_agg = m->n_agg;
+  if (agg_host)
+    EBE_TRY_HIP(hipMemcpy(agg_host, m->agg.as<void>(), size_t(m->n_vertices) * sizeof(int32_t),
+                          hipMemcpyDeviceToHost));
+  return EBE_OK;
+}
+
+ebe_status ebe_matvec_l2(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, int32_t apply_bc,
+                         void* stream) {
+  ebe_status st = check_common("ebe_matvec_l2", m, dt, nrhs, x, y);
+  if (st != EBE_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = ensure_level2(m, dt, s)) != EBE_OK) return st;
+  const bool bc = apply_bc != 0;
+  return hip_status("ebe_matvec_l2", launch_level2(m, dt, nrhs, x, y, bc, bc, false, nullptr, s));
+}
+
+ebe_status ebe_prolong_l2(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, void* stream) {
+  ebe_status st = check_common("ebe_prolong_l2", m, dt, nrhs, x, y);
+  if (st != EBE_OK) return st;
+  return hip_status("ebe_prolong_l2", launch_prolong_p2(m, dt, nrhs, x, y, static_cast<hipStream_t>(stream)));
+}
+
+ebe_status ebe_restrict_l2(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, void* stream) {
+  ebe_status st = check_common("ebe_restrict_l2", m, dt, nrhs, x, y);
+  if (st != EBE_OK) return st;
+  return hip_status("ebe_restrict_l2", launch_restrict_p2(m, dt, nrhs, x, y, static_cast<hipStream_t>(stream)));
+}
+
 ebe_status ebe_diag_blocks(ebe_mesh* m, int32_t level, double* blocks, void* stream) {
-  if (!m || !blocks || (level != 0 && level != 1)) {
-    set_error("ebe_diag_blocks: null argument or level not 0/1");
+  if (!m || !blocks || level < 0 || level > 2) {
+    set_error("ebe_diag_blocks: null argument or level not 0/1/2");
     return EBE_ERR_ARG;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  const int64_t n = level_rows(m, level);
   DBuf tmp;
-  ebe_status st = tmp.alloc(size_t(n) * 6 * sizeof(double));
+  ebe_status st = tmp.alloc(size_t(std::max<int64_t>(n, 1)) * 6 * sizeof(double));
   if (st != EBE_OK) return st;
-  EBE_TRY_HIP(launch_diag_blocks(m, level, tmp.as<double>(), s));
+  if (level == 2) {
+    if ((st = ensure_level2(m, EBE_F64, s)) != EBE_OK) return st;
+    EBE_TRY_HIP(launch_asm_diag(m->a2, tmp.as<double>(), s));
+  } else {
+    EBE_TRY_HIP(launch_diag_blocks(m, level, tmp.as<double>(), s));
+  }
   EBE_TRY_HIP(launch_expand_blocks(n, tmp.as<double>(), blocks, s));
   EBE_TRY_HIP(hipStreamSynchronize(s));
   return EBE_OK;
@@ -163,12 +231,13 @@ ebe_status ebe_block_jacobi(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nr
                             void* stream) {
   ebe_status st = check_common("ebe_block_jacobi", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
-  if (level != 0 && level != 1) {
-    set_error("ebe_block_jacobi: level %d not 0/1", level);
+  if (level < 0 || level > 2) {
+    set_error("ebe_block_jacobi: level %d not 0/1/2", level);
     return EBE_ERR_ARG;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = ensure_blocks(m, s)) != EBE_OK) return st;
+  if (level == 2 && (st = ensure_level2(m, EBE_F64, s)) != EBE_OK) return st;
   return hip_status("ebe_block_jacobi", launch_bjacobi(m, level, dt, nrhs, x, y, s));
 }
 

@@ -51,14 +51,28 @@ class DBuf {
   size_t n_ = 0;
 };
 
+// An operator assembled into 3x3 blocks, in slices of kSliceRows rows: slice
+// s has soff[s+1] - soff[s] slots (its longest row), slot j of row r is entry
+// j * kSliceRows + r; short rows are padded with zero blocks whose column is
+// the row itself.  Values value-major within a slot, so the rows of a
+// wavefront read each value from one contiguous run.
+struct AsmOp {
+  DBuf soff;    // int32 [nslices+1]
+  DBuf col;     // int32 [slots][kSliceRows] column id | fix bits
+  DBuf val[2];  // [slots][9][kSliceRows] block values (row-major 3x3), per dtype (F64, F32)
+  int64_t rows = 0, slots = 0;
+  bool ready[2] = {false, false};
+};
+
 // Solver workspace; grown to the largest nrhs seen.
 struct Workspace {
   int nrhs_cap = 0;
   // FP64 outer vectors [N][3][nrhs]
   DBuf r, p, q;
-  // preconditioner vectors (FP32 or FP64) on level 0 and level 1
+  // preconditioner vectors (FP32 or FP64) on levels 0, 1 and 2
   DBuf rb, ub, e0, p0, q0;
   DBuf r1, u1, e1, p1, q1;
+  DBuf r2, u2, e2, p2, q2;
   // per-column scalars and reduction partials
   DBuf scal;      // double scalars (see solver.cpp for the slots)
   DBuf partials;  // block partial sums
@@ -94,7 +108,7 @@ struct Workspace {
 #ifndef EBE_PATCH_THREADS
 #define EBE_PATCH_THREADS 512
 #endif
-constexpr int kSliceRows = 64;  // rows per slice of the assembled linear-level operator
+constexpr int kSliceRows = 64;  // rows per slice of an assembled operator (AsmOp)
 constexpr int kPatchElems = EBE_PATCH_ELEMS;
 constexpr int kPatchNodes = EBE_PATCH_NODES;
 constexpr int kLinPatchElems = EBE_LIN_PATCH_ELEMS;
@@ -147,26 +161,36 @@ struct ebe_mesh {
   int8_t form[2][2][EBE_MAX_RHS + 1];
   ebe_mesh() { std::memset(form, EBE_FORM_AUTO, sizeof(form)); }
   // 3x3 block Jacobi: inverted symmetric blocks (xx yy zz yz zx xy), per level
-  ebe::DBuf minv64[2], minv32[2];
+  // (levels 0 and 1 with the material; level 2 with its operator)
+  ebe::DBuf minv64[3], minv32[3];
   bool minv_ready = false;
   // geometry cache [E][16] per dtype (F64, F32): G, V, lambda, mu; filled on
   // first use by an entry point, dropped when the material changes
   ebe::DBuf geo[2];
   bool geo_ready[2] = {false, false};
-  // assembled linear-level operator (values on demand): the 3x3 blocks of
-  // K1 over the corner graph (its edges are the quadratic mesh's edge
-  // nodes) in slices of kSliceRows rows; slice s has k1_soff[s+1] - k1_soff[s]
-  // slots (its longest row), slot j of row r at entry j * kSliceRows + r,
-  // short rows padded with zero blocks whose column is the row itself
-  ebe::DBuf k1_soff;    // int32 [nslices+1]
-  ebe::DBuf k1_col;     // int32 [slots][kSliceRows] column id | fix bits
-  ebe::DBuf k1_val[2];  // [slots][9][kSliceRows] block values row-major, per dtype (F64, F32)
-  int64_t k1_slots = 0;
-  bool k1_ready[2] = {false, false};
+  // assembled linear-level operator K1 over the corner graph (its edges are
+  // the quadratic mesh's edge nodes); structure at creation, values on demand
+  ebe::AsmOp k1;
+  // level 2 (aggregation of the corner graph): aggregate of each corner,
+  // members of each aggregate (increasing), coarse fix bits (a component is
+  // fixed when it is fixed at every member), A2 = P2^T K1 P2, and for each
+  // K1 entry the A2 entry it adds into (-1: padding)
+  int64_t n_agg = 0;
+  ebe::DBuf agg;      // int32 [Nv]
+  ebe::DBuf mem_off;  // int32 [Na+1]
+  ebe::DBuf mem;      // int32 [Nv]
+  ebe::DBuf cfix;     // uint8 [Na]
+  ebe::DBuf a2_map;   // int32 [k1.slots][kSliceRows]
+  ebe::AsmOp a2;
   ebe::Workspace ws;
 };
 
 namespace ebe {
+
+// rows (nodes) of level 0 (quadratic mesh), 1 (corners) or 2 (aggregates)
+inline int64_t level_rows(const ebe_mesh* m, int level) {
+  return level == 0 ? m->n_nodes : (level == 1 ? m->n_vertices : m->n_agg);
+}
 
 // ---- kernel launchers (ebe_kernels.hip) -----------------------------------
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
@@ -180,6 +204,9 @@ hipError_t launch_ebe_p1(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* 
 // device.  gamma (optional, device [nrhs] FP64): gamma[r] += (x_r, K x_r)
 // formed element by element.  The staging buffers must have been sized by
 // ensure_stage.
+// y = A2 x at level 2 (its values must be prepared: ensure_level2)
+hipError_t launch_level2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in, bool bc,
+                         bool add, const int* gate, hipStream_t s, double* gamma = nullptr);
 hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in,
                       bool bc, bool add, const int* gate, hipStream_t s, double* gamma = nullptr);
 // the same with the product form given (0 <= form < EBE_NUM_FORMS)
@@ -199,10 +226,14 @@ hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6
 hipError_t launch_expand_blocks(int64_t n, const double* blk6, double* out9, hipStream_t s);
 hipError_t launch_lame(const ebe_mesh* m, hipStream_t s);
 hipError_t launch_geometry(const ebe_mesh* m, ebe_dtype dt, void* out, hipStream_t s);
-// K1 of the linear (corner) mesh into k1_val[0] (FP64, atomics into zeroed
-// blocks), and its FP32 copy into k1_val[1] when f32 is set
+// K1 of the linear (corner) mesh into k1.val[0] (FP64, atomics into zeroed
+// blocks), and its FP32 copy into k1.val[1] when f32 is set
 // assemble: form the FP64 values (zeroed first); f32: copy them to the FP32 values
 hipError_t launch_assemble_p1(const ebe_mesh* m, bool assemble, bool f32, hipStream_t s);
+// the same for A2 from the FP64 K1 values
+hipError_t launch_assemble_a2(const ebe_mesh* m, bool assemble, bool f32, hipStream_t s);
+// FP64 diagonal blocks of an assembled operator as 6 symmetric values per row
+hipError_t launch_asm_diag(const AsmOp& op, double* blk6, hipStream_t s);
 hipError_t launch_check_material(const double* young, const double* poisson, int64_t n, int* bad,
                                  hipStream_t s);
 
@@ -211,6 +242,9 @@ hipError_t launch_prolong(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void*
                           bool bc, hipStream_t s);
 hipError_t launch_restrict(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y,
                            bool bc, hipStream_t s);
+// level 2: y[Nv] = P2 x[Na] (zero at fixed DOFs), y[Na] = P2^T x[Nv] (zero at fixed coarse DOFs)
+hipError_t launch_prolong_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, hipStream_t s);
+hipError_t launch_restrict_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, hipStream_t s);
 hipError_t launch_bjacobi(const ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const void* x,
                           void* y, hipStream_t s);
 
@@ -228,6 +262,17 @@ ebe_status ensure_assembled(ebe_mesh* m, ebe_dtype dt, hipStream_t s);
 // staging, geometry cache, assembled operator (allocates: before any capture)
 ebe_status prepare_products(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, hipStream_t s);
 ebe_status build_patches(ebe_mesh* m, const int32_t* conn10, const uint8_t* fix, hipStream_t s);
+// ---- assembled operators (assembled.cpp) ------------------------------------
+// CSR rows (each increasing, non-empty) -> sliced layout with the columns' fix bits
+ebe_status slice_rows(const std::vector<int32_t>& ptr, const std::vector<int32_t>& col, const uint8_t* fix,
+                      std::vector<int32_t>& soff, std::vector<int32_t>& scol);
+ebe_status upload_asm(AsmOp& op, int64_t rows, const std::vector<int32_t>& soff, const std::vector<int32_t>& scol,
+                      hipStream_t s);
+// aggregation, members, coarse fix bits, A2 structure and the K1 -> A2 entry map
+ebe_status build_level2(ebe_mesh* m, const std::vector<int32_t>& bptr, const std::vector<int32_t>& bcol,
+                        const std::vector<int32_t>& k1soff, const uint8_t* fix, hipStream_t s);
+// A2 values (FP64, and FP32 when asked) and the level-2 block Jacobi (allocates)
+ebe_status ensure_level2(ebe_mesh* m, ebe_dtype dt, hipStream_t s);
 // grow the staging buffers for products with up to nrhs cases of the given element size
 ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes);
 

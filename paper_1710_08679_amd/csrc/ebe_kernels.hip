@@ -900,25 +900,31 @@ void launch_patch_pipe(const ebe_mesh* m, const PatchLevel& L, const void* x, vo
   else launch_patch_pipe_m<T, NR, ORDER, false>(m, L, x, y, stage, bc, add, gate, s, gamma);
 }
 
+// y = A x for an assembled operator whose row fix bits are `fix`
+template <typename T, int NR>
+hipError_t launch_asm_p(const ebe_mesh* m, const AsmOp& op, const uint8_t* fix, const void* x, void* y,
+                        bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess || cus < 1)
+    cus = 256;
+  constexpr int RPB = asm_rows<T, NR>();
+  const int64_t grid =
+      std::max<int64_t>(1, std::min<int64_t>((op.rows + RPB - 1) / RPB, int64_t(EBE_ASM_WG_PER_CU) * cus));
+  hipLaunchKernelGGL((k_assembled<T, NR>), dim3(unsigned(grid)), dim3(asm_threads<T, NR>()), 0, s,
+                     op.soff.as<int32_t>(), op.col.as<int32_t>(), op.val[sizeof(T) == 8 ? 0 : 1].as<T>(), fix,
+                     static_cast<const T*>(x), static_cast<T*>(y), op.rows, int(mask_in), int(bc), int(add), gamma,
+                     m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64),
+                     gate);
+  return hipGetLastError();
+}
+
 template <typename T, int NR>
 hipError_t ebe_dispatch_p(int order, int form, const ebe_mesh* m, const void* x, void* y, bool mask_in, bool bc,
                           bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   T* stage = L.stage.as<T>();
-  if (form == EBE_FORM_ASSEMBLED) {  // linear level only (checked by the caller)
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess || cus < 1)
-      cus = 256;
-    constexpr int RPB = asm_rows<T, NR>();
-    const int64_t grid = std::max<int64_t>(
-        1, std::min<int64_t>((m->n_vertices + RPB - 1) / RPB, int64_t(EBE_ASM_WG_PER_CU) * cus));
-    hipLaunchKernelGGL((k_assembled<T, NR>), dim3(unsigned(grid)), dim3(asm_threads<T, NR>()), 0, s,
-                       m->k1_soff.as<int32_t>(), m->k1_col.as<int32_t>(), m->k1_val[sizeof(T) == 8 ? 0 : 1].as<T>(),
-                       m->fix.as<uint8_t>(), static_cast<const T*>(x), static_cast<T*>(y), m->n_vertices,
-                       int(mask_in), int(bc), int(add), gamma, m->gacc.as<double>(),
-                       reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64), gate);
-    return hipGetLastError();
-  }
+  if (form == EBE_FORM_ASSEMBLED)  // linear level only (checked by the caller)
+    return launch_asm_p<T, NR>(m, m->k1, m->fix.as<uint8_t>(), x, y, mask_in, bc, add, gate, s, gamma);
   if (order == 2) {
     if (form == EBE_FORM_STAGED) launch_patch<T, NR, 2, true>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
     else if (form == EBE_FORM_PIPELINED)
@@ -985,7 +991,7 @@ hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt,
   const size_t need = size_t(L.nslots) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4);
   const int k = dt == EBE_F64 ? 0 : 1;
   if (L.stage.bytes() < need || L.npatch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS || !form_available(order, form) ||
-      (form == EBE_FORM_PIPELINED && !m->geo_ready[k]) || (form == EBE_FORM_ASSEMBLED && !m->k1_ready[k]))
+      (form == EBE_FORM_PIPELINED && !m->geo_ready[k]) || (form == EBE_FORM_ASSEMBLED && !m->k1.ready[k]))
     return hipErrorInvalidValue;  // staging, geometry or assembled values not prepared, or bad form: host bug
   return dt == EBE_F64 ? ebe_dispatch<double>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma)
                        : ebe_dispatch<float>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma);
@@ -1006,6 +1012,23 @@ hipError_t launch_ebe_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* 
 hipError_t launch_ebe_p1(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,
                          hipStream_t s) {
   return launch_ebe(m, 1, dt, nrhs, x, y, bc, bc, false, nullptr, s);
+}
+
+hipError_t launch_level2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in, bool bc,
+                         bool add, const int* gate, hipStream_t s, double* gamma) {
+  if (nrhs < 1 || nrhs > EBE_MAX_RHS || !m->a2.ready[dt == EBE_F64 ? 0 : 1] || m->n_agg < 1)
+    return hipErrorInvalidValue;  // values not prepared: host bug
+  const uint8_t* cf = m->cfix.as<uint8_t>();
+  switch (nrhs) {
+#define EBE_CASE(n)                                                                                        \
+  case n:                                                                                                  \
+    return dt == EBE_F64 ? launch_asm_p<double, n>(m, m->a2, cf, x, y, mask_in, bc, add, gate, s, gamma)  \
+                         : launch_asm_p<float, n>(m, m->a2, cf, x, y, mask_in, bc, add, gate, s, gamma);
+    EBE_CASE(1) EBE_CASE(2) EBE_CASE(3) EBE_CASE(4) EBE_CASE(5) EBE_CASE(6) EBE_CASE(7) EBE_CASE(8)
+    EBE_CASE(9) EBE_CASE(10) EBE_CASE(11) EBE_CASE(12) EBE_CASE(13) EBE_CASE(14) EBE_CASE(15) EBE_CASE(16)
+#undef EBE_CASE
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace ebe

@@ -59,6 +59,46 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t* __restrict__
   y[i] = out;
 }
 
+// Level 2 (aggregates): y[Nv] = P2 x[Na], the aggregate's value copied to
+// every member DOF that is not fixed
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_p2(const int32_t* __restrict__ agg,
+                                                       const uint8_t* __restrict__ fix,
+                                                       const T* __restrict__ x, T* __restrict__ y, int64_t nv,
+                                                       int nrhs) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t w = 3 * int64_t(nrhs);
+  if (i >= nv * w) return;
+  const int64_t v = i / w;
+  const int64_t rem = i - v * w;
+  const int c = int(rem / nrhs);
+  y[i] = ((fix[v] >> c) & 1) ? T(0) : x[int64_t(agg[v]) * w + rem];
+}
+
+// y[Na] = P2^T x[Nv]: the sum over an aggregate's members (increasing id) of
+// their free DOFs, zero at fixed coarse DOFs
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict_p2(const int32_t* __restrict__ moff,
+                                                        const int32_t* __restrict__ mem,
+                                                        const uint8_t* __restrict__ fix,
+                                                        const uint8_t* __restrict__ cfix,
+                                                        const T* __restrict__ x, T* __restrict__ y, int64_t na,
+                                                        int nrhs) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t w = 3 * int64_t(nrhs);
+  if (i >= na * w) return;
+  const int64_t a = i / w;
+  const int64_t rem = i - a * w;
+  const int c = int(rem / nrhs);
+  double acc = 0.0;
+  if (!((cfix[a] >> c) & 1))
+    for (int32_t k = moff[a]; k < moff[a + 1]; ++k) {
+      const int32_t v = mem[k];
+      if (!((fix[v] >> c) & 1)) acc += double(x[int64_t(v) * w + rem]);
+    }
+  y[i] = T(acc);
+}
+
 // y = M^-1 x with symmetric inverse blocks (xx yy zz yz zx xy)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bjacobi(const T* __restrict__ minv,
@@ -125,9 +165,35 @@ hipError_t launch_restrict(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void
   return hipGetLastError();
 }
 
+hipError_t launch_prolong_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, hipStream_t s) {
+  const unsigned g = grid_for(m->n_vertices * 3 * nrhs);
+  if (dt == EBE_F64)
+    hipLaunchKernelGGL(k_prolong_p2<double>, dim3(g), dim3(kBlock), 0, s, m->agg.as<int32_t>(),
+                       m->fix.as<uint8_t>(), static_cast<const double*>(x), static_cast<double*>(y), m->n_vertices,
+                       nrhs);
+  else
+    hipLaunchKernelGGL(k_prolong_p2<float>, dim3(g), dim3(kBlock), 0, s, m->agg.as<int32_t>(), m->fix.as<uint8_t>(),
+                       static_cast<const float*>(x), static_cast<float*>(y), m->n_vertices, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, hipStream_t s) {
+  if (m->n_agg < 1) return hipSuccess;
+  const unsigned g = grid_for(m->n_agg * 3 * nrhs);
+  if (dt == EBE_F64)
+    hipLaunchKernelGGL(k_restrict_p2<double>, dim3(g), dim3(kBlock), 0, s, m->mem_off.as<int32_t>(),
+                       m->mem.as<int32_t>(), m->fix.as<uint8_t>(), m->cfix.as<uint8_t>(),
+                       static_cast<const double*>(x), static_cast<double*>(y), m->n_agg, nrhs);
+  else
+    hipLaunchKernelGGL(k_restrict_p2<float>, dim3(g), dim3(kBlock), 0, s, m->mem_off.as<int32_t>(),
+                       m->mem.as<int32_t>(), m->fix.as<uint8_t>(), m->cfix.as<uint8_t>(),
+                       static_cast<const float*>(x), static_cast<float*>(y), m->n_agg, nrhs);
+  return hipGetLastError();
+}
+
 hipError_t launch_bjacobi(const ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const void* x, void* y,
                           hipStream_t s) {
-  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  const int64_t n = level_rows(m, level);
   const unsigned g = grid_for(n * nrhs);
   if (dt == EBE_F64)
     hipLaunchKernelGGL(k_bjacobi<double>, dim3(g), dim3(kBlock), 0, s, m->minv64[level].as<double>(),

@@ -252,27 +252,11 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
     }
     bptr[v + 1] = int32_t(bcol.size());
   }
-  // sliced layout: slice width = its longest row; padding = zero block in the row's own column
-  const int64_t nsl = (Nv + kSliceRows - 1) / kSliceRows;
-  std::vector<int32_t> soff(nsl + 1, 0);
-  for (int64_t sl = 0; sl < nsl; ++sl) {
-    int32_t width = 0;
-    for (int64_t v = sl * kSliceRows; v < std::min<int64_t>(Nv, (sl + 1) * kSliceRows); ++v)
-      width = std::max(width, bptr[v + 1] - bptr[v]);
-    if (int64_t(soff[sl]) + width >= (int64_t(1) << 31) / (9 * kSliceRows)) {
-      set_error("ebe_mesh_create: corner graph too large for 32-bit block indices");
-      return EBE_ERR_ARG;
-    }
-    soff[sl + 1] = soff[sl] + width;
-  }
-  std::vector<int32_t> scol(size_t(soff[nsl]) * kSliceRows, 0);
-  for (int64_t v = 0; v < Nv; ++v) {
-    const int64_t sl = v / kSliceRows, r = v - sl * kSliceRows;
-    const int32_t len = bptr[v + 1] - bptr[v];
-    for (int32_t j = 0; j < soff[sl + 1] - soff[sl]; ++j) {
-      const int32_t c = j < len ? bcol[bptr[v] + j] : int32_t(v);
-      scol[size_t(soff[sl] + j) * kSliceRows + r] = c | (int32_t(fix[c]) << kIdxBits);
-    }
+  // sliced layout of K1 (padding: zero blocks in the row's own column) and level 2
+  std::vector<int32_t> soff, scol;
+  {
+    const ebe_status sst = slice_rows(bptr, bcol, fix.data(), soff, scol);
+    if (sst != EBE_OK) return sst;
   }
 
   std::vector<int32_t> packed(10 * E);
@@ -305,9 +289,8 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
   if (st == EBE_OK) st = upload(m->edge_ends, ends.data(), std::max<size_t>(ends.size(), 1), s);
   if (st == EBE_OK) st = upload(m->v2e_off, off.data(), off.size(), s);
   if (st == EBE_OK) st = upload(m->v2e_idx, idx.data(), std::max<size_t>(idx.size(), 1), s);
-  if (st == EBE_OK) st = upload(m->k1_soff, soff.data(), soff.size(), s);
-  if (st == EBE_OK) st = upload(m->k1_col, scol.data(), std::max<size_t>(scol.size(), 1), s);
-  m->k1_slots = soff[nsl];
+  if (st == EBE_OK) st = upload_asm(m->k1, Nv, soff, scol, s);
+  if (st == EBE_OK) st = build_level2(m, bptr, bcol, soff, fix.data(), s);
   if (st == EBE_OK) st = m->lame64.alloc(size_t(E) * 2 * sizeof(double));
   if (st == EBE_OK) st = m->lame32.alloc(size_t(E) * 2 * sizeof(float));
   if (st == EBE_OK) st = build_patches(m, conn10, fix.data(), s);
@@ -353,7 +336,8 @@ ebe_status ebe_mesh_set_material(ebe_mesh* m, const double* young_dev, const dou
   EBE_TRY_HIP(launch_lame(m, s));
   m->minv_ready = false;
   m->geo_ready[0] = m->geo_ready[1] = false;
-  m->k1_ready[0] = m->k1_ready[1] = false;
+  m->k1.ready[0] = m->k1.ready[1] = false;
+  m->a2.ready[0] = m->a2.ready[1] = false;
   return EBE_OK;
 }
 

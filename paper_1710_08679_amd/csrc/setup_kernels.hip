@@ -213,6 +213,61 @@ __global__ __launch_bounds__(kBlock) void k_assemble_p1(const int32_t* __restric
   }
 }
 
+// A2 += the free part of every K1 block: fine row v adds block (v, b) into
+// the A2 entry map[] names, rows of fixed (v, p) and columns of fixed (b, q)
+// left out (they are outside the range of P2).
+__global__ __launch_bounds__(kBlock) void k_assemble_a2(const int32_t* __restrict__ k1soff,
+                                                        const int32_t* __restrict__ k1col,
+                                                        const double* __restrict__ k1val,
+                                                        const uint8_t* __restrict__ fix,
+                                                        const int32_t* __restrict__ map, double* __restrict__ a2val,
+                                                        int64_t nv) {
+  constexpr int S = kSliceRows;
+  const int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (v >= nv) return;
+  const int64_t sl = v / S;
+  const int r = int(v - sl * S);
+  const int fa = fix[v];
+  for (int32_t j = k1soff[sl]; j < k1soff[sl + 1]; ++j) {
+    const size_t e = size_t(j) * S + r;
+    const int32_t e2 = map[e];
+    if (e2 < 0) continue;
+    const int fb = (k1col[e] >> kIdxBits) & 7;
+    const double* src = k1val + size_t(j) * 9 * S + r;
+    double* dst = a2val + size_t(e2 / S) * 9 * S + (e2 % S);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        if (!((fa >> p) & 1) && !((fb >> q) & 1)) unsafeAtomicAdd(dst + (3 * p + q) * S, src[(3 * p + q) * S]);
+  }
+}
+
+// diagonal 3x3 blocks of an assembled operator as (xx yy zz yz zx xy)
+__global__ __launch_bounds__(kBlock) void k_asm_diag(const int32_t* __restrict__ soff,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ val, double* __restrict__ blk,
+                                                     int64_t n) {
+  constexpr int S = kSliceRows;
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int64_t sl = i / S;
+  const int r = int(i - sl * S);
+  double* b = blk + 6 * i;
+  for (int k = 0; k < 6; ++k) b[k] = 0.0;
+  for (int32_t j = soff[sl]; j < soff[sl + 1]; ++j)
+    if ((col[size_t(j) * S + r] & kIdxMask) == i) {
+      const double* v = val + size_t(j) * 9 * S + r;
+      b[0] = v[0 * S];
+      b[1] = v[4 * S];
+      b[2] = v[8 * S];
+      b[3] = v[5 * S];
+      b[4] = v[2 * S];
+      b[5] = v[1 * S];
+      return;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
     b[i] = float(a[i]);
@@ -259,9 +314,36 @@ hipError_t launch_diag_blocks(const ebe_mesh* m, int level, double* blk6, hipStr
 
 hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6, double* inv64,
                                 float* inv32, hipStream_t s) {
-  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
-  hipLaunchKernelGGL(k_invert_blocks, dim3(grid_for(n)), dim3(kBlock), 0, s, blk6, m->fix.as<uint8_t>(),
-                     inv64, inv32, n);
+  const int64_t n = level_rows(m, level);
+  const uint8_t* fx = level == 2 ? m->cfix.as<uint8_t>() : m->fix.as<uint8_t>();
+  if (n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_invert_blocks, dim3(grid_for(n)), dim3(kBlock), 0, s, blk6, fx, inv64, inv32, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_a2(const ebe_mesh* m, bool assemble, bool f32, hipStream_t s) {
+  const int64_t nval = m->a2.slots * 9 * kSliceRows;
+  if (assemble) {
+    hipError_t e = launch_fill_zero(m->a2.val[0].as<void>(), size_t(nval) * sizeof(double), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_assemble_a2, dim3(grid_for(m->n_vertices)), dim3(kBlock), 0, s, m->k1.soff.as<int32_t>(),
+                       m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(), m->fix.as<uint8_t>(),
+                       m->a2_map.as<int32_t>(), m->a2.val[0].as<double>(), m->n_vertices);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (!f32 || nval == 0) return hipSuccess;
+  int64_t g = (nval + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_to_f32, dim3(unsigned(g)), dim3(kBlock), 0, s, m->a2.val[0].as<double>(),
+                     m->a2.val[1].as<float>(), nval);
+  return hipGetLastError();
+}
+
+hipError_t launch_asm_diag(const AsmOp& op, double* blk6, hipStream_t s) {
+  if (op.rows < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_asm_diag, dim3(grid_for(op.rows)), dim3(kBlock), 0, s, op.soff.as<int32_t>(),
+                     op.col.as<int32_t>(), op.val[0].as<double>(), blk6, op.rows);
   return hipGetLastError();
 }
 
@@ -287,21 +369,21 @@ hipError_t launch_geometry(const ebe_mesh* m, ebe_dtype dt, void* out, hipStream
 }
 
 hipError_t launch_assemble_p1(const ebe_mesh* m, bool assemble, bool f32, hipStream_t s) {
-  const int64_t nval = m->k1_slots * 9 * kSliceRows;
+  const int64_t nval = m->k1.slots * 9 * kSliceRows;
   if (assemble) {
-    hipError_t e = launch_fill_zero(m->k1_val[0].as<void>(), size_t(nval) * sizeof(double), s);
+    hipError_t e = launch_fill_zero(m->k1.val[0].as<void>(), size_t(nval) * sizeof(double), s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_assemble_p1, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s, m->conn.as<int32_t>(),
-                       m->xv.as<double4>(), m->lame64.as<double2>(), m->k1_soff.as<int32_t>(),
-                       m->k1_col.as<int32_t>(), m->k1_val[0].as<double>(), m->n_elem);
+                       m->xv.as<double4>(), m->lame64.as<double2>(), m->k1.soff.as<int32_t>(),
+                       m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(), m->n_elem);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (!f32) return hipSuccess;
   int64_t g = (nval + kBlock - 1) / kBlock;
   if (g > 65536) g = 65536;
-  hipLaunchKernelGGL(k_to_f32, dim3(unsigned(g < 1 ? 1 : g)), dim3(kBlock), 0, s, m->k1_val[0].as<double>(),
-                     m->k1_val[1].as<float>(), nval);
+  hipLaunchKernelGGL(k_to_f32, dim3(unsigned(g < 1 ? 1 : g)), dim3(kBlock), 0, s, m->k1.val[0].as<double>(),
+                     m->k1.val[1].as<float>(), nval);
   return hipGetLastError();
 }
 

@@ -3,8 +3,9 @@
 //  (a) outer loop, FP64: flexible CG whose preconditioner is a rough inner
 //      solve, stopped when max_j ||r_j|| / ||f_j|| <= tol;
 //  (b) inner loops: block-Jacobi CG to a squared relative residual eps or N
-//      steps, first on the linear mesh made of the corners (level 1), then on
-//      the quadratic mesh (level 0), in FP32 (MIXED) or FP64.
+//      steps, on the aggregates of the corners (level 2, MG3 only), then on
+//      the linear mesh made of the corners (level 1), then on the quadratic
+//      mesh (level 0), in FP32 (MIXED) or FP64.
 //  PCGE (Section 4) is the outer loop with z = M^-1 r instead of lines 8-17.
 //
 // All per-case scalars live on the device (solver_kernels.hip).  The host
@@ -30,6 +31,7 @@ struct Bufs {
   double *r, *p, *q;  // outer, [N][3][n] FP64
   void *rb, *ub, *e0, *p0, *q0;  // level 0
   void *r1, *u1, *e1, *p1, *q1;  // level 1
+  void *r2, *u2, *e2, *p2, *q2;  // level 2
 };
 
 ebe_status ensure_workspace(ebe_mesh* m, int nr) {
@@ -43,6 +45,10 @@ ebe_status ensure_workspace(ebe_mesh* m, int nr) {
   DBuf* coarse[] = {&w.r1, &w.u1, &w.e1, &w.p1, &w.q1};
   for (DBuf* b : coarse)
     if ((st = b->alloc(v1)) != EBE_OK) return st;
+  const size_t v2 = size_t(std::max<int64_t>(m->n_agg, 1)) * 3 * nr * sizeof(double);
+  DBuf* agg[] = {&w.r2, &w.u2, &w.e2, &w.p2, &w.q2};
+  for (DBuf* b : agg)
+    if ((st = b->alloc(v2)) != EBE_OK) return st;
   if ((st = w.scal.alloc(sizeof(SolverScalars))) != EBE_OK) return st;
   if ((st = w.partials.alloc(size_t(kMaxBlocks) * 3 * EBE_MAX_RHS * sizeof(double))) != EBE_OK) return st;
   if ((st = w.counter.alloc(64)) != EBE_OK) return st;
@@ -131,28 +137,35 @@ uintptr_t bits_of(double v) {
 uintptr_t addr(const void* p) { return reinterpret_cast<uintptr_t>(p); }
 
 // Algorithm 1(b) on one level: approximately solve A u = r starting from u.
+// The level's operator: EBE products on levels 0 and 1, the assembled A2 on level 2.
+template <typename T>
+hipError_t level_product(const ebe_mesh* m, int level, int nr, const T* x, T* y, const int* gate, hipStream_t s,
+                         double* gamma = nullptr) {
+  // all solver vectors are kept zero on fixed DOFs, so inputs need no masking
+  if (level == 2) return launch_level2(m, dtype_of<T>(), nr, x, y, false, true, false, gate, s, gamma);
+  return launch_ebe(m, level == 0 ? 2 : 1, dtype_of<T>(), nr, x, y, false, true, false, gate, s, gamma);
+}
+
 template <typename T>
 ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int nr, double eps, int nmax,
                        bool graphs, SolverState& st, hipStream_t s) {
-  const int order = level == 0 ? 2 : 1;
   InnerScalars* din = &st.sc->inner[level];
-  // all solver vectors are kept zero on fixed DOFs, so inputs need no masking
-  EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, u, q, false, true, false, &st.sc->outer_active, s));
+  EBE_K(level_product<T>(m, level, nr, u, q, &st.sc->outer_active, s));
   EBE_K(sk_inner_init<T>(m, level, r, q, e, nr, eps, nmax, st, s));
   int enq = 0;
-  int chunk = level == 0 ? 3 : 4;
+  int chunk = level == 0 ? 3 : (level == 1 ? 4 : 8);
   while (enq < nmax - 1) {
     const int k = std::min(chunk, nmax - 1 - enq);
-    const PatchLevel& L = m->pl[level];
+    const void* data = level == 2 ? m->a2.val[sizeof(T) == 8 ? 0 : 1].as<void>() : m->pl[level].stage.as<void>();
     ebe_status rs = enqueue_steps(
         m,
         {1, uintptr_t(level), uintptr_t(k), uintptr_t(nr), sizeof(T), addr(e), addr(p), addr(q), addr(u),
-         addr(st.sc), addr(st.partials), addr(st.counter), addr(L.stage.as<void>()), addr(m->gacc.as<void>()),
+         addr(st.sc), addr(st.partials), addr(st.counter), addr(data), addr(m->gacc.as<void>()),
          addr(m->minv64[level].as<void>()), addr(m->minv32[level].as<void>()), bits_of(eps), uintptr_t(nmax)},
         graphs, s, [&]() -> ebe_status {
           for (int c = 0; c < k; ++c) {
             EBE_K(sk_inner_p<T>(m, level, e, p, q, nr, st, s));
-            EBE_K(launch_ebe(m, order, dtype_of<T>(), nr, p, q, false, true, false, &din->active, s, din->gamma));
+            EBE_K(level_product<T>(m, level, nr, p, q, &din->active, s, din->gamma));
             EBE_K(sk_inner_update<T>(m, level, e, u, q, p, nr, eps, nmax, st, s));
           }
           return EBE_OK;
@@ -163,16 +176,16 @@ ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int
     rs = read_scalars(m, s, &h);
     if (rs != EBE_OK) return rs;
     if (!h->inner[level].active) break;
-    chunk = std::min(chunk * 2, 32);
+    chunk = std::min(chunk * 2, level == 2 ? 64 : 32);
   }
   return EBE_OK;
 }
 
-// Lines 9-18 of Algorithm 1(a): z from r through both inner levels, then the
-// new search direction p from z.
+// Lines 9-18 of Algorithm 1(a): z from r through the inner levels (2 when
+// MG3), 1 and 0, then the new search direction p from z.
 template <typename T>
-ebe_status mg2_precondition(ebe_mesh* m, int nr, const ebe_pcg_opts& o, const Bufs& b, SolverState& st,
-                            hipStream_t s) {
+ebe_status mg_precondition(ebe_mesh* m, int nr, const ebe_pcg_opts& o, const Bufs& b, SolverState& st,
+                           hipStream_t s) {
   T* rb = static_cast<T*>(b.rb);
   T* ub = static_cast<T*>(b.ub);
   T* r1 = static_cast<T*>(b.r1);
@@ -184,6 +197,16 @@ ebe_status mg2_precondition(ebe_mesh* m, int nr, const ebe_pcg_opts& o, const Bu
     EBE_K(hipMemcpyAsync(u1, ub, size_t(m->n_vertices) * 3 * nr * sizeof(T), hipMemcpyDeviceToDevice, s));
   } else {
     EBE_K(launch_restrict(m, dt, nr, ub, u1, true, s));        // u1 <= P1^T u_bar
+  }
+  if (o.precond == EBE_PREC_MG3) {
+    T* r2 = static_cast<T*>(b.r2);
+    T* u2 = static_cast<T*>(b.u2);
+    EBE_K(launch_restrict_p2(m, dt, nr, r1, r2, s));           // r2 <= P2^T r1
+    EBE_K(launch_restrict_p2(m, dt, nr, u1, u2, s));           // u2 <= P2^T u1
+    ebe_status r2s = inner_solve<T>(m, 2, r2, u2, static_cast<T*>(b.e2), static_cast<T*>(b.p2),
+                                    static_cast<T*>(b.q2), nr, o.inner_eps[2], o.inner_max[2], o.graphs != 0, st, s);
+    if (r2s != EBE_OK) return r2s;
+    EBE_K(launch_prolong_p2(m, dt, nr, u2, u1, s));            // u1 <= P2 u2
   }
   ebe_status rs = inner_solve<T>(m, 1, r1, u1, static_cast<T*>(b.e1), static_cast<T*>(b.p1),
                                  static_cast<T*>(b.q1), nr, o.inner_eps[1], o.inner_max[1], o.graphs != 0, st, s);
@@ -198,10 +221,11 @@ ebe_status mg2_precondition(ebe_mesh* m, int nr, const ebe_pcg_opts& o, const Bu
 }
 
 ebe_status check_opts(const ebe_pcg_opts& o) {
-  if ((o.precond != EBE_PREC_PCGE && o.precond != EBE_PREC_MG2) ||
+  if ((o.precond != EBE_PREC_PCGE && o.precond != EBE_PREC_MG2 && o.precond != EBE_PREC_MG3) ||
       (o.mode != EBE_MODE_FP64 && o.mode != EBE_MODE_MIXED) || !(o.tol > 0.0) || o.max_outer < 1 ||
-      o.check_every < 1 || o.inner_max[0] < 1 || o.inner_max[1] < 1 || !(o.inner_eps[0] >= 0.0) ||
-      !(o.inner_eps[1] >= 0.0) || (o.coarse_guess != 0 && o.coarse_guess != 1) || (o.graphs != 0 && o.graphs != 1)) {
+      o.check_every < 1 || o.inner_max[0] < 1 || o.inner_max[1] < 1 || o.inner_max[2] < 1 ||
+      !(o.inner_eps[0] >= 0.0) || !(o.inner_eps[1] >= 0.0) || !(o.inner_eps[2] >= 0.0) ||
+      (o.coarse_guess != 0 && o.coarse_guess != 1) || (o.graphs != 0 && o.graphs != 1)) {
     set_error("ebe_pcg_solve: invalid options");
     return EBE_ERR_ARG;
   }
@@ -222,8 +246,10 @@ void ebe_pcg_default_opts(ebe_pcg_opts* o) {
   o->check_every = 8;
   o->inner_eps[0] = 0.1;   // Table 2, level 0
   o->inner_eps[1] = 0.05;  // Table 2, level 1
+  o->inner_eps[2] = 0.025; // Table 2, level 2
   o->inner_max[0] = 30;
   o->inner_max[1] = 300;
+  o->inner_max[2] = 3000;
   o->use_x0 = 0;
   o->coarse_guess = 0;
   o->graphs = 1;
@@ -264,12 +290,13 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   st.counter = w.counter.as<unsigned>();
   Bufs b{w.r.as<double>(), w.p.as<double>(), w.q.as<double>(), w.rb.as<void>(),
          w.ub.as<void>(), w.e0.as<void>(), w.p0.as<void>(), w.q0.as<void>(), w.r1.as<void>(),
-         w.u1.as<void>(), w.e1.as<void>(), w.p1.as<void>(), w.q1.as<void>()};
+         w.u1.as<void>(), w.e1.as<void>(), w.p1.as<void>(), w.q1.as<void>(), w.r2.as<void>(),
+         w.u2.as<void>(), w.e2.as<void>(), w.p2.as<void>(), w.q2.as<void>()};
   const size_t vbytes = size_t(m->n_nodes) * 3 * nr * sizeof(double);
 
   // Pick the product forms this solve uses, once per mesh and case count,
   // before anything is captured into a graph (tuning waits on the stream).
-  const bool mg = o.precond == EBE_PREC_MG2;
+  const bool mg = o.precond == EBE_PREC_MG2 || o.precond == EBE_PREC_MG3;
   const ebe_dtype inner_dt = o.mode == EBE_MODE_MIXED ? EBE_F32 : EBE_F64;
   const size_t v1bytes = size_t(m->n_vertices) * 3 * nr * sizeof(double);
   struct Tune {
@@ -287,6 +314,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   }
   for (int t = 0; t < (mg ? 3 : 1); ++t)
     if ((st_ = prepare_products(m, tunes[t].level, tunes[t].dt, nr, s)) != EBE_OK) return st_;
+  if (o.precond == EBE_PREC_MG3 && (st_ = ensure_level2(m, inner_dt, s)) != EBE_OK) return st_;
 
   EBE_K(launch_fill_zero(st.sc, sizeof(SolverScalars), s));
   EBE_K(launch_fill_zero(st.counter, 64, s));
@@ -313,8 +341,8 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
     };
     if (mg) {
       for (int c = 0; c < k; ++c) {
-        rs = (o.mode == EBE_MODE_MIXED) ? mg2_precondition<float>(m, nr, o, b, st, s)
-                                        : mg2_precondition<double>(m, nr, o, b, st, s);
+        rs = (o.mode == EBE_MODE_MIXED) ? mg_precondition<float>(m, nr, o, b, st, s)
+                                        : mg_precondition<double>(m, nr, o, b, st, s);
         if (rs != EBE_OK) return rs;
         if ((rs = product_and_update()) != EBE_OK) return rs;
       }
@@ -346,6 +374,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
     stats->outer_iters = h->outer_iter;
     stats->inner_iters[0] = h->inner[0].steps;
     stats->inner_iters[1] = h->inner[1].steps;
+    stats->inner_iters[2] = h->inner[2].steps;
     stats->max_rel_res = h->max_rel;
     stats->status = result;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -630,7 +630,7 @@ static const T* minv_of(const ebe_mesh* m, int level) {
 template <typename T>
 hipError_t sk_inner_init(const ebe_mesh* m, int level, const T* r, const T* q, T* e, int nr, double eps, int nmax,
                          SolverState& st, hipStream_t s) {
-  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  const int64_t n = level_rows(m, level);
   return run_nodecase<T, 3>(BodyInnerInit<T>{r, q, e, minv_of<T>(m, level), nr},
                             EpiInnerStart<T>{&st.sc->inner[level], eps, nmax}, n, nr, st, &st.sc->outer_active, s);
 }
@@ -638,7 +638,7 @@ hipError_t sk_inner_init(const ebe_mesh* m, int level, const T* r, const T* q, T
 template <typename T>
 hipError_t sk_inner_p(const ebe_mesh* m, int level, const T* e, T* p, T* q, int nr, SolverState& st,
                       hipStream_t s) {
-  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  const int64_t n = level_rows(m, level);
   return run_nodecase<T, 0>(BodyInnerP<T>{e, p, q, minv_of<T>(m, level), st.sc->inner[level].beta, nr}, NoEpi{},
                             n, nr, st, &st.sc->inner[level].active, s);
 }
@@ -646,7 +646,7 @@ hipError_t sk_inner_p(const ebe_mesh* m, int level, const T* e, T* p, T* q, int 
 template <typename T>
 hipError_t sk_inner_update(const ebe_mesh* m, int level, T* e, T* u, const T* q, const T* p, int nr, double eps,
                            int nmax, SolverState& st, hipStream_t s) {
-  const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
+  const int64_t n = level_rows(m, level);
   return run_nodecase<T, 2>(BodyInnerUpdate<T>{e, u, q, p, minv_of<T>(m, level), &st.sc->inner[level], nr},
                             EpiInnerStep<T>{&st.sc->inner[level], eps, nmax}, n, nr, st,
                             &st.sc->inner[level].active, s);

@@ -33,7 +33,7 @@ struct SolverScalars {         // Algorithm 1(a)
   int outer_iter;
   int err;                     // EBE_ERR_BREAKDOWN / EBE_ERR_NONFINITE raised on the device
   int pad;
-  InnerScalars inner[2];
+  InnerScalars inner[3];
 };
 
 struct SolverState {

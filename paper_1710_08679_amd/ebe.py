@@ -19,7 +19,7 @@ OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_INDEX, ERR_INVERTED, ERR_CURVED, ERR_MATERIAL = -1, -2, -3, -4, -5
 ERR_OOM, ERR_HIP, ERR_BREAKDOWN, ERR_NONFINITE, ERR_NUMBERING = -6, -7, -8, -9, -10
 F64, F32 = 0, 1
-PREC_PCGE, PREC_MG2 = 0, 1
+PREC_PCGE, PREC_MG2, PREC_MG3 = 0, 1, 2
 MODE_FP64, MODE_MIXED = 0, 1
 MAX_RHS = 16
 FORM_AUTO, FORM_GATHER, FORM_STAGED, FORM_PIPELINED, FORM_ASSEMBLED = -1, 0, 1, 2, 3
@@ -31,26 +31,27 @@ EXPORTED = (
     "ebe_matvec_p1", "ebe_prolong_p1", "ebe_restrict_p1", "ebe_diag_blocks", "ebe_block_jacobi",
     "ebe_pcg_default_opts", "ebe_pcg_solve", "ebe_adjoint_grad", "ebe_batch_create", "ebe_batch_solve",
     "ebe_batch_destroy", "ebe_status_string", "ebe_last_error", "ebe_build_info", "ebe_autotune",
-    "ebe_set_product_form", "ebe_get_product_form",
+    "ebe_set_product_form", "ebe_get_product_form", "ebe_level2_info", "ebe_matvec_l2", "ebe_prolong_l2",
+    "ebe_restrict_l2",
 )
 
 
 class PcgOpts(ctypes.Structure):
     _fields_ = [("precond", ctypes.c_int32), ("mode", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("inner_eps", ctypes.c_double * 2), ("inner_max", ctypes.c_int32 * 2),
+                ("inner_eps", ctypes.c_double * 3), ("inner_max", ctypes.c_int32 * 3),
                 ("use_x0", ctypes.c_int32), ("coarse_guess", ctypes.c_int32), ("graphs", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
 class PcgStats(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("inner_iters", ctypes.c_int64 * 2), ("max_rel_res", ctypes.c_double),
+                ("inner_iters", ctypes.c_int64 * 3), ("max_rel_res", ctypes.c_double),
                 ("seconds", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {"outer_iters": self.outer_iters, "status": self.status,
-                "inner_iters": [int(self.inner_iters[0]), int(self.inner_iters[1])],
+                "inner_iters": [int(v) for v in self.inner_iters],
                 "max_rel_res": self.max_rel_res, "seconds": self.seconds}
 
 
@@ -99,6 +100,10 @@ def load():
         "ebe_autotune": ([_vp, _i32, _i32, _i32, _vp, ctypes.POINTER(ctypes.c_double)], _i32),
         "ebe_set_product_form": ([_vp, _i32, _i32, _i32, _i32], _i32),
         "ebe_get_product_form": ([_vp, _i32, _i32, _i32, ctypes.POINTER(_i32)], _i32),
+        "ebe_level2_info": ([_vp, ctypes.POINTER(_i64), _vp], _i32),
+        "ebe_matvec_l2": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
+        "ebe_prolong_l2": ([_vp, _i32, _i32, _vp, _vp, _vp], _i32),
+        "ebe_restrict_l2": ([_vp, _i32, _i32, _vp, _vp, _vp], _i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -163,7 +168,8 @@ def default_opts(**kw) -> PcgOpts:
         if k not in names:
             raise TypeError(f"unknown solver option {k!r}")
         if k in ("inner_eps", "inner_max"):
-            getattr(o, k)[0], getattr(o, k)[1] = v
+            for i, x in enumerate(v):  # levels 0, 1 (and 2)
+                getattr(o, k)[i] = x
         else:
             setattr(o, k, v)
     return o
@@ -269,9 +275,50 @@ class Mesh:
         """y (Nv, 3, n) = P1^T x (N, 3, n)."""
         return self._vec_op(load().ebe_restrict_p1, x, self.n_nodes, self.n_vertices, apply_bc, out, stream)
 
+    # ---- level 2 (aggregates of the corner mesh) --------------------------
+    def level2_info(self):
+        """(n_agg, agg) with agg (Nv,) int32: each corner's aggregate."""
+        na = _i64()
+        agg = np.empty(self.n_vertices, dtype=np.int32)
+        _check(load().ebe_level2_info(self.handle, ctypes.byref(na), agg.ctypes.data))
+        return int(na.value), agg
+
+    @property
+    def n_agg(self):
+        na = _i64()
+        _check(load().ebe_level2_info(self.handle, ctypes.byref(na), None))
+        return int(na.value)
+
+    def matvec_l2(self, x, apply_bc=False, out=None, stream=None):
+        """y = A2 x on the aggregates; x (Na, 3, nrhs)."""
+        na = self.n_agg
+        return self._vec_op(load().ebe_matvec_l2, x, na, na, apply_bc, out, stream)
+
+    def prolong_l2(self, x, out=None, stream=None):
+        """y (Nv, 3, n) = P2 x (Na, 3, n)."""
+        return self._vec_op2(load().ebe_prolong_l2, x, self.n_agg, self.n_vertices, out, stream)
+
+    def restrict_l2(self, x, out=None, stream=None):
+        """y (Na, 3, n) = P2^T x (Nv, 3, n)."""
+        return self._vec_op2(load().ebe_restrict_l2, x, self.n_vertices, self.n_agg, out, stream)
+
+    def _vec_op2(self, fn, x, rows_in, rows_out, out, stream):
+        import torch
+        if x.dim() != 3 or x.shape[0] != rows_in or x.shape[1] != 3:
+            raise ValueError(f"x must be ({rows_in}, 3, nrhs)")
+        nrhs = int(x.shape[2])
+        if out is None:
+            out = torch.empty((rows_out, 3, nrhs), dtype=x.dtype, device=x.device)
+        _check(fn(self.handle, _dtype_code(x.dtype), nrhs, _dev(x, name="x"),
+                  _dev(out, x.dtype, (rows_out, 3, nrhs), "out"), _stream(stream)))
+        return out
+
+    def _rows(self, level):
+        return (self.n_nodes, self.n_vertices, self.n_agg)[level]
+
     def block_jacobi(self, x, level=0, out=None, stream=None):
         import torch
-        rows = self.n_nodes if level == 0 else self.n_vertices
+        rows = self._rows(level)
         if x.dim() != 3 or x.shape[0] != rows or x.shape[1] != 3:
             raise ValueError(f"x must be ({rows}, 3, nrhs)")
         nrhs = int(x.shape[2])
@@ -282,9 +329,9 @@ class Mesh:
         return out
 
     def diag_blocks(self, level=0, stream=None):
-        """(rows, 3, 3) float64 nodal diagonal blocks (fixed rows/cols -> identity)."""
+        """(rows, 3, 3) float64 nodal diagonal blocks (level 0, 1 or 2)."""
         import torch
-        rows = self.n_nodes if level == 0 else self.n_vertices
+        rows = self._rows(level)
         out = torch.empty((rows, 3, 3), dtype=torch.float64, device="cuda")
         _check(load().ebe_diag_blocks(self.handle, int(level), _dev(out), _stream(stream)))
         return out

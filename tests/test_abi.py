@@ -50,14 +50,16 @@ def test_default_options_follow_table2(lib):
     assert o.inner_eps[1] == g["levels"]["1"]["tolerance"]
     assert o.inner_max[0] == g["levels"]["0"]["max_iterations"]
     assert o.inner_max[1] == g["levels"]["1"]["max_iterations"]
+    assert o.inner_eps[2] == g["levels"]["2"]["tolerance"]
+    assert o.inner_max[2] == g["levels"]["2"]["max_iterations"]
     assert o.tol == g["outer_tolerance"]["value"]
 
 
 def test_struct_layouts_match_header(tmp_path):
     """The binding's ctypes structures match the C header, field by field:
     a C program built from include/ebe.h prints sizes and offsets."""
-    assert ctypes.sizeof(ebe.PcgOpts) == 64
-    assert ctypes.sizeof(ebe.PcgStats) == 40
+    assert ctypes.sizeof(ebe.PcgOpts) == 80
+    assert ctypes.sizeof(ebe.PcgStats) == 48
     fields = {"ebe_pcg_opts": ebe.PcgOpts, "ebe_pcg_stats": ebe.PcgStats}
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "ebe.h"', "int main(void) {"]
     for cname, py in fields.items():
@@ -140,3 +142,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.ebe_get_product_form(None, 0, ebe.F32, 4, ctypes.byref(f)) == ebe.ERR_ARG
     assert lib.ebe_batch_solve(None, None, None, None, None, None) == ebe.ERR_ARG
     assert lib.ebe_adjoint_grad(None, ebe.F64, 1, None, None, None, None) == ebe.ERR_ARG
+    assert lib.ebe_level2_info(None, None, None) == ebe.ERR_ARG
+    assert lib.ebe_matvec_l2(None, ebe.F32, 1, None, None, 0, None) == ebe.ERR_ARG
+    assert lib.ebe_prolong_l2(None, ebe.F32, 1, None, None, None) == ebe.ERR_ARG
+    assert lib.ebe_restrict_l2(None, ebe.F32, 1, None, None, None) == ebe.ERR_ARG

@@ -1,0 +1,132 @@
+"""GPU parity of level 2 (aggregation of the corner mesh) against the oracle,
+through the C ABI: the aggregates (bit-exact), P2 and P2^T, A2 x, the level-2
+block Jacobi, and three-level solves against the direct solution."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import alg1, amg, fem, solve
+from paper_1710_08679_amd import ebe, meshgen
+from tests.helpers import parity_mesh
+
+pytestmark = pytest.mark.gpu
+
+DT = {np.float64: torch.float64, np.float32: torch.float32}
+
+
+def to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def dof_apply(P, v):
+    M, _, n = v.shape
+    return (P @ v.reshape(3 * M, n)).reshape(P.shape[0] // 3, 3, n)
+
+
+@pytest.fixture(scope="module")
+def lv2(gpu_lib):
+    m = parity_mesh(9, 7, 5, seed=3, bc=True)
+    K1 = fem.assemble(m.xyz, m.conn, m.young, m.poisson, order=1, n_nodes=m.n_vertices)
+    agg, na, P2, A2, cfx = amg.level2(m.conn, m.n_vertices, K1, m.fixed)
+    print(f"[level 2] Nv={m.n_vertices} aggregates={na}", flush=True)
+    return m, ebe.Mesh.from_generated(m), agg, na, P2, A2, cfx
+
+
+def test_aggregates_equal_the_oracle(lv2):
+    m, gm, agg, na, *_ = lv2
+    n, a = gm.level2_info()
+    assert n == na and np.array_equal(a, agg)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_transfers_match_oracle(lv2, dtype):
+    m, gm, agg, na, P2, A2, cfx = lv2
+    rng = meshgen.rng_for(93, 0)
+    x2 = rng.standard_normal((na, 3, 5)).astype(dtype)
+    x1 = rng.standard_normal((m.n_vertices, 3, 5)).astype(dtype)
+    y1 = gm.prolong_l2(to_dev(x2, dtype)).cpu().numpy().astype(np.float64)
+    y2 = gm.restrict_l2(to_dev(x1, dtype)).cpu().numpy().astype(np.float64)
+    r1 = dof_apply(P2, x2.astype(np.float64))
+    r2 = dof_apply(P2.T.tocsr(), x1.astype(np.float64))
+    r2[cfx] = 0
+    assert np.array_equal(y1, r1)  # a copy: exact in either precision
+    u = float(np.finfo(dtype).eps)
+    assert np.max(np.abs(y2 - r2)) <= 2 * u * np.max(np.abs(r2))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("nrhs", [1, 4, 7, 16])
+def test_a2_product_matches_oracle(lv2, dtype, nrhs):
+    m, gm, agg, na, P2, A2, cfx = lv2
+    x = meshgen.rng_for(94, nrhs).standard_normal((na, 3, nrhs)).astype(dtype)
+    xd = x.astype(np.float64)
+    y = gm.matvec_l2(to_dev(x, dtype)).cpu().numpy().astype(np.float64)
+    yb = gm.matvec_l2(to_dev(x, dtype), apply_bc=True).cpu().numpy().astype(np.float64)
+    ref = dof_apply(A2, xd)
+    xm = xd.copy()
+    xm[cfx] = 0
+    refb = dof_apply(A2, xm)
+    refb[cfx] = 0
+    # |A2| |x| bounds the rounding of the (summed, then rounded) blocks and of the products
+    bound = dof_apply(abs(A2), np.abs(xd)) + 1e-300
+    c = 1e-12 if dtype == np.float64 else 64 * float(np.finfo(np.float32).eps)
+    assert np.max(np.abs(y - ref) / bound) <= c
+    assert np.max(np.abs(yb - refb) / bound) <= c
+    assert np.all(yb[cfx] == 0)
+
+
+def test_level2_blocks_match_oracle(lv2):
+    m, gm, agg, na, P2, A2, cfx = lv2
+    got = gm.diag_blocks(2).cpu().numpy()
+    ref = fem.diag_blocks(A2, na)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+    Minv = solve.block_jacobi_inverse(A2, cfx, na)
+    x = meshgen.rng_for(95, 0).standard_normal((na, 3, 4))
+    x[cfx] = 0.0
+    z = gm.block_jacobi(to_dev(x, np.float64), level=2).cpu().numpy()
+    zr = np.einsum("nab,nbr->nar", Minv, x)
+    assert np.max(np.abs(z - zr)) <= 1e-12 * np.max(np.abs(zr))
+
+
+def test_level2_follows_a_material_change(lv2):
+    m, gm, agg, na, P2, A2, cfx = lv2
+    E2 = m.young * 1.7
+    gm.set_material(to_dev(E2, np.float64), to_dev(m.poisson, np.float64))
+    try:
+        x = meshgen.rng_for(96, 0).standard_normal((na, 3, 2))
+        y = gm.matvec_l2(to_dev(x, np.float64)).cpu().numpy()
+        assert np.max(np.abs(y - 1.7 * dof_apply(A2, x))) <= 1e-12 * np.max(np.abs(y))
+    finally:
+        gm.set_material(to_dev(m.young, np.float64), to_dev(m.poisson, np.float64))
+
+
+@pytest.fixture(scope="module")
+def crust3(gpu_lib):
+    m = meshgen.crust_mesh(12, 12, 6)
+    f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(3, 2), nrhs=16)
+    K = fem.assemble(m.xyz, m.conn, m.young, m.poisson)
+    print(f"[crust 12x12x6] DOF={m.n_dof}: oracle sparse LU", flush=True)
+    return m, ebe.Mesh.from_generated(m), f, solve.sparse_solve(K, f, m.fixed)
+
+
+@pytest.mark.parametrize("mode", [ebe.MODE_MIXED, ebe.MODE_FP64])
+def test_crust_mg3_within_1e6(crust3, mode):
+    m, gm, f, ud = crust3
+    u, st = gm.solve(torch.from_numpy(f).cuda(), precond=ebe.PREC_MG3, mode=mode, tol=1e-8)
+    print(f"[crust MG3 mode={mode}] {st}", flush=True)
+    assert st["status"] == ebe.OK and st["max_rel_res"] <= 1e-8
+    assert st["inner_iters"][2] > 0
+    err = np.linalg.norm(u.cpu().numpy() - ud) / np.linalg.norm(ud)
+    assert err <= 1e-6
+
+
+def test_small_mg3_matches_oracle_three_level_solve(gpu_lib):
+    m = meshgen.crust_mesh(6, 6, 3)
+    f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(3, 2), nrhs=4)
+    gm = ebe.Mesh.from_generated(m)
+    u, st = gm.solve(torch.from_numpy(f).cuda(), precond=ebe.PREC_MG3, tol=1e-10)
+    uo, sto = alg1.adaptive_cg(m.xyz, m.conn, m.n_vertices, m.young, m.poisson, m.fixed, f, tol=1e-10, levels=3)
+    print(f"[crust 6x6x3 MG3] gpu {st} oracle {sto}", flush=True)
+    assert st["status"] == ebe.OK
+    # both converge to the same solution; iteration counts are not pinned
+    assert np.linalg.norm(u.cpu().numpy() - uo) / np.linalg.norm(uo) <= 1e-8
