@@ -18,13 +18,18 @@ is plain aggregation with one 3-DOF (translation) coarse node per aggregate:
     3. a corner still free (none can be: a corner left free by pass 1 had an
        aggregated neighbour when it was visited) roots an aggregate with its
        free neighbours.
-* P2 maps DOF (I, c) of aggregate I to DOF (a, c) of each member a, except
-  where (a, c) is fixed (Dirichlet);
-* A2 = P2^T K1 P2 (Galerkin); a coarse DOF all of whose fine DOFs are fixed
+* the tentative prolongator T maps DOF (I, c) of aggregate I to DOF (a, c)
+  of each member a, except where (a, c) is fixed (Dirichlet);
+* P2 = (I - omega D1^-1 K1p) T with omega = 2/3 (smoothed aggregation: one
+  damped block-Jacobi step applied to T), K1p = K1 with fixed rows and
+  columns removed, D1^-1 the level-1 block Jacobi (fixed DOFs: identity);
+* A2 = P2^T K1p P2 (Galerkin); a coarse DOF all of whose fine DOFs are fixed
   has an empty row and column and is treated as fixed at level 2.
 """
 import numpy as np
 import scipy.sparse as sp
+
+from .solve import block_jacobi_inverse
 
 
 def corner_graph(conn, n_vertices):
@@ -63,9 +68,12 @@ def aggregate(nbrs):
     return agg, na
 
 
+OMEGA = 2.0 / 3.0
+
+
 def prolongation_p2(agg, n_agg, fixed):
-    """P2 as a (3 Nv) x (3 Na) 0/1 matrix on DOFs (node-major, component-minor);
-    rows of fixed fine DOFs are empty."""
+    """The tentative prolongator T as a (3 Nv) x (3 Na) 0/1 matrix on DOFs
+    (node-major, component-minor); rows of fixed fine DOFs are empty."""
     nv = agg.shape[0]
     fx = np.asarray(fixed).astype(bool)[:nv]
     rows, cols = [], []
@@ -88,13 +96,31 @@ def coarse_fixed(agg, n_agg, fixed):
     return ~free
 
 
+def projected(K1, fixed):
+    """K1p = P K1 P: the rows and columns of fixed DOFs removed."""
+    keep = sp.diags((~np.asarray(fixed).astype(bool)[:K1.shape[0] // 3]).ravel().astype(float))
+    return (keep @ K1 @ keep).tocsr()
+
+
+def smoothed(T, K1, fixed, omega=OMEGA):
+    """P2 = (I - omega D1^-1 K1p) T, D1 the 3x3 diagonal blocks of K1p with the
+    fixed DOFs' rows and columns set to identity."""
+    nv = K1.shape[0] // 3
+    K1p = projected(K1, fixed)
+    Dinv = block_jacobi_inverse(K1, np.asarray(fixed)[:nv], nv)
+    D = sp.block_diag(list(Dinv)).tocsr()
+    return (T - omega * (D @ (K1p @ T))).tocsr()
+
+
 def galerkin(K1, P2):
     """A2 = P2^T K1 P2."""
     return (P2.T @ K1 @ P2).tocsr()
 
 
-def level2(conn, n_vertices, K1, fixed):
-    """Everything level 2 needs: (agg, n_agg, P2, A2, coarse fixed mask)."""
+def level2(conn, n_vertices, K1, fixed, omega=OMEGA):
+    """Everything level 2 needs: (agg, n_agg, P2, A2, coarse fixed mask);
+    omega = 0 gives the unsmoothed (tentative) prolongator."""
     agg, na = aggregate(corner_graph(conn, n_vertices))
-    P2 = prolongation_p2(agg, na, fixed)
-    return agg, na, P2, galerkin(K1, P2), coarse_fixed(agg, na, fixed)
+    T = prolongation_p2(agg, na, fixed)
+    P2 = smoothed(T, K1, fixed, omega) if omega != 0 else T
+    return agg, na, P2, galerkin(projected(K1, fixed), P2), coarse_fixed(agg, na, fixed)

@@ -3,9 +3,11 @@
 * Aggregation, by hand on paths, a star and a small tree, and structurally on
   a mesh: a partition of the corners into connected aggregates, each holding
   a corner together with its whole neighbourhood.
+* Smoothed prolongator: maps a coarse translation to the fine translation
+  without Dirichlet conditions (K1 annihilates it, so the smoothing step
+  leaves it); empty rows at fixed DOFs; omega = 0 gives the 0/1 tentative map.
 * Galerkin A2: symmetric; without Dirichlet conditions it annihilates the
-  three coarse translations (K1 annihilates rigid translations and P2 maps a
-  coarse constant to a fine constant); with one-corner aggregates it is
+  three coarse translations; with one-corner aggregates and omega = 0 it is
   P K1 P (the fixed DOFs' rows and columns removed); positive definite on
   the free coarse DOFs of a clamped mesh.
 * Three-level Algorithm 1 converges to the direct solution.
@@ -85,7 +87,27 @@ def test_galerkin_null_space_and_symmetry():
     # the same for P2 itself: a coarse constant is a fine constant
     t = np.zeros(3 * na)
     t[0::3] = 1.0
-    assert np.array_equal(P2 @ t, np.tile([1.0, 0.0, 0.0], m.n_vertices))
+    assert np.max(np.abs(P2 @ t - np.tile([1.0, 0.0, 0.0], m.n_vertices))) <= 1e-13
+    T = amg.prolongation_p2(agg, na, free)
+    assert np.array_equal(T @ t, np.tile([1.0, 0.0, 0.0], m.n_vertices))
+    assert (P2 - T).nnz > 0  # the smoothing step reaches neighbouring aggregates
+
+
+def test_smoothed_prolongator_rows_and_omega_zero():
+    m = mesh(4)
+    meshgen.fix_faces(m, [(2, 0)])
+    K1 = fem.assemble(m.xyz, m.conn, m.young, m.poisson, order=1, n_nodes=m.n_vertices)
+    agg, na, P2, A2, cfx = amg.level2(m.conn, m.n_vertices, K1, m.fixed)
+    fx = m.fixed[:m.n_vertices].astype(bool).ravel()
+    assert abs(P2[np.nonzero(fx)[0]]).max() == 0
+    _, _, T, A0, _ = amg.level2(m.conn, m.n_vertices, K1, m.fixed, omega=0.0)
+    assert np.array_equal(T.toarray(), amg.prolongation_p2(agg, na, m.fixed).toarray())
+    # each fine row of P2 touches only the aggregates of the corner's neighbours
+    nb = amg.corner_graph(m.conn, m.n_vertices)
+    P = P2.tocsr()
+    for v in range(0, m.n_vertices, 7):
+        cols = set((P.indices[P.indptr[3 * v]:P.indptr[3 * v + 3]] // 3).tolist())
+        assert cols <= set(agg[np.append(nb[v], v)].tolist())
 
 
 def test_galerkin_with_singleton_aggregates_is_projected_k1():
@@ -94,7 +116,7 @@ def test_galerkin_with_singleton_aggregates_is_projected_k1():
     K1 = fem.assemble(m.xyz, m.conn, m.young, m.poisson, order=1, n_nodes=m.n_vertices)
     agg = np.arange(m.n_vertices)
     P2 = amg.prolongation_p2(agg, m.n_vertices, m.fixed)
-    A2 = amg.galerkin(K1, P2)
+    A2 = amg.galerkin(amg.projected(K1, m.fixed), P2)
     keep = ~m.fixed[:m.n_vertices].astype(bool).ravel()
     D = sp.diags(keep.astype(float))
     ref = (D @ K1 @ D).tocsr()
