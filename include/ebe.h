@@ -93,8 +93,8 @@ typedef struct ebe_mesh ebe_mesh;   /* opaque; owns device copies of the mesh an
 typedef struct ebe_batch ebe_batch; /* opaque; a set of meshes solved together */
 
 /* Solver options.  ebe_pcg_default_opts() fills the paper's settings:
- * MG2, MIXED, tol 1e-8, inner tolerances {0.1, 0.05} and maxima {30, 300}
- * (Section 4, Table 2). */
+ * MG3 (three inner levels), MIXED, tol 1e-8, inner tolerances
+ * {0.1, 0.05, 0.025} and maxima {30, 300, 3000} (Section 4, Table 2). */
 typedef struct {
   int32_t precond;      /* EBE_PREC_* */
   int32_t mode;         /* EBE_MODE_* */
@@ -191,22 +191,24 @@ ebe_status ebe_block_jacobi(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int3
 
 /* ---- level 2: algebraic coarsening of the linear mesh ------------------- */
 
-/* Inner loop level 2 of Algorithm 1(a) runs on a coarsening of the corner
- * mesh: corners grouped into aggregates (three greedy passes over the corner
- * graph in increasing id: a corner whose neighbours are all free roots an
- * aggregate of itself and its neighbours; a corner left joins the lowest
- * neighbouring aggregate; leftovers root their own), one 3-DOF node per
- * aggregate.  P2 copies an aggregate's value to its members' free DOFs;
- * A2 = P2^T K1 P2, kept as 3x3 blocks (Section 2: "3 x 3 block compressed row
- * storage"); a coarse DOF whose members are all fixed in that component is
- * fixed.  Built with the mesh (structure) and on first use (values, per
+/* Inner loop level 2 of Algorithm 1(a) runs on a smoothed-aggregation
+ * coarsening of the corner mesh: corners grouped into aggregates (three
+ * greedy passes over the corner graph in increasing id: a corner whose
+ * neighbours are all free roots an aggregate of itself and its neighbours; a
+ * corner left joins the lowest neighbouring aggregate; leftovers root their
+ * own), one 3-DOF node per aggregate.  The tentative map T copies an
+ * aggregate's value to its members' free DOFs; P2 = (I - 2/3 D1^-1 K1p) T
+ * (one damped block-Jacobi step, K1p = P K1 P, D1 the level-1 blocks);
+ * A2 = P2^T K1p P2, kept as 3x3 blocks (Section 2: "3 x 3 block compressed
+ * row storage"); a coarse DOF whose members are all fixed in that component
+ * is fixed.  Built with the mesh (structure) and on first use (values, per
  * material).
  *   ebe_level2_info: number of aggregates, and (agg_host [n_vertices] or
  *     NULL) each corner's aggregate; synchronous.
  *   ebe_matvec_l2: y = A2 x, x/y [n_agg][3][nrhs] of dtype (apply_bc: P A2 P).
  *   ebe_prolong_l2: y[n_vertices] = P2 x[n_agg] (zero at fixed DOFs).
- *   ebe_restrict_l2: y[n_agg] = P2^T x[n_vertices] (members' free DOFs
- *     summed; zero at fixed coarse DOFs).
+ *   ebe_restrict_l2: y[n_agg] = P2^T x[n_vertices] (zero at fixed coarse
+ *     DOFs).
  * The vector entry points are asynchronous except the first call after a
  * material change, which forms A2 and synchronises the stream. */
 ebe_status ebe_level2_info(const ebe_mesh* mesh, int64_t* n_agg, int32_t* agg_host);

@@ -43,5 +43,5 @@ class SurfaceMisfit(torch.autograd.Function):
 def surface_misfit(young, mesh, poisson, f, surf_dofs, target, opts=None, grad_dtype=torch.float64):
     """L(E) with an adjoint gradient; see the module docstring."""
     if opts is None:
-        opts = ebe.default_opts(precond=ebe.PREC_MG2, mode=ebe.MODE_MIXED, tol=1e-10)
+        opts = ebe.default_opts(precond=ebe.PREC_MG3, mode=ebe.MODE_MIXED, tol=1e-10)
     return SurfaceMisfit.apply(young, mesh, poisson, f, surf_dofs, target, opts, grad_dtype)

@@ -72,10 +72,15 @@ ebe_status ensure_assembled(ebe_mesh* m, ebe_dtype dt, hipStream_t s) {
 ebe_status ensure_level2(ebe_mesh* m, ebe_dtype dt, hipStream_t s) {
   const int k = dt == EBE_F64 ? 0 : 1;
   if (m->a2.ready[k]) return EBE_OK;
-  ebe_status st = ensure_assembled(m, EBE_F64, s);  // A2 is summed from the FP64 K1 blocks
+  // P2 and A2 are formed from the FP64 K1 blocks and the level-1 block Jacobi
+  ebe_status st = ensure_assembled(m, EBE_F64, s);
+  if (st == EBE_OK) st = ensure_blocks(m, s);
   const size_t n = std::max<size_t>(size_t(m->a2.slots) * 9 * kSliceRows, 1);
+  const size_t np = std::max<size_t>(size_t(m->n_vertices) * m->p2_width * 9, 1);
   if (st == EBE_OK) st = m->a2.val[0].alloc(n * sizeof(double));
   if (st == EBE_OK && k == 1) st = m->a2.val[1].alloc(n * sizeof(float));
+  if (st == EBE_OK) st = m->p2_val[0].alloc(np * sizeof(double));
+  if (st == EBE_OK) st = m->p2_val[1].alloc(np * sizeof(float));
   if (st != EBE_OK) return st;
   const bool fresh = !m->a2.ready[0];
   EBE_TRY_HIP(launch_assemble_a2(m, fresh, k == 1, s));
@@ -197,13 +202,17 @@ ebe_status ebe_matvec_l2(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x,
 ebe_status ebe_prolong_l2(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, void* stream) {
   ebe_status st = check_common("ebe_prolong_l2", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
-  return hip_status("ebe_prolong_l2", launch_prolong_p2(m, dt, nrhs, x, y, static_cast<hipStream_t>(stream)));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = ensure_level2(m, EBE_F64, s)) != EBE_OK) return st;  // P2 is formed with A2
+  return hip_status("ebe_prolong_l2", launch_prolong_p2(m, dt, nrhs, x, y, s));
 }
 
 ebe_status ebe_restrict_l2(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, void* stream) {
   ebe_status st = check_common("ebe_restrict_l2", m, dt, nrhs, x, y);
   if (st != EBE_OK) return st;
-  return hip_status("ebe_restrict_l2", launch_restrict_p2(m, dt, nrhs, x, y, static_cast<hipStream_t>(stream)));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = ensure_level2(m, EBE_F64, s)) != EBE_OK) return st;  // P2 is formed with A2
+  return hip_status("ebe_restrict_l2", launch_restrict_p2(m, dt, nrhs, x, y, s));
 }
 
 ebe_status ebe_diag_blocks(ebe_mesh* m, int32_t level, double* blocks, void* stream) {

@@ -14,9 +14,14 @@
 //   3. a corner still free (none: a corner left free by pass 1 had an
 //      aggregated neighbour when it was visited) roots an aggregate with its
 //      free neighbours.
-// P2 copies coarse DOF (I, c) to DOF (a, c) of every member a that is not
-// fixed; A2 = P2^T K1 P2 (Galerkin), so its block (I, J) is the sum of the
-// K1 blocks (a, b), a in I, b in J, with fixed rows and columns left out.
+// The tentative prolongator T copies coarse DOF (I, c) to DOF (a, c) of every
+// member a that is not fixed; P2 = (I - omega D1^-1 K1p) T (smoothed
+// aggregation: one damped block-Jacobi step on T, K1p = K1 without the fixed
+// rows and columns, D1 its diagonal blocks with fixed DOFs set to identity),
+// so fine row a of P2 reaches the aggregates of a's neighbours; A2 =
+// P2^T K1p P2 (Galerkin) couples aggregates two steps apart.  Here: the
+// structure of P2 (per fine row, its aggregates, increasing), of P2^T, and of
+// A2's block rows; the values are formed on the GPU (setup_kernels.hip).
 #include <algorithm>
 #include <vector>
 
@@ -75,7 +80,7 @@ ebe_status upload_asm(AsmOp& op, int64_t rows, const std::vector<int32_t>& soff,
 }
 
 ebe_status build_level2(ebe_mesh* m, const std::vector<int32_t>& bptr, const std::vector<int32_t>& bcol,
-                        const std::vector<int32_t>& k1soff, const uint8_t* fix, hipStream_t s) {
+                        const uint8_t* fix, hipStream_t s) {
   const int64_t nv = int64_t(bptr.size()) - 1;
   // aggregation (the row of v in K1 is v and its neighbours)
   std::vector<int32_t> agg(nv, -1);
@@ -104,56 +109,72 @@ ebe_status build_level2(ebe_mesh* m, const std::vector<int32_t>& bptr, const std
       if (agg[bcol[k]] < 0) agg[bcol[k]] = na;
     ++na;
   }
-  // members (increasing) and coarse fix bits
-  std::vector<int32_t> moff(na + 1, 0), mem(nv);
-  for (int64_t v = 0; v < nv; ++v) moff[agg[v] + 1]++;
-  for (int32_t a = 0; a < na; ++a) moff[a + 1] += moff[a];
-  {
-    std::vector<int32_t> fill(moff.begin(), moff.end() - 1);
-    for (int64_t v = 0; v < nv; ++v) mem[fill[agg[v]]++] = int32_t(v);
-  }
+  // coarse fix bits: a component is fixed when it is fixed at every member
   std::vector<uint8_t> cfix(na, 7);
   for (int64_t v = 0; v < nv; ++v) cfix[agg[v]] &= uint8_t(fix[v] & 7);
-  // A2 rows: the aggregates of the members' neighbours, increasing
-  std::vector<int32_t> aptr(na + 1, 0), acol;
+  // P2 rows: the aggregates of v and its neighbours, increasing, padded with -1
+  int32_t width = 1;
+  std::vector<int32_t> tmp;
+  for (int64_t v = 0; v < nv; ++v) {
+    tmp.clear();
+    for (int32_t k = bptr[v]; k < bptr[v + 1]; ++k) tmp.push_back(agg[bcol[k]]);
+    std::sort(tmp.begin(), tmp.end());
+    width = std::max(width, int32_t(std::unique(tmp.begin(), tmp.end()) - tmp.begin()));
+  }
+  std::vector<int32_t> pcol(size_t(nv) * width, -1);
+  for (int64_t v = 0; v < nv; ++v) {
+    tmp.clear();
+    for (int32_t k = bptr[v]; k < bptr[v + 1]; ++k) tmp.push_back(agg[bcol[k]]);
+    std::sort(tmp.begin(), tmp.end());
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    std::copy(tmp.begin(), tmp.end(), pcol.begin() + size_t(v) * width);
+  }
+  if (int64_t(nv) * width >= (int64_t(1) << 31) / 9) {
+    set_error("level 2: prolongator too large for 32-bit indices");
+    return EBE_ERR_ARG;
+  }
+  // P2^T: for each aggregate, the P2 entries (v * width + w) naming it, in v order
+  std::vector<int32_t> toff(na + 1, 0), tidx;
+  for (size_t i = 0; i < pcol.size(); ++i)
+    if (pcol[i] >= 0) toff[pcol[i] + 1]++;
+  for (int32_t a = 0; a < na; ++a) toff[a + 1] += toff[a];
+  tidx.resize(toff[na]);
+  {
+    std::vector<int32_t> fill(toff.begin(), toff.end() - 1);
+    for (size_t i = 0; i < pcol.size(); ++i)
+      if (pcol[i] >= 0) tidx[fill[pcol[i]]++] = int32_t(i);
+  }
+  // A2 rows: J reached from I through P2^T, K1 and P2, increasing
+  std::vector<int32_t> aptr(na + 1, 0), acol, alen(na);
   std::vector<int32_t> stamp(na, -1);
   for (int32_t a = 0; a < na; ++a) {
     const size_t b0 = acol.size();
-    for (int32_t i = moff[a]; i < moff[a + 1]; ++i) {
-      const int32_t v = mem[i];
+    for (int32_t t = toff[a]; t < toff[a + 1]; ++t) {
+      const int64_t v = tidx[t] / width;
       for (int32_t k = bptr[v]; k < bptr[v + 1]; ++k) {
-        const int32_t b = agg[bcol[k]];
-        if (stamp[b] != a) {
-          stamp[b] = a;
-          acol.push_back(b);
-        }
+        const int32_t* pr = pcol.data() + size_t(bcol[k]) * width;
+        for (int32_t w = 0; w < width && pr[w] >= 0; ++w)
+          if (stamp[pr[w]] != a) {
+            stamp[pr[w]] = a;
+            acol.push_back(pr[w]);
+          }
       }
     }
     std::sort(acol.begin() + b0, acol.end());
     aptr[a + 1] = int32_t(acol.size());
+    alen[a] = aptr[a + 1] - aptr[a];
   }
   std::vector<int32_t> asoff, ascol;
   ebe_status st = slice_rows(aptr, acol, cfix.data(), asoff, ascol);
   if (st != EBE_OK) return st;
-  // for each K1 entry, the A2 entry its block adds into
-  std::vector<int32_t> map(size_t(k1soff.back()) * kSliceRows, -1);
-  for (int64_t v = 0; v < nv; ++v) {
-    const int64_t sl = v / kSliceRows, r = v - sl * kSliceRows;
-    const int32_t I = agg[v];
-    const int64_t sI = I / kSliceRows, rI = I - sI * kSliceRows;
-    for (int32_t j = 0; j < bptr[v + 1] - bptr[v]; ++j) {
-      const int32_t J = agg[bcol[bptr[v] + j]];
-      const int32_t jj = int32_t(std::lower_bound(acol.begin() + aptr[I], acol.begin() + aptr[I + 1], J) -
-                                 (acol.begin() + aptr[I]));
-      map[size_t(k1soff[sl] + j) * kSliceRows + r] = int32_t((asoff[sI] + jj) * kSliceRows + rI);
-    }
-  }
   m->n_agg = na;
+  m->p2_width = width;
   if ((st = up(m->agg, agg, s)) != EBE_OK) return st;
-  if ((st = up(m->mem_off, moff, s)) != EBE_OK) return st;
-  if ((st = up(m->mem, mem, s)) != EBE_OK) return st;
   if ((st = up(m->cfix, cfix, s)) != EBE_OK) return st;
-  if ((st = up(m->a2_map, map, s)) != EBE_OK) return st;
+  if ((st = up(m->p2_col, pcol, s)) != EBE_OK) return st;
+  if ((st = up(m->p2t_off, toff, s)) != EBE_OK) return st;
+  if ((st = up(m->p2t_idx, tidx, s)) != EBE_OK) return st;
+  if ((st = up(m->a2_len, alen, s)) != EBE_OK) return st;
   return upload_asm(m->a2, na, asoff, ascol, s);
 }
 

@@ -171,16 +171,21 @@ struct ebe_mesh {
   // assembled linear-level operator K1 over the corner graph (its edges are
   // the quadratic mesh's edge nodes); structure at creation, values on demand
   ebe::AsmOp k1;
-  // level 2 (aggregation of the corner graph): aggregate of each corner,
-  // members of each aggregate (increasing), coarse fix bits (a component is
-  // fixed when it is fixed at every member), A2 = P2^T K1 P2, and for each
-  // K1 entry the A2 entry it adds into (-1: padding)
+  // level 2 (smoothed aggregation of the corner graph): aggregate of each
+  // corner, coarse fix bits (a component is fixed when it is fixed at every
+  // member), the smoothed prolongator P2 by fine rows (p2_width slots: the
+  // aggregates of the corner and its neighbours, increasing, -1 padding; 3x3
+  // blocks per slot, values with A2), its transpose as lists of P2 entries
+  // per aggregate, and A2 = P2^T K1p P2 with its rows' lengths
   int64_t n_agg = 0;
-  ebe::DBuf agg;      // int32 [Nv]
-  ebe::DBuf mem_off;  // int32 [Na+1]
-  ebe::DBuf mem;      // int32 [Nv]
-  ebe::DBuf cfix;     // uint8 [Na]
-  ebe::DBuf a2_map;   // int32 [k1.slots][kSliceRows]
+  int32_t p2_width = 0;
+  ebe::DBuf agg;        // int32 [Nv]
+  ebe::DBuf cfix;       // uint8 [Na]
+  ebe::DBuf p2_col;     // int32 [Nv][p2_width]
+  ebe::DBuf p2_val[2];  // [Nv][p2_width][9] per dtype (F64, F32)
+  ebe::DBuf p2t_off;    // int32 [Na+1]
+  ebe::DBuf p2t_idx;    // int32 [entries]: v * p2_width + slot
+  ebe::DBuf a2_len;     // int32 [Na]
   ebe::AsmOp a2;
   ebe::Workspace ws;
 };
@@ -230,7 +235,9 @@ hipError_t launch_geometry(const ebe_mesh* m, ebe_dtype dt, void* out, hipStream
 // blocks), and its FP32 copy into k1.val[1] when f32 is set
 // assemble: form the FP64 values (zeroed first); f32: copy them to the FP32 values
 hipError_t launch_assemble_p1(const ebe_mesh* m, bool assemble, bool f32, hipStream_t s);
-// the same for A2 from the FP64 K1 values
+// P2 (FP64 and FP32) from the FP64 K1 values and the level-1 block Jacobi,
+// then A2 = P2^T K1p P2 (FP64 atomics into zeroed blocks) when assemble is
+// set; the FP32 copy of A2 when f32 is set
 hipError_t launch_assemble_a2(const ebe_mesh* m, bool assemble, bool f32, hipStream_t s);
 // FP64 diagonal blocks of an assembled operator as 6 symmetric values per row
 hipError_t launch_asm_diag(const AsmOp& op, double* blk6, hipStream_t s);
@@ -268,9 +275,9 @@ ebe_status slice_rows(const std::vector<int32_t>& ptr, const std::vector<int32_t
                       std::vector<int32_t>& soff, std::vector<int32_t>& scol);
 ebe_status upload_asm(AsmOp& op, int64_t rows, const std::vector<int32_t>& soff, const std::vector<int32_t>& scol,
                       hipStream_t s);
-// aggregation, members, coarse fix bits, A2 structure and the K1 -> A2 entry map
+// aggregation, coarse fix bits, the structures of P2, P2^T and A2
 ebe_status build_level2(ebe_mesh* m, const std::vector<int32_t>& bptr, const std::vector<int32_t>& bcol,
-                        const std::vector<int32_t>& k1soff, const uint8_t* fix, hipStream_t s);
+                        const uint8_t* fix, hipStream_t s);
 // A2 values (FP64, and FP32 when asked) and the level-2 block Jacobi (allocates)
 ebe_status ensure_level2(ebe_mesh* m, ebe_dtype dt, hipStream_t s);
 // grow the staging buffers for products with up to nrhs cases of the given element size

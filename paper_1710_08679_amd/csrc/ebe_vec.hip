@@ -59,42 +59,54 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t* __restrict__
   y[i] = out;
 }
 
-// Level 2 (aggregates): y[Nv] = P2 x[Na], the aggregate's value copied to
-// every member DOF that is not fixed
+// Level 2 (aggregates): y[Nv] = P2 x[Na] with the smoothed prolongator held
+// by fine rows (width slots: aggregate id or -1, and a 3x3 block each); one
+// work-item per fine value (row, component, case)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong_p2(const int32_t* __restrict__ agg,
-                                                       const uint8_t* __restrict__ fix,
-                                                       const T* __restrict__ x, T* __restrict__ y, int64_t nv,
-                                                       int nrhs) {
+__global__ __launch_bounds__(kBlock) void k_prolong_p2(const int32_t* __restrict__ pcol, int width,
+                                                       const T* __restrict__ pval, const T* __restrict__ x,
+                                                       T* __restrict__ y, int64_t nv, int nrhs) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t w = 3 * int64_t(nrhs);
-  if (i >= nv * w) return;
-  const int64_t v = i / w;
-  const int64_t rem = i - v * w;
-  const int c = int(rem / nrhs);
-  y[i] = ((fix[v] >> c) & 1) ? T(0) : x[int64_t(agg[v]) * w + rem];
+  const int64_t w3 = 3 * int64_t(nrhs);
+  if (i >= nv * w3) return;
+  const int64_t v = i / w3;
+  const int64_t rem = i - v * w3;
+  const int p = int(rem / nrhs);
+  const int j = int(rem - int64_t(p) * nrhs);
+  double acc = 0.0;
+  for (int w = 0; w < width; ++w) {
+    const int32_t J = pcol[v * width + w];
+    if (J < 0) break;
+    const T* b = pval + (v * width + w) * 9 + 3 * p;
+    const T* xs = x + int64_t(J) * w3 + j;
+    acc += double(b[0]) * double(xs[0]) + double(b[1]) * double(xs[nrhs]) + double(b[2]) * double(xs[2 * nrhs]);
+  }
+  y[i] = T(acc);
 }
 
-// y[Na] = P2^T x[Nv]: the sum over an aggregate's members (increasing id) of
-// their free DOFs, zero at fixed coarse DOFs
+// y[Na] = P2^T x[Nv]: for aggregate I, the P2 entries naming it (fine rows in
+// increasing order), each block transposed; zero at fixed coarse DOFs
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_restrict_p2(const int32_t* __restrict__ moff,
-                                                        const int32_t* __restrict__ mem,
-                                                        const uint8_t* __restrict__ fix,
-                                                        const uint8_t* __restrict__ cfix,
+__global__ __launch_bounds__(kBlock) void k_restrict_p2(const int32_t* __restrict__ toff,
+                                                        const int32_t* __restrict__ tidx, int width,
+                                                        const T* __restrict__ pval, const uint8_t* __restrict__ cfix,
                                                         const T* __restrict__ x, T* __restrict__ y, int64_t na,
                                                         int nrhs) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t w = 3 * int64_t(nrhs);
-  if (i >= na * w) return;
-  const int64_t a = i / w;
-  const int64_t rem = i - a * w;
-  const int c = int(rem / nrhs);
+  const int64_t w3 = 3 * int64_t(nrhs);
+  if (i >= na * w3) return;
+  const int64_t a = i / w3;
+  const int64_t rem = i - a * w3;
+  const int q = int(rem / nrhs);
+  const int j = int(rem - int64_t(q) * nrhs);
   double acc = 0.0;
-  if (!((cfix[a] >> c) & 1))
-    for (int32_t k = moff[a]; k < moff[a + 1]; ++k) {
-      const int32_t v = mem[k];
-      if (!((fix[v] >> c) & 1)) acc += double(x[int64_t(v) * w + rem]);
+  if (!((cfix[a] >> q) & 1))
+    for (int32_t t = toff[a]; t < toff[a + 1]; ++t) {
+      const int64_t e = tidx[t];
+      const int64_t v = e / width;
+      const T* b = pval + e * 9 + q;
+      const T* xs = x + v * w3 + j;
+      acc += double(b[0]) * double(xs[0]) + double(b[3]) * double(xs[nrhs]) + double(b[6]) * double(xs[2 * nrhs]);
     }
   y[i] = T(acc);
 }
@@ -168,12 +180,13 @@ hipError_t launch_restrict(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void
 hipError_t launch_prolong_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, hipStream_t s) {
   const unsigned g = grid_for(m->n_vertices * 3 * nrhs);
   if (dt == EBE_F64)
-    hipLaunchKernelGGL(k_prolong_p2<double>, dim3(g), dim3(kBlock), 0, s, m->agg.as<int32_t>(),
-                       m->fix.as<uint8_t>(), static_cast<const double*>(x), static_cast<double*>(y), m->n_vertices,
-                       nrhs);
+    hipLaunchKernelGGL(k_prolong_p2<double>, dim3(g), dim3(kBlock), 0, s, m->p2_col.as<int32_t>(), m->p2_width,
+                       m->p2_val[0].as<double>(), static_cast<const double*>(x), static_cast<double*>(y),
+                       m->n_vertices, nrhs);
   else
-    hipLaunchKernelGGL(k_prolong_p2<float>, dim3(g), dim3(kBlock), 0, s, m->agg.as<int32_t>(), m->fix.as<uint8_t>(),
-                       static_cast<const float*>(x), static_cast<float*>(y), m->n_vertices, nrhs);
+    hipLaunchKernelGGL(k_prolong_p2<float>, dim3(g), dim3(kBlock), 0, s, m->p2_col.as<int32_t>(), m->p2_width,
+                       m->p2_val[1].as<float>(), static_cast<const float*>(x), static_cast<float*>(y), m->n_vertices,
+                       nrhs);
   return hipGetLastError();
 }
 
@@ -181,12 +194,12 @@ hipError_t launch_restrict_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const v
   if (m->n_agg < 1) return hipSuccess;
   const unsigned g = grid_for(m->n_agg * 3 * nrhs);
   if (dt == EBE_F64)
-    hipLaunchKernelGGL(k_restrict_p2<double>, dim3(g), dim3(kBlock), 0, s, m->mem_off.as<int32_t>(),
-                       m->mem.as<int32_t>(), m->fix.as<uint8_t>(), m->cfix.as<uint8_t>(),
+    hipLaunchKernelGGL(k_restrict_p2<double>, dim3(g), dim3(kBlock), 0, s, m->p2t_off.as<int32_t>(),
+                       m->p2t_idx.as<int32_t>(), m->p2_width, m->p2_val[0].as<double>(), m->cfix.as<uint8_t>(),
                        static_cast<const double*>(x), static_cast<double*>(y), m->n_agg, nrhs);
   else
-    hipLaunchKernelGGL(k_restrict_p2<float>, dim3(g), dim3(kBlock), 0, s, m->mem_off.as<int32_t>(),
-                       m->mem.as<int32_t>(), m->fix.as<uint8_t>(), m->cfix.as<uint8_t>(),
+    hipLaunchKernelGGL(k_restrict_p2<float>, dim3(g), dim3(kBlock), 0, s, m->p2t_off.as<int32_t>(),
+                       m->p2t_idx.as<int32_t>(), m->p2_width, m->p2_val[1].as<float>(), m->cfix.as<uint8_t>(),
                        static_cast<const float*>(x), static_cast<float*>(y), m->n_agg, nrhs);
   return hipGetLastError();
 }

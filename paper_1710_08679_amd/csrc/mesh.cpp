@@ -290,7 +290,7 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
   if (st == EBE_OK) st = upload(m->v2e_off, off.data(), off.size(), s);
   if (st == EBE_OK) st = upload(m->v2e_idx, idx.data(), std::max<size_t>(idx.size(), 1), s);
   if (st == EBE_OK) st = upload_asm(m->k1, Nv, soff, scol, s);
-  if (st == EBE_OK) st = build_level2(m, bptr, bcol, soff, fix.data(), s);
+  if (st == EBE_OK) st = build_level2(m, bptr, bcol, fix.data(), s);
   if (st == EBE_OK) st = m->lame64.alloc(size_t(E) * 2 * sizeof(double));
   if (st == EBE_OK) st = m->lame32.alloc(size_t(E) * 2 * sizeof(float));
   if (st == EBE_OK) st = build_patches(m, conn10, fix.data(), s);

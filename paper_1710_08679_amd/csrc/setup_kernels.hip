@@ -213,15 +213,72 @@ __global__ __launch_bounds__(kBlock) void k_assemble_p1(const int32_t* __restric
   }
 }
 
-// A2 += the free part of every K1 block: fine row v adds block (v, b) into
-// the A2 entry map[] names, rows of fixed (v, p) and columns of fixed (b, q)
-// left out (they are outside the range of P2).
-__global__ __launch_bounds__(kBlock) void k_assemble_a2(const int32_t* __restrict__ k1soff,
+// Level-2 prolongator P2 = (I - omega D1^-1 K1p) T, one work-item per fine
+// row v: slot w of the row (aggregate J) is [J = agg(v)] I_free(v)
+// - omega D1^-1(v) sum_{b in row v of K1, agg(b) = J} K1p(v, b), with K1p's
+// fixed rows and columns left out and D1^-1 the level-1 block-Jacobi inverse
+// (identity at fixed DOFs).  The sums are accumulated in the output row.
+constexpr double kOmega = 2.0 / 3.0;
+
+__global__ __launch_bounds__(kBlock) void k_smooth_p2(const int32_t* __restrict__ k1soff,
+                                                      const int32_t* __restrict__ k1col,
+                                                      const double* __restrict__ k1val,
+                                                      const uint8_t* __restrict__ fix,
+                                                      const int32_t* __restrict__ agg,
+                                                      const double* __restrict__ minv1,
+                                                      const int32_t* __restrict__ pcol, int width,
+                                                      double* __restrict__ p64, float* __restrict__ p32,
+                                                      int64_t nv) {
+  constexpr int S = kSliceRows;
+  const int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (v >= nv) return;
+  const int64_t sl = v / S;
+  const int r = int(v - sl * S);
+  const int fa = fix[v];
+  const int32_t* pc = pcol + size_t(v) * width;
+  double* out = p64 + size_t(v) * width * 9;
+  for (int i = 0; i < width * 9; ++i) out[i] = 0.0;
+  for (int32_t j = k1soff[sl]; j < k1soff[sl + 1]; ++j) {
+    const int32_t wd = k1col[size_t(j) * S + r];
+    const int fb = (wd >> kIdxBits) & 7;
+    const int32_t J = agg[wd & kIdxMask];
+    int w = 0;
+    while (w < width - 1 && pc[w] != J) ++w;  // present by construction
+    const double* blk = k1val + size_t(j) * 9 * S + r;
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q)
+        if (!((fa >> p) & 1) && !((fb >> q) & 1)) out[w * 9 + 3 * p + q] += blk[(3 * p + q) * S];
+  }
+  const double* m = minv1 + 6 * v;
+  const double D[3][3] = {{m[0], m[5], m[4]}, {m[5], m[1], m[3]}, {m[4], m[3], m[2]}};
+  const int32_t av = agg[v];
+  for (int w = 0; w < width; ++w) {
+    double B[9];
+    for (int i = 0; i < 9; ++i) B[i] = out[w * 9 + i];
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) {
+        double val = (pc[w] == av && p == q && !((fa >> p) & 1)) ? 1.0 : 0.0;
+        val -= kOmega * (D[p][0] * B[q] + D[p][1] * B[3 + q] + D[p][2] * B[6 + q]);
+        out[w * 9 + 3 * p + q] = val;
+        p32[size_t(v) * width * 9 + w * 9 + 3 * p + q] = float(val);
+      }
+  }
+}
+
+// A2 += P2(v, I)^T K1p(v, b) P2(b, J) for every K1 block (v, b) of fine row v
+// and every pair of slots of rows v and b (FP64 atomics); the entry (I, J) is
+// found by bisection in A2's row I (columns increasing over its first len
+// slots).
+__global__ __launch_bounds__(kBlock) void k_galerkin_a2(const int32_t* __restrict__ k1soff,
                                                         const int32_t* __restrict__ k1col,
                                                         const double* __restrict__ k1val,
                                                         const uint8_t* __restrict__ fix,
-                                                        const int32_t* __restrict__ map, double* __restrict__ a2val,
-                                                        int64_t nv) {
+                                                        const int32_t* __restrict__ pcol, int width,
+                                                        const double* __restrict__ p64,
+                                                        const int32_t* __restrict__ a2soff,
+                                                        const int32_t* __restrict__ a2col,
+                                                        const int32_t* __restrict__ a2len,
+                                                        double* __restrict__ a2val, int64_t nv) {
   constexpr int S = kSliceRows;
   const int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (v >= nv) return;
@@ -229,17 +286,44 @@ __global__ __launch_bounds__(kBlock) void k_assemble_a2(const int32_t* __restric
   const int r = int(v - sl * S);
   const int fa = fix[v];
   for (int32_t j = k1soff[sl]; j < k1soff[sl + 1]; ++j) {
-    const size_t e = size_t(j) * S + r;
-    const int32_t e2 = map[e];
-    if (e2 < 0) continue;
-    const int fb = (k1col[e] >> kIdxBits) & 7;
-    const double* src = k1val + size_t(j) * 9 * S + r;
-    double* dst = a2val + size_t(e2 / S) * 9 * S + (e2 % S);
-#pragma unroll
+    const int32_t wd = k1col[size_t(j) * S + r];
+    const int fb = (wd >> kIdxBits) & 7;
+    const int64_t b = wd & kIdxMask;
+    const double* blk = k1val + size_t(j) * 9 * S + r;
+    double T[3][3];
+    bool any = false;
     for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int q = 0; q < 3; ++q)
-        if (!((fa >> p) & 1) && !((fb >> q) & 1)) unsafeAtomicAdd(dst + (3 * p + q) * S, src[(3 * p + q) * S]);
+      for (int q = 0; q < 3; ++q) {
+        T[p][q] = (!((fa >> p) & 1) && !((fb >> q) & 1)) ? blk[(3 * p + q) * S] : 0.0;
+        any |= T[p][q] != 0.0;
+      }
+    if (!any) continue;  // padding, or a block wholly in fixed DOFs
+    for (int wi = 0; wi < width; ++wi) {
+      const int32_t I = pcol[size_t(v) * width + wi];
+      if (I < 0) break;
+      const double* PI = p64 + (size_t(v) * width + wi) * 9;
+      double L[3][3];  // P2(v, I)^T K1p(v, b)
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) L[p][q] = PI[0 * 3 + p] * T[0][q] + PI[1 * 3 + p] * T[1][q] + PI[2 * 3 + p] * T[2][q];
+      const int64_t sI = I / S;
+      const int rI = int(I - sI * S);
+      const int32_t k0 = a2soff[sI];
+      for (int wj = 0; wj < width; ++wj) {
+        const int32_t J = pcol[size_t(b) * width + wj];
+        if (J < 0) break;
+        const double* PJ = p64 + (size_t(b) * width + wj) * 9;
+        int32_t lo = 0, hi = a2len[I] - 1;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          if ((a2col[size_t(k0 + mid) * S + rI] & kIdxMask) < J) lo = mid + 1;
+          else hi = mid;
+        }
+        double* dst = a2val + size_t(k0 + lo) * 9 * S + rI;
+        for (int p = 0; p < 3; ++p)
+          for (int q = 0; q < 3; ++q)
+            unsafeAtomicAdd(dst + (3 * p + q) * S, L[p][0] * PJ[0 * 3 + q] + L[p][1] * PJ[1 * 3 + q] + L[p][2] * PJ[2 * 3 + q]);
+      }
+    }
   }
 }
 
@@ -324,11 +408,17 @@ hipError_t launch_invert_blocks(const ebe_mesh* m, int level, const double* blk6
 hipError_t launch_assemble_a2(const ebe_mesh* m, bool assemble, bool f32, hipStream_t s) {
   const int64_t nval = m->a2.slots * 9 * kSliceRows;
   if (assemble) {
-    hipError_t e = launch_fill_zero(m->a2.val[0].as<void>(), size_t(nval) * sizeof(double), s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_assemble_a2, dim3(grid_for(m->n_vertices)), dim3(kBlock), 0, s, m->k1.soff.as<int32_t>(),
+    hipLaunchKernelGGL(k_smooth_p2, dim3(grid_for(m->n_vertices)), dim3(kBlock), 0, s, m->k1.soff.as<int32_t>(),
                        m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(), m->fix.as<uint8_t>(),
-                       m->a2_map.as<int32_t>(), m->a2.val[0].as<double>(), m->n_vertices);
+                       m->agg.as<int32_t>(), m->minv64[1].as<double>(), m->p2_col.as<int32_t>(), m->p2_width,
+                       m->p2_val[0].as<double>(), m->p2_val[1].as<float>(), m->n_vertices);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_fill_zero(m->a2.val[0].as<void>(), size_t(nval) * sizeof(double), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_galerkin_a2, dim3(grid_for(m->n_vertices)), dim3(kBlock), 0, s, m->k1.soff.as<int32_t>(),
+                       m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(), m->fix.as<uint8_t>(),
+                       m->p2_col.as<int32_t>(), m->p2_width, m->p2_val[0].as<double>(), m->a2.soff.as<int32_t>(),
+                       m->a2.col.as<int32_t>(), m->a2_len.as<int32_t>(), m->a2.val[0].as<double>(), m->n_vertices);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -239,7 +239,7 @@ extern "C" {
 void ebe_pcg_default_opts(ebe_pcg_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
-  o->precond = EBE_PREC_MG2;
+  o->precond = EBE_PREC_MG3;
   o->mode = EBE_MODE_MIXED;
   o->tol = 1e-8;
   o->max_outer = 10000;

@@ -45,7 +45,7 @@ def test_status_strings_and_build_info(lib):
 def test_default_options_follow_table2(lib):
     g = json.load(open(os.path.join(ROOT, "tests", "golden", "table2_inner_loops.json")))
     o = ebe.default_opts()
-    assert o.precond == ebe.PREC_MG2 and o.mode == ebe.MODE_MIXED
+    assert o.precond == ebe.PREC_MG3 and o.mode == ebe.MODE_MIXED
     assert o.inner_eps[0] == g["levels"]["0"]["tolerance"]
     assert o.inner_eps[1] == g["levels"]["1"]["tolerance"]
     assert o.inner_max[0] == g["levels"]["0"]["max_iterations"]

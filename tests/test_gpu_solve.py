@@ -90,7 +90,7 @@ def test_crust_mixed_mg2_within_1e6(crust, coarse_guess):
 
 def test_crust_fp64_paths_within_1e10(crust):
     m, gm, f, K, ud = crust
-    for precond in (ebe.PREC_PCGE, ebe.PREC_MG2):
+    for precond in (ebe.PREC_PCGE, ebe.PREC_MG2, ebe.PREC_MG3):
         u, st = gm.solve(dev(f), precond=precond, mode=ebe.MODE_FP64, tol=1e-13)
         print(f"[crust FP64 precond={precond}] {st}", flush=True)
         assert st["status"] == ebe.OK
@@ -155,8 +155,8 @@ def test_full_size_crust_mixed_solve(gpu_lib):
     gm = ebe.Mesh.from_generated(m)
     fd = dev(f)
     print(f"[crust 96x96x48] DOF={m.n_dof}", flush=True)
-    u, st = gm.solve(fd, precond=ebe.PREC_MG2, mode=ebe.MODE_MIXED, tol=1e-8)
-    print(f"[crust 96x96x48 mixed MG2] {st}", flush=True)
+    u, st = gm.solve(fd, precond=ebe.PREC_MG3, mode=ebe.MODE_MIXED, tol=1e-8)
+    print(f"[crust 96x96x48 mixed MG3] {st}", flush=True)
     assert st["status"] == ebe.OK and st["max_rel_res"] <= 1e-8
     fixed = torch.from_numpy(m.fixed.astype(bool)).cuda()
     fb = fd.clone()
