@@ -1,8 +1,10 @@
 """GPU parity of level 2 (smoothed aggregation of the corner mesh) against the
 oracle, through the C ABI: the aggregates (bit-exact), P2 and P2^T, A2 x, the
 level-2 block Jacobi, and three-level solves against the direct solution.
-Bounds are relative to the absolute-value products (|P2| |x|, |P2|^T |K1p|
-|P2| |x|), which bound the rounding of the sums whatever their order."""
+Bounds are relative to the absolute values of the terms summed (|P2|+ |x|
+with |P2|+ = |T| + omega |D1^-1| |K1p| |T|, and |P2|+^T |K1p| |P2|+ |x|), which
+bound the rounding of the sums whatever their order."""
+import scipy.sparse as sp
 import numpy as np
 import pytest
 import torch
@@ -30,9 +32,13 @@ def lv2(gpu_lib):
     m = parity_mesh(9, 7, 5, seed=3, bc=True)
     K1 = fem.assemble(m.xyz, m.conn, m.young, m.poisson, order=1, n_nodes=m.n_vertices)
     agg, na, P2, A2, cfx = amg.level2(m.conn, m.n_vertices, K1, m.fixed)
-    absA = (abs(P2).T @ abs(amg.projected(K1, m.fixed)) @ abs(P2)).tocsr()
+    T = amg.prolongation_p2(agg, na, m.fixed)
+    K1p = abs(amg.projected(K1, m.fixed))
+    D = sp.block_diag(list(np.abs(solve.block_jacobi_inverse(K1, m.fixed[:m.n_vertices], m.n_vertices)))).tocsr()
+    absP = (abs(T) + amg.OMEGA * (D @ (K1p @ abs(T)))).tocsr()
+    absA = (absP.T @ K1p @ absP).tocsr()
     print(f"[level 2] Nv={m.n_vertices} aggregates={na}", flush=True)
-    return m, ebe.Mesh.from_generated(m), agg, na, P2, A2, cfx, absA
+    return m, ebe.Mesh.from_generated(m), agg, na, P2, A2, cfx, (absP, absA)
 
 
 def test_aggregates_equal_the_oracle(lv2):
@@ -42,18 +48,19 @@ def test_aggregates_equal_the_oracle(lv2):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_transfers_match_oracle(lv2, dtype):
-    m, gm, agg, na, P2, A2, cfx, absA = lv2
-    rng = meshgen.rng_for(93, 0)
-    x2 = rng.standard_normal((na, 3, 5)).astype(dtype)
-    x1 = rng.standard_normal((m.n_vertices, 3, 5)).astype(dtype)
+@pytest.mark.parametrize("nrhs", [5, 8, 16])
+def test_transfers_match_oracle(lv2, dtype, nrhs):
+    m, gm, agg, na, P2, A2, cfx, (absP, absA) = lv2
+    rng = meshgen.rng_for(93, nrhs)
+    x2 = rng.standard_normal((na, 3, nrhs)).astype(dtype)
+    x1 = rng.standard_normal((m.n_vertices, 3, nrhs)).astype(dtype)
     y1 = gm.prolong_l2(to_dev(x2, dtype)).cpu().numpy().astype(np.float64)
     y2 = gm.restrict_l2(to_dev(x1, dtype)).cpu().numpy().astype(np.float64)
     r1 = dof_apply(P2, x2.astype(np.float64))
     r2 = dof_apply(P2.T.tocsr(), x1.astype(np.float64))
     r2[cfx] = 0
-    b1 = dof_apply(abs(P2), np.abs(x2.astype(np.float64))) + 1e-300
-    b2 = dof_apply(abs(P2).T.tocsr(), np.abs(x1.astype(np.float64))) + 1e-300
+    b1 = dof_apply(absP, np.abs(x2.astype(np.float64))) + 1e-300
+    b2 = dof_apply(absP.T.tocsr(), np.abs(x1.astype(np.float64))) + 1e-300
     c = 1e-13 if dtype == np.float64 else 8 * float(np.finfo(np.float32).eps)
     assert np.max(np.abs(y1 - r1) / b1) <= c
     assert np.max(np.abs(y2 - r2) / b2) <= c
@@ -64,7 +71,7 @@ def test_transfers_match_oracle(lv2, dtype):
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nrhs", [1, 4, 7, 16])
 def test_a2_product_matches_oracle(lv2, dtype, nrhs):
-    m, gm, agg, na, P2, A2, cfx, absA = lv2
+    m, gm, agg, na, P2, A2, cfx, (absP, absA) = lv2
     x = meshgen.rng_for(94, nrhs).standard_normal((na, 3, nrhs)).astype(dtype)
     xd = x.astype(np.float64)
     y = gm.matvec_l2(to_dev(x, dtype)).cpu().numpy().astype(np.float64)
@@ -74,8 +81,8 @@ def test_a2_product_matches_oracle(lv2, dtype, nrhs):
     xm[cfx] = 0
     refb = dof_apply(A2, xm)
     refb[cfx] = 0
-    # |P2|^T |K1p| |P2| |x| bounds the rounding of the (summed, then rounded)
-    # blocks and of the products
+    # |P2|+^T |K1p| |P2|+ |x| bounds the rounding of the (summed, then
+    # rounded) blocks and of the products
     bound = dof_apply(absA, np.abs(xd)) + 1e-300
     c = 1e-12 if dtype == np.float64 else 64 * float(np.finfo(np.float32).eps)
     assert np.max(np.abs(y - ref) / bound) <= c
@@ -84,7 +91,7 @@ def test_a2_product_matches_oracle(lv2, dtype, nrhs):
 
 
 def test_level2_blocks_match_oracle(lv2):
-    m, gm, agg, na, P2, A2, cfx, absA = lv2
+    m, gm, agg, na, P2, A2, cfx, (absP, absA) = lv2
     got = gm.diag_blocks(2).cpu().numpy()
     ref = fem.diag_blocks(A2, na)
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
@@ -97,7 +104,7 @@ def test_level2_blocks_match_oracle(lv2):
 
 
 def test_level2_follows_a_material_change(lv2):
-    m, gm, agg, na, P2, A2, cfx, absA = lv2
+    m, gm, agg, na, P2, A2, cfx, (absP, absA) = lv2
     E2 = m.young * 1.7
     gm.set_material(to_dev(E2, np.float64), to_dev(m.poisson, np.float64))
     try:

@@ -143,11 +143,12 @@ def test_multi_rhs_equals_single_columns(small):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_grid_transfers_match_oracle(small, dtype):
+@pytest.mark.parametrize("nrhs", [3, 6, 16])
+def test_grid_transfers_match_oracle(small, dtype, nrhs):
     m, gm, _, _, kap = small
     P = fem.prolongation_p1(m.conn, m.n_nodes, m.n_vertices)
-    xc = meshgen.rng_for(84, 0).standard_normal((m.n_vertices, 3, 3)).astype(dtype)
-    xf = meshgen.rng_for(84, 1).standard_normal((m.n_nodes, 3, 3)).astype(dtype)
+    xc = meshgen.rng_for(84, 0).standard_normal((m.n_vertices, 3, nrhs)).astype(dtype)
+    xf = meshgen.rng_for(84, 1).standard_normal((m.n_nodes, 3, nrhs)).astype(dtype)
     yp = gm.prolong(to_dev(xc, dtype)).cpu().numpy().astype(np.float64)
     yr = gm.restrict(to_dev(xf, dtype)).cpu().numpy().astype(np.float64)
     rp = fem.apply_scalar_op(P, xc.astype(np.float64))
