@@ -145,3 +145,29 @@ def test_small_mg3_matches_oracle_three_level_solve(gpu_lib):
     assert st["status"] == ebe.OK
     # both converge to the same solution; iteration counts are not pinned
     assert np.linalg.norm(u.cpu().numpy() - uo) / np.linalg.norm(uo) <= 1e-8
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (2, 1, 1), (3, 2, 2)])
+def test_tiny_meshes_level2_and_mg3(gpu_lib, grid):
+    """One or a few aggregates (a single slice, ragged rows): aggregates,
+    A2 x and an MG3 solve against the dense solution."""
+    m = meshgen.kuhn_mesh(*grid, jitter=0.1, rng=meshgen.rng_for(97, sum(grid)))
+    meshgen.fix_faces(m, [(2, 0)])
+    K1 = fem.assemble(m.xyz, m.conn, m.young, m.poisson, order=1, n_nodes=m.n_vertices)
+    agg, na, P2, A2, cfx = amg.level2(m.conn, m.n_vertices, K1, m.fixed)
+    gm = ebe.Mesh.from_generated(m)
+    n, a = gm.level2_info()
+    assert n == na and np.array_equal(a, agg)
+    x = meshgen.rng_for(98, 0).standard_normal((na, 3, 2))
+    y = gm.matvec_l2(to_dev(x, np.float64), apply_bc=True).cpu().numpy()
+    xm = x.copy()
+    xm[cfx] = 0
+    ref = dof_apply(A2, xm)
+    ref[cfx] = 0
+    assert np.max(np.abs(y - ref)) <= 1e-12 * max(np.max(np.abs(ref)), 1e-300)
+    f = meshgen.top_face_random_loads(m, meshgen.rng_for(98, 1), nrhs=1)
+    K = fem.assemble(m.xyz, m.conn, m.young, m.poisson)
+    ud = solve.dense_solve(K, f, m.fixed)
+    u, st = gm.solve(torch.from_numpy(f).cuda(), precond=ebe.PREC_MG3, mode=ebe.MODE_MIXED, tol=1e-10)
+    assert st["status"] == ebe.OK
+    assert np.linalg.norm(u.cpu().numpy() - ud) <= 1e-8 * np.linalg.norm(ud)

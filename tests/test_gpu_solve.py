@@ -39,7 +39,8 @@ def test_small_cube_pcge_fp64_reaches_dense_solution(cube):
     assert rel_err(u2.cpu().numpy(), ud) <= 1e-10
 
 
-@pytest.mark.parametrize("precond,mode", [(ebe.PREC_MG2, ebe.MODE_MIXED), (ebe.PREC_MG2, ebe.MODE_FP64)])
+@pytest.mark.parametrize("precond,mode", [(ebe.PREC_MG2, ebe.MODE_MIXED), (ebe.PREC_MG2, ebe.MODE_FP64),
+                                          (ebe.PREC_MG3, ebe.MODE_MIXED), (ebe.PREC_MG3, ebe.MODE_FP64)])
 def test_small_cube_mg2(cube, precond, mode):
     m, gm, f, K, ud = cube
     u, st = gm.solve(dev(f), precond=precond, mode=mode, tol=1e-12)
