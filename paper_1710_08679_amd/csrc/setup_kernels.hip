@@ -243,7 +243,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_p2(const int32_t* __restrict_
     const int fb = (wd >> kIdxBits) & 7;
     const int32_t J = agg[wd & kIdxMask];
     int w = 0;
-    while (w < width - 1 && pc[w] != J) ++w;  // present by construction
+    while (w < width - 1 && pc[w] != J) ++w;
+    if (pc[w] != J) continue;  // cannot happen: the row lists every neighbour's aggregate
     const double* blk = k1val + size_t(j) * 9 * S + r;
     for (int p = 0; p < 3; ++p)
       for (int q = 0; q < 3; ++q)
@@ -318,6 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_galerkin_a2(const int32_t* __restric
           if ((a2col[size_t(k0 + mid) * S + rI] & kIdxMask) < J) lo = mid + 1;
           else hi = mid;
         }
+        if ((a2col[size_t(k0 + lo) * S + rI] & kIdxMask) != J) continue;  // cannot happen (structure)
         double* dst = a2val + size_t(k0 + lo) * 9 * S + rI;
         for (int p = 0; p < 3; ++p)
           for (int q = 0; q < 3; ++q)
