@@ -90,14 +90,17 @@ struct Workspace {
 
 // Element patches (patches.cpp): consecutive element ranges whose node sums
 // fit in LDS.  Quadratic level: at most kPatchElems elements touching at most
-// kPatchNodes nodes.  Linear level: at most kLinPatchElems elements touching
-// at most kLinPatchCorners corners (a linear element carries far less work,
-// so its patches are larger).
+// kPatchNodes nodes; 48 elements and 128 nodes fit a block of 2x2x2
+// hexahedra of 6 tetrahedra (5^3 = 125 nodes) exactly, so on meshes in
+// Morton order patches are compact blocks and fewer of their nodes are shared
+// than with 64-element ranges that cut hexahedra apart.  Linear level: at most
+// kLinPatchElems elements touching at most kLinPatchCorners corners (a linear
+// element carries far less work, so its patches are larger).
 #ifndef EBE_PATCH_ELEMS
-#define EBE_PATCH_ELEMS 64
+#define EBE_PATCH_ELEMS 48
 #endif
 #ifndef EBE_PATCH_NODES
-#define EBE_PATCH_NODES 192
+#define EBE_PATCH_NODES 128
 #endif
 #ifndef EBE_LIN_PATCH_ELEMS
 #define EBE_LIN_PATCH_ELEMS 256
@@ -108,12 +111,18 @@ struct Workspace {
 #ifndef EBE_PATCH_THREADS
 #define EBE_PATCH_THREADS 512
 #endif
+#ifndef EBE_PATCH_THREADS_F64
+#define EBE_PATCH_THREADS_F64 256
+#endif
 constexpr int kSliceRows = 64;  // rows per slice of an assembled operator (AsmOp)
 constexpr int kPatchElems = EBE_PATCH_ELEMS;
 constexpr int kPatchNodes = EBE_PATCH_NODES;
 constexpr int kLinPatchElems = EBE_LIN_PATCH_ELEMS;
 constexpr int kLinPatchCorners = EBE_LIN_PATCH_CORNERS;  // local ids are bytes: at most 256
 constexpr int kPatchThreads = EBE_PATCH_THREADS;  // workgroup size cap of the patch kernels
+// FP64 quadratic patches: smaller workgroups, so two fit per CU within the
+// registers the FP64 element operator needs (two wavefronts per SIMD)
+constexpr int kPatchThreadsF64 = EBE_PATCH_THREADS_F64;
 static_assert(kPatchNodes <= 256 && kLinPatchCorners <= 256, "patch-local node ids are bytes");
 // (x, K x) sums of the patch kernels: workgroup w adds its per-case sums to
 // slot w % kGammaSlots (one 128-byte line each), and the last workgroup to

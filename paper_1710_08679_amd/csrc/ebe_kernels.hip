@@ -72,10 +72,12 @@ constexpr int chunk_for(int nr, int order, int value_bytes, bool stage) {
 }
 
 // one work-item per (element, case) of a pass, at most kPatchThreads
+// (kPatchThreadsF64 for quadratic FP64 patches)
 constexpr int threads_for(int nr, int order, int value_bytes, bool stage) {
   const int want = ((order == 2 ? kPatchElems : kLinPatchElems) * chunk_for(nr, order, value_bytes, stage) + 63) /
                    64 * 64;
-  return want > kPatchThreads ? kPatchThreads : want;
+  const int cap = (order == 2 && value_bytes == 8) ? kPatchThreadsF64 : kPatchThreads;
+  return want > cap ? cap : want;
 }
 
 // LDS of one patch workgroup and the wavefronts per SIMD that LDS leaves
