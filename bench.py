@@ -149,6 +149,45 @@ def solver_block(torch, ebe, meshgen, modes=("mixed_mg3", "mixed_mg2", "fp64_mg2
 FORM_NAMES = {0: "gather", 1: "staged", 2: "pipelined", 3: "assembled"}
 
 
+def adjoint_block(torch, ebe, meshgen, steps, warmup):
+    """The adjoint workload: 64x64x32 hexes x 6 = 786,432 tets, lognormal moduli,
+    4 cases: the element-gradient kernel g_e = -sum_c lam_c,e^T (K_e/E_e) u_c,e
+    in FP64 and FP32, and one full dMisfit/dE (forward solve, adjoint solve,
+    kernel) through torch.autograd with default solver options (FP64 outer)."""
+    from paper_1710_08679_amd.autograd import surface_misfit
+    m = meshgen.adjoint_mesh(64, 64, 32)
+    gm = ebe.Mesh.from_generated(m)
+    n = 4
+    out = {"workload": "adjoint 64x64x32 hexes x 6 tets, lognormal E, 4 cases", "elements": m.n_elem, "runs": []}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        u = torch.randn((m.n_nodes, 3, n), dtype=torch.float64, device="cuda").to(dt)
+        lam = torch.randn((m.n_nodes, 3, n), dtype=torch.float64, device="cuda").to(dt)
+        g = torch.empty((m.n_elem,), dtype=dt, device="cuda")
+        t = time_launches(lambda i: gm.adjoint_grad(u, lam, out=g), steps, warmup, torch)
+        out["runs"].append({"kernel": "adjoint_grad", "dtype": name, "ms": t,
+                            "gelem_case_per_s": m.n_elem * n / (t * 1e-3) / 1e9,
+                            "input_gb_per_s": 2 * 3 * m.n_nodes * n * (8 if name == "f64" else 4) / (t * 1e-3) / 1e9})
+        print(f"# adjoint kernel {name} n={n}: {t:.3f} ms, {out['runs'][-1]['gelem_case_per_s']:.1f} Gelem*case/s",
+              file=sys.stderr, flush=True)
+    f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(4, 3), nrhs=n)
+    S = torch.from_numpy(meshgen.top_surface_dofs(m)).cuda()
+    d = 1e-3 * torch.randn((S.shape[0], n), dtype=torch.float64, device="cuda")
+    fd = torch.from_numpy(f).cuda()
+    pd = torch.from_numpy(m.poisson).cuda()
+    for rep_i in range(2):  # the first one sets up the level-2 operator and workspace
+        E = torch.from_numpy(m.young).cuda().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = surface_misfit(E, gm, pd, fd, S, d)
+        loss.backward()
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+    out["runs"].append({"kernel": "misfit + gradient (two solves + kernel)", "dtype": "mixed solves, f64 kernel",
+                        "seconds": dt_s})
+    print(f"# adjoint misfit + gradient: {dt_s:.3f} s", file=sys.stderr, flush=True)
+    return out
+
+
 def batch_block(torch, ebe, meshgen, n_mesh, with_big):
     """Batched uneven serving-size set: n_mesh crust meshes with log-uniform
     element counts in [5e4, 2e6] and 1..16 cases each (optionally plus the
@@ -197,6 +236,7 @@ def main():
     ap.add_argument("--variants", default="f64:1,f64:4,f64:16,f32:1,f32:4,f32:16",
                     help="comma list of dtype:n products to time")
     ap.add_argument("--no-solver", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--solver-modes", default="mixed_mg3,mixed_mg2,fp64_mg2,fp64_pcge")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=100000)
@@ -312,6 +352,8 @@ def main():
             "roofline": roof, "roofline_alt": alt, "variants": variants}
     if not args.no_solver:
         line["solver"] = solver_block(torch, ebe, meshgen, args.solver_modes.split(","))
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_block(torch, ebe, meshgen, args.steps, args.warmup)
     if args.batch > 0:
         line["batch"] = batch_block(torch, ebe, meshgen, args.batch, args.batch_big)
     if not args.no_cpu:
