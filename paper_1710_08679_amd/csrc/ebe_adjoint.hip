@@ -42,22 +42,21 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const int32_t* __restrict__ 
                                 xv[cw[3] & kIdxMask], G);
     const auto lm = lame[e];
     const T s = V * T(0.05) / T(young[e]);
-    T ue[10][3];
+    // streaming element operator: nodal values read as needed, each nodal
+    // force contracted with the adjoint state as soon as it is known
+    T unused = T(0);
+    p2_apply<T>(
+        G, T(lm.x) * s, T(lm.y) * s,
+        [&](int a, int c) -> T {
+          return ((cw[a] >> (kIdxBits + c)) & 1) ? T(0) : u[size_t(cw[a] & kIdxMask) * (3 * NR) + c * NR + r];
+        },
+        [&](int a, const T f[3]) {
+          const T* p = lam + size_t(cw[a] & kIdxMask) * (3 * NR) + r;
 #pragma unroll
-    for (int a = 0; a < 10; ++a) {
-      const T* p = u + size_t(cw[a] & kIdxMask) * (3 * NR) + r;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) ue[a][c] = ((cw[a] >> (kIdxBits + c)) & 1) ? T(0) : p[c * NR];
-    }
-    T f[10][3];
-    p2_forces<T>(G, T(lm.x) * s, T(lm.y) * s, ue, f);
-#pragma unroll
-    for (int a = 0; a < 10; ++a) {
-      const T* p = lam + size_t(cw[a] & kIdxMask) * (3 * NR) + r;
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        if (!((cw[a] >> (kIdxBits + c)) & 1)) acc += p[c * NR] * f[a][c];
-    }
+          for (int c = 0; c < 3; ++c)
+            if (!((cw[a] >> (kIdxBits + c)) & 1)) acc += p[c * NR] * f[c];
+        },
+        false, unused);
   }
 #pragma unroll
   for (int off = 1; off < NR; off <<= 1) acc += __shfl_xor(acc, off, NR);
@@ -84,22 +83,19 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_loop(const int32_t* __restri
   const T s = V * T(0.05) / T(young[e]);
   T acc = T(0);
   for (int r = 0; r < nrhs; ++r) {
-    T ue[10][3];
+    T unused = T(0);
+    p2_apply<T>(
+        G, T(lm.x) * s, T(lm.y) * s,
+        [&](int a, int c) -> T {
+          return ((cw[a] >> (kIdxBits + c)) & 1) ? T(0) : u[size_t(cw[a] & kIdxMask) * 3 * nrhs + c * nrhs + r];
+        },
+        [&](int a, const T f[3]) {
+          const T* p = lam + size_t(cw[a] & kIdxMask) * 3 * nrhs + r;
 #pragma unroll
-    for (int a = 0; a < 10; ++a) {
-      const T* p = u + size_t(cw[a] & kIdxMask) * 3 * nrhs + r;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) ue[a][c] = ((cw[a] >> (kIdxBits + c)) & 1) ? T(0) : p[c * nrhs];
-    }
-    T f[10][3];
-    p2_forces<T>(G, T(lm.x) * s, T(lm.y) * s, ue, f);
-#pragma unroll
-    for (int a = 0; a < 10; ++a) {
-      const T* p = lam + size_t(cw[a] & kIdxMask) * 3 * nrhs + r;
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        if (!((cw[a] >> (kIdxBits + c)) & 1)) acc += p[c * nrhs] * f[a][c];
-    }
+          for (int c = 0; c < 3; ++c)
+            if (!((cw[a] >> (kIdxBits + c)) & 1)) acc += p[c * nrhs] * f[c];
+        },
+        false, unused);
   }
   g[e] = -acc;
 }
