@@ -188,6 +188,7 @@ struct ebe_mesh {
   // per aggregate, and A2 = P2^T K1p P2 with its rows' lengths
   int64_t n_agg = 0;
   int32_t p2_width = 0;
+  int32_t a2_maxlen = 0;  // longest row of A2 (blocks)
   ebe::DBuf agg;        // int32 [Nv]
   ebe::DBuf cfix;       // uint8 [Na]
   ebe::DBuf p2_col;     // int32 [Nv][p2_width]

@@ -329,6 +329,79 @@ __global__ __launch_bounds__(kBlock) void k_galerkin_a2(const int32_t* __restric
   }
 }
 
+// The same sum by coarse rows, without global atomics: one wavefront per row
+// I of A2, which walks the P2 entries (v, I) (the transposed prolongator)
+// and v's K1 blocks (v, b), and adds P2(v, I)^T K1p(v, b) P2(b, J) into the
+// row's blocks held in LDS (columns found by bisection in the row's column
+// list), then writes the row.  Used when the longest row fits the LDS.
+constexpr int kGalerkinThreads = 64;
+constexpr int kGalerkinMaxRow = 800;  // row sums and columns within 64 KB of LDS
+
+__global__ __launch_bounds__(kGalerkinThreads) void k_galerkin_rows(
+    const int32_t* __restrict__ k1soff, const int32_t* __restrict__ k1col, const double* __restrict__ k1val,
+    const uint8_t* __restrict__ fix, const int32_t* __restrict__ pcol, int width, const double* __restrict__ p64,
+    const int32_t* __restrict__ toff, const int32_t* __restrict__ tidx, const int32_t* __restrict__ a2soff,
+    const int32_t* __restrict__ a2col, const int32_t* __restrict__ a2len, double* __restrict__ a2val,
+    int64_t na) {
+  constexpr int S = kSliceRows;
+  extern __shared__ double lds[];  // [len][9] block sums, then [len] column ids
+  const int64_t I = blockIdx.x;
+  if (I >= na) return;
+  const int tid = threadIdx.x;
+  const int64_t sI = I / S;
+  const int rI = int(I - sI * S);
+  const int len = a2len[I];
+  const int32_t k0 = a2soff[sI];
+  double* acc = lds;
+  int32_t* cols = reinterpret_cast<int32_t*>(lds + size_t(len) * 9);
+  for (int i = tid; i < len; i += kGalerkinThreads) cols[i] = a2col[size_t(k0 + i) * S + rI] & kIdxMask;
+  for (int i = tid; i < len * 9; i += kGalerkinThreads) acc[i] = 0.0;
+  __syncthreads();
+  for (int32_t t = toff[I] + tid; t < toff[I + 1]; t += kGalerkinThreads) {
+    const int64_t e = tidx[t];
+    const int64_t v = e / width;
+    const double* PI = p64 + e * 9;
+    const int fa = fix[v];
+    const int64_t sl = v / S;
+    const int r = int(v - sl * S);
+    for (int32_t j = k1soff[sl]; j < k1soff[sl + 1]; ++j) {
+      const int32_t wd = k1col[size_t(j) * S + r];
+      const int fb = (wd >> kIdxBits) & 7;
+      const int64_t b = wd & kIdxMask;
+      const double* blk = k1val + size_t(j) * 9 * S + r;
+      double T[3][3];
+      bool any = false;
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) {
+          T[p][q] = (!((fa >> p) & 1) && !((fb >> q) & 1)) ? blk[(3 * p + q) * S] : 0.0;
+          any |= T[p][q] != 0.0;
+        }
+      if (!any) continue;
+      double L[3][3];  // P2(v, I)^T K1p(v, b)
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) L[p][q] = PI[0 * 3 + p] * T[0][q] + PI[1 * 3 + p] * T[1][q] + PI[2 * 3 + p] * T[2][q];
+      for (int wj = 0; wj < width; ++wj) {
+        const int32_t J = pcol[b * width + wj];
+        if (J < 0) break;
+        int lo = 0, hi = len - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (cols[mid] < J) lo = mid + 1;
+          else hi = mid;
+        }
+        if (cols[lo] != J) continue;  // cannot happen (structure)
+        const double* PJ = p64 + (b * width + wj) * 9;
+        for (int p = 0; p < 3; ++p)
+          for (int q = 0; q < 3; ++q)
+            atomicAdd(acc + lo * 9 + 3 * p + q, L[p][0] * PJ[0 * 3 + q] + L[p][1] * PJ[1 * 3 + q] + L[p][2] * PJ[2 * 3 + q]);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < len * 9; i += kGalerkinThreads)
+    a2val[(size_t(k0 + i / 9) * 9 + i % 9) * S + rI] = acc[i];
+}
+
 // diagonal 3x3 blocks of an assembled operator as (xx yy zz yz zx xy)
 __global__ __launch_bounds__(kBlock) void k_asm_diag(const int32_t* __restrict__ soff,
                                                      const int32_t* __restrict__ col,
@@ -417,10 +490,20 @@ hipError_t launch_assemble_a2(const ebe_mesh* m, bool assemble, bool f32, hipStr
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = launch_fill_zero(m->a2.val[0].as<void>(), size_t(nval) * sizeof(double), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_galerkin_a2, dim3(grid_for(m->n_vertices)), dim3(kBlock), 0, s, m->k1.soff.as<int32_t>(),
-                       m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(), m->fix.as<uint8_t>(),
-                       m->p2_col.as<int32_t>(), m->p2_width, m->p2_val[0].as<double>(), m->a2.soff.as<int32_t>(),
-                       m->a2.col.as<int32_t>(), m->a2_len.as<int32_t>(), m->a2.val[0].as<double>(), m->n_vertices);
+    if (m->a2_maxlen <= kGalerkinMaxRow) {
+      const size_t lds = size_t(m->a2_maxlen) * (9 * sizeof(double) + sizeof(int32_t));
+      hipLaunchKernelGGL(k_galerkin_rows, dim3(unsigned(m->n_agg)), dim3(kGalerkinThreads), lds, s,
+                         m->k1.soff.as<int32_t>(), m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(),
+                         m->fix.as<uint8_t>(), m->p2_col.as<int32_t>(), m->p2_width, m->p2_val[0].as<double>(),
+                         m->p2t_off.as<int32_t>(), m->p2t_idx.as<int32_t>(), m->a2.soff.as<int32_t>(),
+                         m->a2.col.as<int32_t>(), m->a2_len.as<int32_t>(), m->a2.val[0].as<double>(), m->n_agg);
+    } else {
+      hipLaunchKernelGGL(k_galerkin_a2, dim3(grid_for(m->n_vertices)), dim3(kBlock), 0, s,
+                         m->k1.soff.as<int32_t>(), m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(),
+                         m->fix.as<uint8_t>(), m->p2_col.as<int32_t>(), m->p2_width, m->p2_val[0].as<double>(),
+                         m->a2.soff.as<int32_t>(), m->a2.col.as<int32_t>(), m->a2_len.as<int32_t>(),
+                         m->a2.val[0].as<double>(), m->n_vertices);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
