@@ -7,7 +7,9 @@
  * (Section 2, Eq. (3)) on 10-node tetrahedra with isotropic linear
  * elasticity (Eq. (1a-c)) and per-element moduli, applied to n load cases
  * at once (Section 3.1), inside the adaptive conjugate-gradient solver of
- * Algorithm 1 (FP64 outer loop, two-level FP32 multigrid inner loops).
+ * Algorithm 1 (FP64 outer loop, FP32 multigrid inner loops on the quadratic
+ * mesh, its corner-only linear mesh and an algebraic coarsening of the
+ * latter).
  * Element matrices are never stored: they are rebuilt from vertex
  * coordinates and material at every product (Section 2, EBE method).
  *
@@ -19,7 +21,8 @@
  * - Multi-case vectors use the layout [node][component][rhs], rhs fastest
  *   (Section 3.1: the case index is the innermost, contiguous loop), so a
  *   vector of n cases on N nodes holds 3*N*n values.  Quadratic-level vectors
- *   have N = n_nodes; linear-level (corner-only) vectors have N = n_vertices.
+ *   have N = n_nodes; linear-level (corner-only) vectors have N = n_vertices;
+ *   level-2 vectors have N = the number of aggregates (ebe_level2_info).
  * - Buffers must not overlap unless stated.  Device buffers must be 16-byte
  *   aligned (every hipMalloc / torch allocation is); a misaligned one is
  *   rejected with EBE_ERR_ARG.
