@@ -160,6 +160,8 @@ struct ebe_mesh {
   ebe::DBuf edge_ends;  // int32 [N-Nv][2]
   ebe::DBuf v2e_off;    // int32 [Nv+1] corner -> incident edge nodes (CSR)
   ebe::DBuf v2e_idx;    // int32 [2 (N-Nv)]
+  ebe::DBuf v2el_off;   // int32 [Nv+1] corner -> incident elements (CSR)
+  ebe::DBuf v2el;       // int32 [4E] element * 4 + the corner's local index, by element
   // element patches of the two levels
   ebe::DBuf lconn;      // uint8 [E][16] quadratic-patch-local ids of the 10 nodes (padded to 16 bytes)
   ebe::DBuf lconn1;     // uint8 [E][4]  linear-patch-local ids of the 4 corners

@@ -220,6 +220,21 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
     }
   }
 
+  // corner -> incident elements (CSR, by element), for the row-wise K1 assembly
+  if (4 * E >= (int64_t(1) << 31)) {
+    set_error("ebe_mesh_create: too many elements for 32-bit corner incidence lists");
+    return EBE_ERR_ARG;
+  }
+  std::vector<int32_t> veoff(Nv + 1, 0), vel(size_t(4 * E));
+  for (int64_t e = 0; e < E; ++e)
+    for (int a = 0; a < 4; ++a) veoff[conn10[10 * e + a] + 1]++;
+  for (int64_t v = 0; v < Nv; ++v) veoff[v + 1] += veoff[v];
+  {
+    std::vector<int32_t> fill(veoff.begin(), veoff.end() - 1);
+    for (int64_t e = 0; e < E; ++e)
+      for (int a = 0; a < 4; ++a) vel[fill[conn10[10 * e + a]]++] = int32_t(4 * e + a);
+  }
+
   // node fix bits and packed connectivity
   std::vector<uint8_t> fix(N, 0);
   bool any_bc = false;
@@ -289,6 +304,8 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
   if (st == EBE_OK) st = upload(m->edge_ends, ends.data(), std::max<size_t>(ends.size(), 1), s);
   if (st == EBE_OK) st = upload(m->v2e_off, off.data(), off.size(), s);
   if (st == EBE_OK) st = upload(m->v2e_idx, idx.data(), std::max<size_t>(idx.size(), 1), s);
+  if (st == EBE_OK) st = upload(m->v2el_off, veoff.data(), veoff.size(), s);
+  if (st == EBE_OK) st = upload(m->v2el, vel.data(), vel.size(), s);
   if (st == EBE_OK) st = upload_asm(m->k1, Nv, soff, scol, s);
   if (st == EBE_OK) st = build_level2(m, bptr, bcol, fix.data(), s);
   if (st == EBE_OK) st = m->lame64.alloc(size_t(E) * 2 * sizeof(double));

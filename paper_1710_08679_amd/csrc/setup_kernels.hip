@@ -173,46 +173,6 @@ __global__ __launch_bounds__(kBlock) void k_geometry(const int32_t* __restrict__
   o[15] = T(0);
 }
 
-// K1_e of element i added into the assembled K1: block (a, b) of the linear
-// tetrahedron is V [lambda G_a G_b^T + mu (G_a . G_b) I + mu G_b G_a^T]
-// (f_a = V sigma G_a with sigma from the constant strain; the same operator
-// p1_forces applies), found in row a by a scan of its slice's (short) slots;
-// the first match is the row's own entry, padding comes after it.
-__global__ __launch_bounds__(kBlock) void k_assemble_p1(const int32_t* __restrict__ conn, const double4* __restrict__ xv,
-                                                        const double2* __restrict__ lame,
-                                                        const int32_t* __restrict__ soff,
-                                                        const int32_t* __restrict__ col, double* __restrict__ val,
-                                                        int64_t n) {
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= n) return;
-  int v[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) v[a] = conn[i * 10 + a] & kIdxMask;
-  double G[4][3];
-  const double V = tet_geometry<double>(xv[v[0]], xv[v[1]], xv[v[2]], xv[v[3]], G);
-  const double2 lm = lame[i];
-  const double cl = lm.x * V, cm = lm.y * V;
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int sl = v[a] / kSliceRows, r = v[a] - sl * kSliceRows;
-    const int j0 = soff[sl], j1 = soff[sl + 1];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int j = j0;
-      while (j < j1 && (col[size_t(j) * kSliceRows + r] & kIdxMask) != v[b]) ++j;
-      if (j == j1) continue;  // cannot happen for a consistent structure
-      const double gg = G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2];
-      double* blk = val + size_t(j) * 9 * kSliceRows + r;
-#pragma unroll
-      for (int p = 0; p < 3; ++p)
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-          unsafeAtomicAdd(blk + (3 * p + q) * kSliceRows,
-                          cl * G[a][p] * G[b][q] + cm * G[a][q] * G[b][p] + (p == q ? cm * gg : 0.0));
-    }
-  }
-}
-
 // Level-2 prolongator P2 = (I - omega D1^-1 K1p) T, one work-item per fine
 // row v: slot w of the row (aggregate J) is [J = agg(v)] I_free(v)
 // - omega D1^-1(v) sum_{b in row v of K1, agg(b) = J} K1p(v, b), with K1p's
@@ -427,6 +387,53 @@ __global__ __launch_bounds__(kBlock) void k_asm_diag(const int32_t* __restrict__
     }
 }
 
+// K1 by rows, without atomics: one work-item per corner v writes its row's
+// blocks, summing for each element around v (the corner's element list,
+// each entry element * 4 + local corner a) the blocks (a, b) of the linear
+// tetrahedron, V [lambda G_a G_b^T + mu (G_a . G_b) I + mu G_b G_a^T]
+// (f_a = V sigma G_a with sigma from the constant strain; the operator
+// p1_forces applies), each found in the row by a scan of its (short) slot
+// list; padding slots stay zero.  The rows of a wavefront are the 64
+// rows of one slice, so each value access of the wavefront is one
+// contiguous run.
+__global__ __launch_bounds__(kBlock) void k_assemble_p1_rows(const int32_t* __restrict__ conn,
+                                                             const double4* __restrict__ xv,
+                                                             const double2* __restrict__ lame,
+                                                             const int32_t* __restrict__ voff,
+                                                             const int32_t* __restrict__ vel,
+                                                             const int32_t* __restrict__ soff,
+                                                             const int32_t* __restrict__ col,
+                                                             double* __restrict__ val, int64_t nv) {
+  constexpr int S = kSliceRows;
+  const int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (v >= nv) return;
+  const int64_t sl = v / S;
+  const int r = int(v - sl * S);
+  const int32_t j0 = soff[sl], j1 = soff[sl + 1];
+  for (int32_t j = j0; j < j1; ++j)
+    for (int i = 0; i < 9; ++i) val[(size_t(j) * 9 + i) * S + r] = 0.0;
+  for (int32_t t = voff[v]; t < voff[v + 1]; ++t) {
+    const int64_t el = vel[t] >> 2;
+    const int a = vel[t] & 3;
+    int w[4];
+    for (int k = 0; k < 4; ++k) w[k] = conn[el * 10 + k] & kIdxMask;
+    double G[4][3];
+    const double V = tet_geometry<double>(xv[w[0]], xv[w[1]], xv[w[2]], xv[w[3]], G);
+    const double2 lm = lame[el];
+    const double cl = lm.x * V, cm = lm.y * V;
+    for (int b = 0; b < 4; ++b) {
+      int32_t j = j0;
+      while (j < j1 && (col[size_t(j) * S + r] & kIdxMask) != w[b]) ++j;
+      if (j == j1) continue;  // cannot happen for a consistent structure
+      const double gg = G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2];
+      double* blk = val + size_t(j) * 9 * S + r;
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q)
+          blk[(3 * p + q) * S] += cl * G[a][p] * G[b][q] + cm * G[a][q] * G[b][p] + (p == q ? cm * gg : 0.0);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
     b[i] = float(a[i]);
@@ -546,12 +553,11 @@ hipError_t launch_geometry(const ebe_mesh* m, ebe_dtype dt, void* out, hipStream
 hipError_t launch_assemble_p1(const ebe_mesh* m, bool assemble, bool f32, hipStream_t s) {
   const int64_t nval = m->k1.slots * 9 * kSliceRows;
   if (assemble) {
-    hipError_t e = launch_fill_zero(m->k1.val[0].as<void>(), size_t(nval) * sizeof(double), s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_assemble_p1, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s, m->conn.as<int32_t>(),
-                       m->xv.as<double4>(), m->lame64.as<double2>(), m->k1.soff.as<int32_t>(),
-                       m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(), m->n_elem);
-    e = hipGetLastError();
+    hipLaunchKernelGGL(k_assemble_p1_rows, dim3(grid_for(m->n_vertices)), dim3(kBlock), 0, s,
+                       m->conn.as<int32_t>(), m->xv.as<double4>(), m->lame64.as<double2>(),
+                       m->v2el_off.as<int32_t>(), m->v2el.as<int32_t>(), m->k1.soff.as<int32_t>(),
+                       m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(), m->n_vertices);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (!f32) return hipSuccess;
