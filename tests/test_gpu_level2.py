@@ -135,6 +135,18 @@ def test_crust_mg3_within_1e6(crust3, mode):
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("nrhs", [3, 7])
+def test_crust_mg3_odd_case_counts(crust3, nrhs):
+    """Case counts that are not powers of two (one case per work-item in the
+    assembled and transfer kernels, workgroups of 3 * 85 and 7 * 36 lanes)."""
+    m, gm, f, ud = crust3
+    fs = np.ascontiguousarray(f[:, :, :nrhs])
+    u, st = gm.solve(torch.from_numpy(fs).cuda(), precond=ebe.PREC_MG3, mode=ebe.MODE_MIXED, tol=1e-8)
+    assert st["status"] == ebe.OK and st["max_rel_res"] <= 1e-8
+    err = np.linalg.norm(u.cpu().numpy() - ud[:, :, :nrhs]) / np.linalg.norm(ud[:, :, :nrhs])
+    assert err <= 1e-6
+
+
 def test_small_mg3_matches_oracle_three_level_solve(gpu_lib):
     m = meshgen.crust_mesh(6, 6, 3)
     f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(3, 2), nrhs=4)
