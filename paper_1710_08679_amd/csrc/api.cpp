@@ -72,6 +72,10 @@ ebe_status ensure_assembled(ebe_mesh* m, ebe_dtype dt, hipStream_t s) {
 ebe_status ensure_level2(ebe_mesh* m, ebe_dtype dt, hipStream_t s) {
   const int k = dt == EBE_F64 ? 0 : 1;
   if (m->a2.ready[k]) return EBE_OK;
+  if (m->a2_maxlen > kA2MaxRow) {
+    set_error("level 2: a coarse row couples %d aggregates (at most %d); use MG2", m->a2_maxlen, kA2MaxRow);
+    return EBE_ERR_ARG;
+  }
   // P2 and A2 are formed from the FP64 K1 blocks and the level-1 block Jacobi
   ebe_status st = ensure_assembled(m, EBE_F64, s);
   if (st == EBE_OK) st = ensure_blocks(m, s);

@@ -170,6 +170,7 @@ ebe_status build_level2(ebe_mesh* m, const std::vector<int32_t>& bptr, const std
   m->n_agg = na;
   m->p2_width = width;
   m->a2_maxlen = alen.empty() ? 0 : *std::max_element(alen.begin(), alen.end());
+
   if ((st = up(m->agg, agg, s)) != EBE_OK) return st;
   if ((st = up(m->cfix, cfix, s)) != EBE_OK) return st;
   if ((st = up(m->p2_col, pcol, s)) != EBE_OK) return st;

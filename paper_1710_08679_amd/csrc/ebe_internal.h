@@ -115,6 +115,7 @@ struct Workspace {
 #define EBE_PATCH_THREADS_F64 256
 #endif
 constexpr int kSliceRows = 64;  // rows per slice of an assembled operator (AsmOp)
+constexpr int kA2MaxRow = 800;  // longest level-2 row (blocks) whose sums fit 64 KB of LDS
 constexpr int kPatchElems = EBE_PATCH_ELEMS;
 constexpr int kPatchNodes = EBE_PATCH_NODES;
 constexpr int kLinPatchElems = EBE_LIN_PATCH_ELEMS;

@@ -226,76 +226,14 @@ __global__ __launch_bounds__(kBlock) void k_smooth_p2(const int32_t* __restrict_
   }
 }
 
-// A2 += P2(v, I)^T K1p(v, b) P2(b, J) for every K1 block (v, b) of fine row v
-// and every pair of slots of rows v and b (FP64 atomics); the entry (I, J) is
-// found by bisection in A2's row I (columns increasing over its first len
-// slots).
-__global__ __launch_bounds__(kBlock) void k_galerkin_a2(const int32_t* __restrict__ k1soff,
-                                                        const int32_t* __restrict__ k1col,
-                                                        const double* __restrict__ k1val,
-                                                        const uint8_t* __restrict__ fix,
-                                                        const int32_t* __restrict__ pcol, int width,
-                                                        const double* __restrict__ p64,
-                                                        const int32_t* __restrict__ a2soff,
-                                                        const int32_t* __restrict__ a2col,
-                                                        const int32_t* __restrict__ a2len,
-                                                        double* __restrict__ a2val, int64_t nv) {
-  constexpr int S = kSliceRows;
-  const int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (v >= nv) return;
-  const int64_t sl = v / S;
-  const int r = int(v - sl * S);
-  const int fa = fix[v];
-  for (int32_t j = k1soff[sl]; j < k1soff[sl + 1]; ++j) {
-    const int32_t wd = k1col[size_t(j) * S + r];
-    const int fb = (wd >> kIdxBits) & 7;
-    const int64_t b = wd & kIdxMask;
-    const double* blk = k1val + size_t(j) * 9 * S + r;
-    double T[3][3];
-    bool any = false;
-    for (int p = 0; p < 3; ++p)
-      for (int q = 0; q < 3; ++q) {
-        T[p][q] = (!((fa >> p) & 1) && !((fb >> q) & 1)) ? blk[(3 * p + q) * S] : 0.0;
-        any |= T[p][q] != 0.0;
-      }
-    if (!any) continue;  // padding, or a block wholly in fixed DOFs
-    for (int wi = 0; wi < width; ++wi) {
-      const int32_t I = pcol[size_t(v) * width + wi];
-      if (I < 0) break;
-      const double* PI = p64 + (size_t(v) * width + wi) * 9;
-      double L[3][3];  // P2(v, I)^T K1p(v, b)
-      for (int p = 0; p < 3; ++p)
-        for (int q = 0; q < 3; ++q) L[p][q] = PI[0 * 3 + p] * T[0][q] + PI[1 * 3 + p] * T[1][q] + PI[2 * 3 + p] * T[2][q];
-      const int64_t sI = I / S;
-      const int rI = int(I - sI * S);
-      const int32_t k0 = a2soff[sI];
-      for (int wj = 0; wj < width; ++wj) {
-        const int32_t J = pcol[size_t(b) * width + wj];
-        if (J < 0) break;
-        const double* PJ = p64 + (size_t(b) * width + wj) * 9;
-        int32_t lo = 0, hi = a2len[I] - 1;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          if ((a2col[size_t(k0 + mid) * S + rI] & kIdxMask) < J) lo = mid + 1;
-          else hi = mid;
-        }
-        if ((a2col[size_t(k0 + lo) * S + rI] & kIdxMask) != J) continue;  // cannot happen (structure)
-        double* dst = a2val + size_t(k0 + lo) * 9 * S + rI;
-        for (int p = 0; p < 3; ++p)
-          for (int q = 0; q < 3; ++q)
-            unsafeAtomicAdd(dst + (3 * p + q) * S, L[p][0] * PJ[0 * 3 + q] + L[p][1] * PJ[1 * 3 + q] + L[p][2] * PJ[2 * 3 + q]);
-      }
-    }
-  }
-}
-
-// The same sum by coarse rows, without global atomics: one wavefront per row
-// I of A2, which walks the P2 entries (v, I) (the transposed prolongator)
-// and v's K1 blocks (v, b), and adds P2(v, I)^T K1p(v, b) P2(b, J) into the
-// row's blocks held in LDS (columns found by bisection in the row's column
-// list), then writes the row.  Used when the longest row fits the LDS.
+// A2 = P2^T K1p P2 by coarse rows, without global atomics: one wavefront per
+// row I of A2 walks the P2 entries (v, I) (the transposed prolongator) and
+// v's K1 blocks (v, b), and adds P2(v, I)^T K1p(v, b) P2(b, J) for every
+// slot J of P2's row b into the row's blocks held in LDS (columns found by
+// bisection in the row's column list), then writes the row.  Level 2 is
+// refused (MG2 remains) on a mesh whose longest A2 row does not fit the LDS.
 constexpr int kGalerkinThreads = 64;
-constexpr int kGalerkinMaxRow = 800;  // row sums and columns within 64 KB of LDS
+constexpr int kGalerkinMaxRow = kA2MaxRow;
 
 __global__ __launch_bounds__(kGalerkinThreads) void k_galerkin_rows(
     const int32_t* __restrict__ k1soff, const int32_t* __restrict__ k1col, const double* __restrict__ k1val,
@@ -497,20 +435,13 @@ hipError_t launch_assemble_a2(const ebe_mesh* m, bool assemble, bool f32, hipStr
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = launch_fill_zero(m->a2.val[0].as<void>(), size_t(nval) * sizeof(double), s);
     if (e != hipSuccess) return e;
-    if (m->a2_maxlen <= kGalerkinMaxRow) {
-      const size_t lds = size_t(m->a2_maxlen) * (9 * sizeof(double) + sizeof(int32_t));
-      hipLaunchKernelGGL(k_galerkin_rows, dim3(unsigned(m->n_agg)), dim3(kGalerkinThreads), lds, s,
-                         m->k1.soff.as<int32_t>(), m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(),
-                         m->fix.as<uint8_t>(), m->p2_col.as<int32_t>(), m->p2_width, m->p2_val[0].as<double>(),
-                         m->p2t_off.as<int32_t>(), m->p2t_idx.as<int32_t>(), m->a2.soff.as<int32_t>(),
-                         m->a2.col.as<int32_t>(), m->a2_len.as<int32_t>(), m->a2.val[0].as<double>(), m->n_agg);
-    } else {
-      hipLaunchKernelGGL(k_galerkin_a2, dim3(grid_for(m->n_vertices)), dim3(kBlock), 0, s,
-                         m->k1.soff.as<int32_t>(), m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(),
-                         m->fix.as<uint8_t>(), m->p2_col.as<int32_t>(), m->p2_width, m->p2_val[0].as<double>(),
-                         m->a2.soff.as<int32_t>(), m->a2.col.as<int32_t>(), m->a2_len.as<int32_t>(),
-                         m->a2.val[0].as<double>(), m->n_vertices);
-    }
+    if (m->a2_maxlen > kGalerkinMaxRow) return hipErrorInvalidValue;  // rejected by ensure_level2
+    const size_t lds = size_t(m->a2_maxlen) * (9 * sizeof(double) + sizeof(int32_t));
+    hipLaunchKernelGGL(k_galerkin_rows, dim3(unsigned(m->n_agg)), dim3(kGalerkinThreads), lds, s,
+                       m->k1.soff.as<int32_t>(), m->k1.col.as<int32_t>(), m->k1.val[0].as<double>(),
+                       m->fix.as<uint8_t>(), m->p2_col.as<int32_t>(), m->p2_width, m->p2_val[0].as<double>(),
+                       m->p2t_off.as<int32_t>(), m->p2t_idx.as<int32_t>(), m->a2.soff.as<int32_t>(),
+                       m->a2.col.as<int32_t>(), m->a2_len.as<int32_t>(), m->a2.val[0].as<double>(), m->n_agg);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
