@@ -37,10 +37,28 @@
 namespace ebe {
 namespace {
 
+// Size of the MI355X last-level (Infinity) cache shared by all XCDs.
+constexpr int64_t kStreamStageBytes = int64_t(256) << 20;
+
 template <typename T, int VW>
 struct alignas(sizeof(T) * VW) VecT {
   T v[VW];
 };
+
+// Non-temporal (streaming) vector store and load, for the staged partial
+// sums of shared nodes when a product's staging area is larger than the
+// last-level cache and would only push the input vector out of the caches.
+template <typename T, int VW>
+__device__ __forceinline__ void store_stream(T* p, const VecT<T, VW>& v) {
+  typedef T NV __attribute__((ext_vector_type(VW)));
+  __builtin_nontemporal_store(*reinterpret_cast<const NV*>(&v), reinterpret_cast<NV*>(p));
+}
+template <typename T, int VW>
+__device__ __forceinline__ VecT<T, VW> load_stream(const T* p) {
+  typedef T NV __attribute__((ext_vector_type(VW)));
+  const NV r = __builtin_nontemporal_load(reinterpret_cast<const NV*>(p));
+  return *reinterpret_cast<const VecT<T, VW>*>(&r);
+}
 
 // widest vector (at most 16 bytes) whose width divides both n and the pass
 // width, so every vector of a node row lies inside one pass and is aligned
@@ -199,7 +217,7 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
     const int32_t* __restrict__ conn, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
     const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
     const double4* __restrict__ xv, const typename Pair<T>::type* __restrict__ lame, const T* __restrict__ x,
-    T* __restrict__ y, T* __restrict__ stage, int bc, int add, double* __restrict__ gamma,
+    T* __restrict__ y, T* __restrict__ stage, int stream, int bc, int add, double* __restrict__ gamma,
     double* __restrict__ gslot, unsigned* __restrict__ gcount, const int* __restrict__ gate,
     const T* __restrict__ gcache) {
   constexpr int NLOC = ORDER == 2 ? 10 : 4;
@@ -357,7 +375,9 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
 #pragma unroll
           for (int t = 0; t < VEC; ++t) v.v[t] = T(F[ent * WC + q + t]);
           if (wd < 0) {  // shared node: partial sum to its staging slot
-            *reinterpret_cast<V*>(stage + size_t(slots[ent]) * W + col) = v;
+            T* sp = stage + size_t(slots[ent]) * W + col;
+          if (stream) store_stream<T, VEC>(sp, v);
+          else *reinterpret_cast<V*>(sp) = v;
           } else {
             V* yp = reinterpret_cast<V*>(y + size_t(wd & kIdxMask) * W + col);
             const bool fixed = bc && ((wd >> (kIdxBits + c)) & 1);
@@ -404,8 +424,9 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
     const T* __restrict__ gcache, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
     const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
     const T* __restrict__ x,
-    T* __restrict__ y, T* __restrict__ stage, int npatch, int bc, int add, double* __restrict__ gamma,
-    double* __restrict__ gslot, unsigned* __restrict__ gcount, const int* __restrict__ gate) {
+    T* __restrict__ y, T* __restrict__ stage, int stream, int npatch, int bc, int add,
+    double* __restrict__ gamma, double* __restrict__ gslot, unsigned* __restrict__ gcount,
+    const int* __restrict__ gate) {
   using LW = typename std::conditional<ORDER == 2, uint4, uint32_t>::type;  // an element's local ids
   constexpr int GV = 16 / int(sizeof(T));   // values per 16-byte piece of a geometry row
   using GR = VecT<T, GV>;
@@ -580,7 +601,9 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) 
 #pragma unroll
         for (int t = 0; t < VEC; ++t) v.v[t] = T(F[ent * W + sq + t]);
         if (wd < 0) {
-          *reinterpret_cast<V*>(stage + size_t(slots[ent]) * W + col) = v;
+          T* sp = stage + size_t(slots[ent]) * W + col;
+          if (stream) store_stream<T, VEC>(sp, v);
+          else *reinterpret_cast<V*>(sp) = v;
         } else {
           V* yp = reinterpret_cast<V*>(y + size_t(wd & kIdxMask) * W + col);
           const bool fixed = bc && ((wd >> (kIdxBits + sc)) & 1);
@@ -626,8 +649,8 @@ constexpr int reduce_width() {
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_reduce_shared(const int32_t* __restrict__ snode,
                                                        const int32_t* __restrict__ soff,
-                                                       const T* __restrict__ stage, T* __restrict__ y,
-                                                       int32_t nshared, int bc, int add,
+                                                       const T* __restrict__ stage, int stream,
+                                                       T* __restrict__ y, int32_t nshared, int bc, int add,
                                                        const int* __restrict__ gate) {
   constexpr int W = 3 * NR;
   constexpr int VW = reduce_width<T, NR>();
@@ -644,15 +667,16 @@ __global__ __launch_bounds__(256) void k_reduce_shared(const int32_t* __restrict
   double acc[VW];
 #pragma unroll
   for (int t = 0; t < VW; ++t) acc[t] = 0.0;
+  auto ld = [&](int32_t jj) { return stream ? load_stream<T, VW>(sp + jj * W) : *reinterpret_cast<const V*>(sp + jj * W); };
   int32_t j = j0;
   for (; j + 2 <= j1; j += 2) {
-    const V a = *reinterpret_cast<const V*>(sp + j * W);
-    const V b = *reinterpret_cast<const V*>(sp + (j + 1) * W);
+    const V a = ld(j);
+    const V b = ld(j + 1);
 #pragma unroll
     for (int t = 0; t < VW; ++t) acc[t] += double(a.v[t]) + double(b.v[t]);
   }
   if (j < j1) {
-    const V a = *reinterpret_cast<const V*>(sp + j * W);
+    const V a = ld(j);
 #pragma unroll
     for (int t = 0; t < VW; ++t) acc[t] += double(a.v[t]);
   }
@@ -848,8 +872,8 @@ __global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
 }
 
 template <typename T, int NR, int ORDER, bool STAGE, bool MASK>
-void launch_patch_m(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool bc, bool add,
-                    const int* gate, hipStream_t s, double* gamma) {
+void launch_patch_m(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool stream, bool bc,
+                    bool add, const int* gate, hipStream_t s, double* gamma) {
   using P = typename Pair<T>::type;
   const P* lame = (sizeof(T) == 8) ? reinterpret_cast<const P*>(m->lame64.as<void>())
                                    : reinterpret_cast<const P*>(m->lame32.as<void>());
@@ -857,23 +881,23 @@ void launch_patch_m(const ebe_mesh* m, const PatchLevel& L, const void* x, void*
                      dim3(threads_for(NR, ORDER, int(sizeof(T)), STAGE)), 0, s, m->conn.as<int32_t>(),
                      ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(), L.pelem.as<int32_t>(),
                      L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(), m->xv.as<double4>(), lame,
-                     static_cast<const T*>(x), static_cast<T*>(y), stage, int(bc), int(add), gamma,
+                     static_cast<const T*>(x), static_cast<T*>(y), stage, int(stream), int(bc), int(add), gamma,
                      m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64),
                      gate, m->geo_ready[sizeof(T) == 8 ? 0 : 1] ? m->geo[sizeof(T) == 8 ? 0 : 1].as<T>() : nullptr);
 }
 
 template <typename T, int NR, int ORDER, bool STAGE>
-void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool mask_in, bool bc,
-                  bool add, const int* gate, hipStream_t s, double* gamma) {
-  if (mask_in) launch_patch_m<T, NR, ORDER, STAGE, true>(m, L, x, y, stage, bc, add, gate, s, gamma);
-  else launch_patch_m<T, NR, ORDER, STAGE, false>(m, L, x, y, stage, bc, add, gate, s, gamma);
+void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool stream,
+                  bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
+  if (mask_in) launch_patch_m<T, NR, ORDER, STAGE, true>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
+  else launch_patch_m<T, NR, ORDER, STAGE, false>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
 }
 
 // Pipelined form: as many persistent workgroups as fit on the device at once
 // (measured occupancy x CUs), at most one per patch.
 template <typename T, int NR, int ORDER, bool MASK>
-void launch_patch_pipe_m(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool bc,
-                         bool add, const int* gate, hipStream_t s, double* gamma) {
+void launch_patch_pipe_m(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool stream,
+                         bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
   constexpr int TPB = threads_for(NR, ORDER, int(sizeof(T)), false);
   static const int per_cu = [] {
     int n = 0;
@@ -891,15 +915,16 @@ void launch_patch_pipe_m(const ebe_mesh* m, const PatchLevel& L, const void* x, 
                      m->geo[sizeof(T) == 8 ? 0 : 1].as<T>(),
                      ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(), L.pelem.as<int32_t>(),
                      L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(),
-                     static_cast<const T*>(x), static_cast<T*>(y), stage, int(L.npatch), int(bc), int(add), gamma,
+                     static_cast<const T*>(x), static_cast<T*>(y), stage, int(stream), int(L.npatch), int(bc),
+                     int(add), gamma,
                      m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64), gate);
 }
 
 template <typename T, int NR, int ORDER>
-void launch_patch_pipe(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool mask_in,
-                       bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
-  if (mask_in) launch_patch_pipe_m<T, NR, ORDER, true>(m, L, x, y, stage, bc, add, gate, s, gamma);
-  else launch_patch_pipe_m<T, NR, ORDER, false>(m, L, x, y, stage, bc, add, gate, s, gamma);
+void launch_patch_pipe(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool stream,
+                       bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
+  if (mask_in) launch_patch_pipe_m<T, NR, ORDER, true>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
+  else launch_patch_pipe_m<T, NR, ORDER, false>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
 }
 
 // y = A x for an assembled operator whose row fix bits are `fix`
@@ -925,24 +950,27 @@ hipError_t ebe_dispatch_p(int order, int form, const ebe_mesh* m, const void* x,
                           bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   T* stage = L.stage.as<T>();
+  // stream the staged partials past the caches when they cannot stay in the
+  // last-level cache until the shared-node pass reads them back
+  const bool st = int64_t(L.nslots) * 3 * NR * int64_t(sizeof(T)) > kStreamStageBytes;
   if (form == EBE_FORM_ASSEMBLED)  // linear level only (checked by the caller)
     return launch_asm_p<T, NR>(m, m->k1, m->fix.as<uint8_t>(), x, y, mask_in, bc, add, gate, s, gamma);
   if (order == 2) {
-    if (form == EBE_FORM_STAGED) launch_patch<T, NR, 2, true>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
+    if (form == EBE_FORM_STAGED) launch_patch<T, NR, 2, true>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
     else if (form == EBE_FORM_PIPELINED)
-      launch_patch_pipe<T, NR, 2>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
-    else launch_patch<T, NR, 2, false>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
+      launch_patch_pipe<T, NR, 2>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
+    else launch_patch<T, NR, 2, false>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
   } else {
-    if (form == EBE_FORM_STAGED) launch_patch<T, NR, 1, true>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
+    if (form == EBE_FORM_STAGED) launch_patch<T, NR, 1, true>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
     else if (form == EBE_FORM_PIPELINED)
-      launch_patch_pipe<T, NR, 1>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
-    else launch_patch<T, NR, 1, false>(m, L, x, y, stage, mask_in, bc, add, gate, s, gamma);
+      launch_patch_pipe<T, NR, 1>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
+    else launch_patch<T, NR, 1, false>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || L.nshared == 0) return e;
   const int64_t work = L.nshared * (3 * NR / reduce_width<T, NR>());
   hipLaunchKernelGGL((k_reduce_shared<T, NR>), dim3(unsigned((work + 255) / 256)), dim3(256), 0, s,
-                     L.snode.as<int32_t>(), L.soff.as<int32_t>(), stage, static_cast<T*>(y), int32_t(L.nshared),
+                     L.snode.as<int32_t>(), L.soff.as<int32_t>(), stage, int(st), static_cast<T*>(y), int32_t(L.nshared),
                      int(bc), int(add), gate);
   return hipGetLastError();
 }
