@@ -51,13 +51,19 @@ struct alignas(sizeof(T) * VW) VecT {
 template <typename T, int VW>
 __device__ __forceinline__ void store_stream(T* p, const VecT<T, VW>& v) {
   typedef T NV __attribute__((ext_vector_type(VW)));
-  __builtin_nontemporal_store(*reinterpret_cast<const NV*>(&v), reinterpret_cast<NV*>(p));
+  static_assert(sizeof(NV) == sizeof(VecT<T, VW>), "vector widths 1, 2, 4 only");
+  NV r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  __builtin_nontemporal_store(r, reinterpret_cast<NV*>(p));
 }
 template <typename T, int VW>
 __device__ __forceinline__ VecT<T, VW> load_stream(const T* p) {
   typedef T NV __attribute__((ext_vector_type(VW)));
+  static_assert(sizeof(NV) == sizeof(VecT<T, VW>), "vector widths 1, 2, 4 only");
   const NV r = __builtin_nontemporal_load(reinterpret_cast<const NV*>(p));
-  return *reinterpret_cast<const VecT<T, VW>*>(&r);
+  VecT<T, VW> out;
+  __builtin_memcpy(&out, &r, sizeof(out));
+  return out;
 }
 
 // widest vector (at most 16 bytes) whose width divides both n and the pass
