@@ -101,7 +101,7 @@ def _stiffness(xe, E, nu, shape_fn, rule):
         Jinv = np.linalg.inv(J)                        # Jinv[d, c] = dxi_d/dx_c
         dNdx = np.einsum("nd,mdc->mnc", dN, Jinv)      # (m, n, 3)
         B = strain_matrix(dNdx)                        # (m, 6, 3n)
-        K += (wts[q] * np.abs(detJ))[:, None, None] * np.einsum("mia,mij,mjb->mab", B, D, B)
+        K += (wts[q] * np.abs(detJ))[:, None, None] * (B.transpose(0, 2, 1) @ (D @ B))  # B^T D B
     return K
 
 
@@ -168,7 +168,7 @@ def ebe_apply(xyz, conn, E, nu, x, order=2, chunk=20000):
         c = conn[s:s + chunk]
         Ke = kfun(xyz[c], E[s:s + chunk], nu[s:s + chunk])
         dm = _dof_map(c)
-        ye = np.einsum("mab,mbr->mar", Ke, xf[dm])
+        ye = Ke @ xf[dm]                                  # K_i (Q_i^T x), element by element
         for r in range(n):
             y[:, r] += np.bincount(dm.ravel(), weights=ye[:, :, r].ravel(), minlength=3 * N)
     return y.reshape(N, 3, n)
