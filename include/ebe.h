@@ -97,7 +97,11 @@ typedef struct ebe_batch ebe_batch; /* opaque; a set of meshes solved together *
 
 /* Solver options.  ebe_pcg_default_opts() fills the paper's settings:
  * MG3 (three inner levels), MIXED, tol 1e-8, inner tolerances
- * {0.1, 0.05, 0.025} and maxima {30, 300, 3000} (Section 4, Table 2). */
+ * {0.1, 0.05, 0.025} and maxima {30, 300, 3000} (Section 4, Table 2).
+ * MG3 needs every row of the level-2 operator to couple at most 800
+ * aggregates (the set-up sums a row in 64 KB of LDS); on a mesh past that
+ * limit a solve asked for MG3 runs MG2 instead and says so in
+ * ebe_pcg_stats.precond_used. */
 typedef struct {
   int32_t precond;      /* EBE_PREC_* */
   int32_t mode;         /* EBE_MODE_* */
@@ -121,6 +125,10 @@ typedef struct {
   int64_t inner_iters[3];  /* total inner steps on levels 0, 1 and 2 */
   double max_rel_res;      /* max_j ||r_j|| / ||f_j|| of the recursive residual at exit */
   double seconds;          /* wall time of the solve, host clock */
+  int32_t precond_used;    /* the preconditioner that ran: opts.precond, except that EBE_PREC_MG3
+                              falls back to EBE_PREC_MG2 on a mesh whose level-2 rows are too long
+                              for the level-2 set-up (more than 800 coupled aggregates) */
+  int32_t graphs_captured; /* HIP graphs captured (not replayed) during this solve */
 } ebe_pcg_stats;
 
 /* ---- mesh ------------------------------------------------------------- */

@@ -86,6 +86,7 @@ struct Workspace {
     hipGraphExec_t exec = nullptr;
   };
   std::vector<Graph> graphs;
+  int64_t captures = 0;  // graphs captured so far (ebe_pcg_stats reports the count per solve)
 };
 
 // Element patches (patches.cpp): consecutive element ranges whose node sums

@@ -92,7 +92,8 @@ constexpr size_t kMaxGraphs = 24;
 // Enqueue a fixed run of solver steps on s: directly, or (graphs on, s not
 // the legacy default stream) by replaying a graph captured from the same run
 // the first time it is met.  key holds everything the run's kernels take as
-// arguments, so a replay is exactly the run it stands for.
+// arguments, and the product forms that pick those kernels, so a replay is
+// exactly the run it stands for.
 template <class Steps>
 ebe_status enqueue_steps(ebe_mesh* m, std::vector<uintptr_t>&& key, bool graphs, hipStream_t s, Steps&& steps) {
   if (!graphs || s == nullptr) return steps();
@@ -124,6 +125,7 @@ ebe_status enqueue_steps(ebe_mesh* m, std::vector<uintptr_t>&& key, bool graphs,
     return EBE_ERR_HIP;
   }
   G.push_back(Workspace::Graph{std::move(key), exec});
+  ++m->ws.captures;
   EBE_TRY_HIP(hipGraphLaunch(exec, s));
   return EBE_OK;
 }
@@ -157,9 +159,11 @@ ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int
   while (enq < nmax - 1) {
     const int k = std::min(chunk, nmax - 1 - enq);
     const void* data = level == 2 ? m->a2.val[sizeof(T) == 8 ? 0 : 1].as<void>() : m->pl[level].stage.as<void>();
+    const int form = level == 2 ? EBE_FORM_ASSEMBLED : product_form(m, level == 0 ? 2 : 1, dtype_of<T>(), nr);
     ebe_status rs = enqueue_steps(
         m,
-        {1, uintptr_t(level), uintptr_t(k), uintptr_t(nr), sizeof(T), addr(e), addr(p), addr(q), addr(u),
+        {1, uintptr_t(level), uintptr_t(k), uintptr_t(nr), sizeof(T), uintptr_t(form), addr(e), addr(p), addr(q),
+         addr(u),
          addr(st.sc), addr(st.partials), addr(st.counter), addr(data), addr(m->gacc.as<void>()),
          addr(m->minv64[level].as<void>()), addr(m->minv32[level].as<void>()), bits_of(eps), uintptr_t(nmax)},
         graphs, s, [&]() -> ebe_status {
@@ -276,6 +280,9 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   else ebe_pcg_default_opts(&o);
   ebe_status st_ = check_opts(o);
   if (st_ != EBE_OK) return st_;
+  // level 2's set-up sums a coarse row in LDS: past its limit, run MG2
+  if (o.precond == EBE_PREC_MG3 && m->a2_maxlen > kA2MaxRow) o.precond = EBE_PREC_MG2;
+  const int64_t captures0 = m->ws.captures;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st_ = ensure_blocks(m, s)) != EBE_OK) return st_;
   if ((st_ = ensure_stage(m, nr, sizeof(double))) != EBE_OK) return st_;
@@ -348,7 +355,8 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
       }
     } else {
       rs = enqueue_steps(m,
-                         {2, uintptr_t(k), uintptr_t(nr), addr(b.r), addr(b.p), addr(b.q), addr(u), addr(st.sc),
+                         {2, uintptr_t(k), uintptr_t(nr), uintptr_t(product_form(m, 2, EBE_F64, nr)), addr(b.r),
+                          addr(b.p), addr(b.q), addr(u), addr(st.sc),
                           addr(st.partials), addr(st.counter), addr(m->pl[0].stage.as<void>()),
                           addr(m->gacc.as<void>()), addr(m->minv64[0].as<void>()), bits_of(o.tol),
                           uintptr_t(o.max_outer)},
@@ -378,6 +386,8 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
     stats->max_rel_res = h->max_rel;
     stats->status = result;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->precond_used = o.precond;
+    stats->graphs_captured = int32_t(m->ws.captures - captures0);
   }
   if (result < 0) set_error("ebe_pcg_solve: %s", ebe_status_string(result));
   return result;

@@ -47,12 +47,14 @@ class PcgOpts(ctypes.Structure):
 class PcgStats(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("inner_iters", ctypes.c_int64 * 3), ("max_rel_res", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("precond_used", ctypes.c_int32),
+                ("graphs_captured", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"outer_iters": self.outer_iters, "status": self.status,
                 "inner_iters": [int(v) for v in self.inner_iters],
-                "max_rel_res": self.max_rel_res, "seconds": self.seconds}
+                "max_rel_res": self.max_rel_res, "seconds": self.seconds,
+                "precond_used": self.precond_used, "graphs_captured": self.graphs_captured}
 
 
 class EbeError(RuntimeError):

@@ -270,6 +270,63 @@ def lognormal_material(mesh: Mesh, rng: np.random.Generator, sigma: float = 0.3)
     mesh.young = mesh.young * np.exp(sigma * rng.standard_normal(mesh.n_elem))
 
 
+def shuffled(mesh: Mesh, rng: np.random.Generator) -> Mesh:
+    """The same mesh with its elements in random order and its node ids
+    permuted at random within the corners and within the edge nodes (so the
+    numbering stays vertex-first): the unordered numbering of a general
+    unstructured mesh, where consecutive elements share few nodes."""
+    pe = rng.permutation(mesh.n_elem)
+    nv = mesh.n_vertices
+    newid = np.concatenate([rng.permutation(nv), nv + rng.permutation(mesh.n_nodes - nv)])  # old -> new
+    xyz = np.empty_like(mesh.xyz)
+    xyz[newid] = mesh.xyz
+    fixed = np.empty_like(mesh.fixed)
+    fixed[newid] = mesh.fixed
+    refined = None
+    if mesh.refined is not None:
+        refined = np.empty_like(mesh.refined)
+        refined[newid] = mesh.refined
+    return Mesh(xyz=xyz, conn=newid[mesh.conn[pe]].astype(np.int32), n_vertices=nv, young=mesh.young[pe].copy(),
+                poisson=mesh.poisson[pe].copy(), fixed=fixed, grid=mesh.grid, lengths=mesh.lengths,
+                refined=refined)
+
+
+def hub_mesh(arms: int) -> Mesh:
+    """A hub corner c shared by `arms` arms of two tetrahedra each: arm i is
+    (c, a_i, b_i, d_i) and (a_i, b_i, d_i, t_i), rotated by 2 pi i / arms
+    about the z axis (arms overlap in space: only the operator matters), with
+    a_i, b_i and t_i fully fixed.  Corner ids: t_i first, then a_i, b_i, d_i,
+    then c, so every t_i roots its own aggregate when the corner graph is
+    coarsened in increasing id and c couples all of them: a coarse operator
+    whose rows couple `arms` aggregates."""
+    M = int(arms)
+    t = np.arange(M)
+    a, b, d = M + 3 * t, M + 3 * t + 1, M + 3 * t + 2
+    c = 4 * M
+    nv = 4 * M + 1
+    e0 = nv + 9 * t  # 9 edge nodes per arm: ca, ab, cb, cd, ad, bd, at, bt, dt
+    ca, ab, cb, cd, ad, bd, at, bt, dt = (e0 + k for k in range(9))
+    conn = np.concatenate([
+        np.stack([np.full(M, c), a, b, d, ca, ab, cb, cd, ad, bd], axis=1),
+        np.stack([a, b, d, t, ab, bd, ad, at, bt, dt], axis=1)]).astype(np.int32)
+    n = nv + 9 * M
+    xyz = np.zeros((n, 3))
+    th = 2.0 * np.pi * t / M
+    cs, sn = np.cos(th), np.sin(th)
+
+    def rot(p):
+        return np.stack([cs * p[0] - sn * p[1], sn * p[0] + cs * p[1], np.full(M, float(p[2]))], axis=1)
+
+    xyz[a], xyz[b], xyz[d], xyz[t] = rot((1.0, 0.0, 0.0)), rot((0.0, 1.0, 0.0)), rot((0.0, 0.0, 1.0)), \
+        rot((1.0, 1.0, 1.0))
+    for k, (p, q) in enumerate(((c, a), (a, b), (c, b), (c, d), (a, d), (b, d), (a, t), (b, t), (d, t))):
+        xyz[e0 + k] = 0.5 * (xyz[p] + xyz[q])
+    fixed = np.zeros((n, 3), dtype=np.uint8)
+    fixed[np.concatenate([a, b, t])] = 1
+    E = conn.shape[0]
+    return Mesh(xyz=xyz, conn=conn, n_vertices=nv, young=np.ones(E), poisson=np.full(E, 0.25), fixed=fixed)
+
+
 def random_vectors(rng: np.random.Generator, n_nodes: int, nrhs: int, dtype=np.float64) -> np.ndarray:
     """(N, 3, nrhs) N(0, 1) input vectors (RHS index fastest)."""
     return rng.standard_normal((n_nodes, 3, nrhs)).astype(dtype)

@@ -91,3 +91,26 @@ def sampled_matvec(m, x, nodes):
             y[k] += rows @ xe
             b[k] += np.abs(rows) @ np.abs(xe)
     return y, b
+
+
+def restricted_matvec(m, x, nodes):
+    """Oracle (K x) and (|K| |x|) at a node set, from the element products of
+    every element that touches it (exact there: no other element contributes)."""
+    mark = np.zeros(m.n_nodes, dtype=bool)
+    mark[nodes] = True
+    els = np.nonzero(mark[m.conn].any(axis=1))[0]
+    N, _, n = x.shape
+    xf = x.reshape(3 * N, n)
+    y = np.zeros((3 * N, n))
+    b = np.zeros((3 * N, n))
+    for s in range(0, els.size, 20000):
+        es = els[s:s + 20000]
+        Ke = fem.element_stiffness_p2(m.xyz[m.conn[es]], m.young[es], m.poisson[es])
+        dm = (3 * m.conn[es][:, :, None].astype(np.int64) + np.arange(3)).reshape(es.size, 30)
+        xe = xf[dm]
+        ye = Ke @ xe
+        be = np.abs(Ke) @ np.abs(xe)
+        for r in range(n):
+            y[:, r] += np.bincount(dm.ravel(), weights=ye[:, :, r].ravel(), minlength=3 * N)
+            b[:, r] += np.bincount(dm.ravel(), weights=be[:, :, r].ravel(), minlength=3 * N)
+    return y.reshape(N, 3, n)[nodes], b.reshape(N, 3, n)[nodes]

@@ -12,7 +12,8 @@ import torch
 
 from oracle import fem, solve, adjoint
 from paper_1710_08679_amd import ebe, meshgen
-from tests.helpers import assert_close_bound, kappa_max, oracle_K, parity_mesh, sampled_matvec, tol_factor
+from tests.helpers import (assert_close_bound, kappa_max, oracle_K, parity_mesh, restricted_matvec, sampled_matvec,
+                           tol_factor)
 
 pytestmark = pytest.mark.gpu
 
@@ -287,3 +288,98 @@ def test_full_size_matvec_invariants(big):
     rot = torch.stack([-X[:, 1], X[:, 0], torch.zeros_like(X[:, 0])], dim=1)[:, :, None].contiguous()
     yr = gm.matvec(rot)
     assert float(yr.abs().max()) <= 1e-10 * float(gm.matvec(x[:, :, :1].contiguous()).abs().max())
+
+
+def test_full_size_f32_n16_tuned_at_xcd_range_boundaries(big):
+    """The benchmarked configuration (FP32, 16 cases, the tuned form) checked at
+    every node of whole patches where the patch kernels change hands: the
+    first patches, the first, second and last patches of each XCD's contiguous
+    range (a 2x2x2-hex block of 48 elements per patch on this Morton-ordered
+    mesh), the patches a persistent workgroup reaches on its second trip, and
+    the last patches."""
+    m, gm, kap = big
+    nrhs = 16
+    x = meshgen.random_vectors(meshgen.rng_for(2, 40), m.n_nodes, nrhs).astype(np.float32)
+    gm.autotune(0, torch.float32, nrhs)
+    try:
+        y = gm.matvec(to_dev(x, np.float32)).cpu().numpy().astype(np.float64)
+    finally:
+        gm.set_form(0, torch.float32, nrhs, ebe.FORM_AUTO)
+    npatch = m.n_elem // 48
+    q = npatch // 8
+    patches = set()
+    for xcd in range(9):
+        for d in (-2, -1, 0, 1, 63, 64, 65, 130):
+            p = xcd * q + d
+            if 0 <= p < npatch:
+                patches.add(p)
+    els = np.concatenate([np.arange(48 * p, 48 * p + 48) for p in sorted(patches)])
+    nodes = np.unique(m.conn[els])
+    print(f"[xcd boundaries] {len(patches)} patches, {nodes.size} nodes", flush=True)
+    ref, bnd = restricted_matvec(m, x.astype(np.float64), nodes)
+    tol = tol_factor(np.float32, kap) * bnd
+    err = np.abs(y[nodes] - ref)
+    assert np.all(err <= tol), float(np.max(err / tol))
+
+
+@pytest.mark.parametrize("form", FORMS + ["tuned"])
+def test_full_size_f32_n16_all_nodes_against_fp64(big, form):
+    """Every node of the FP32 16-case product against the FP64 product of the
+    same (FP32-rounded) input: a lost or doubled partial sum anywhere would be
+    an O(1) error at its node."""
+    m, gm, kap = big
+    nrhs = 16
+    x = meshgen.random_vectors(meshgen.rng_for(2, 41), m.n_nodes, nrhs).astype(np.float32)
+    xd = to_dev(x, np.float32)
+    y64 = gm.matvec(xd.double())
+    if form == "tuned":
+        gm.autotune(0, torch.float32, nrhs)
+        y32 = gm.matvec(xd)
+        gm.set_form(0, torch.float32, nrhs, ebe.FORM_AUTO)
+    else:
+        with forced_form(gm, 0, np.float32, nrhs, form):
+            y32 = gm.matvec(xd)
+    err = (y32.double() - y64).abs()
+    scale = float(y64.abs().max())
+    assert float(err.max()) <= 2e-4 * scale, float(err.max()) / scale
+    assert float(err.norm() / y64.norm()) <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# unordered numbering: elements and node ids shuffled (vertex-first kept)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def shuffled(gpu_lib):
+    m = meshgen.shuffled(parity_mesh(5, 4, 4, seed=3, bc=True), meshgen.rng_for(78, 0))
+    print(f"[shuffled parity mesh] E={m.n_elem} N={m.n_nodes}", flush=True)
+    return m, ebe.Mesh.from_generated(m), oracle_K(m), oracle_K(m, order=1), kappa_max(m)
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("nrhs", [1, 4, 16])
+def test_shuffled_mesh_matvec_matches_oracle(shuffled, dtype, nrhs, form):
+    """Consecutive elements of a shuffled mesh share few nodes, so patches are
+    cut by the node limit long before the element limit and most of their
+    nodes are shared with other patches."""
+    m, gm, K, _, kap = shuffled
+    x = meshgen.rng_for(79, nrhs).standard_normal((m.n_nodes, 3, nrhs)).astype(dtype)
+    with forced_form(gm, 0, dtype, nrhs, form):
+        y = gm.matvec(to_dev(x, dtype)).cpu().numpy().astype(np.float64)
+        yb = gm.matvec(to_dev(x, dtype), apply_bc=True).cpu().numpy().astype(np.float64)
+    xr = x.astype(np.float64)
+    ref = (K @ xr.reshape(-1, nrhs)).reshape(y.shape)
+    assert_close_bound(y, ref, abs(K), xr, dtype, kap, f"shuffled K x {dtype.__name__} n={nrhs} form={form}")
+    assert_close_bound(yb, fem.matvec_bc(K, xr, m.fixed), abs(K), xr, dtype, kap, "shuffled P K P x")
+
+
+@pytest.mark.parametrize("form", FORMS1)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_shuffled_mesh_linear_matvec_matches_oracle(shuffled, dtype, form):
+    m, gm, _, K1, kap = shuffled
+    x = meshgen.rng_for(79, 100).standard_normal((m.n_vertices, 3, 7)).astype(dtype)
+    with forced_form(gm, 1, dtype, 7, form):
+        y = gm.matvec_p1(to_dev(x, dtype)).cpu().numpy().astype(np.float64)
+    xr = x.astype(np.float64)
+    ref = (K1 @ xr.reshape(-1, 7)).reshape(y.shape)
+    assert_close_bound(y, ref, abs(K1), xr, dtype, kap, f"shuffled K1 x form={form}")

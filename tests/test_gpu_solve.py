@@ -1,5 +1,7 @@
 """GPU solves (Algorithm 1 and PCGE) against the oracle's direct solutions,
 plus the adjoint gradient through torch.autograd."""
+import copy
+
 import numpy as np
 import pytest
 import torch
@@ -146,6 +148,68 @@ def test_graph_replays_match_eager_solves(crust, precond, mode):
             assert rel_err(ug.cpu().numpy(), ref) <= 1e-6
 
 
+def test_graph_capture_follows_product_form(crust):
+    """Graphs are keyed by the product forms as well as by buffers: after the
+    form of a product changes, the next solve on a stream captures new graphs
+    instead of replaying ones whose kernels were picked for the old form."""
+    m, gm, f, K, ud = crust
+    fd = dev(f[:, :, :4])
+    ref = ud[:, :, :4]
+    keys = [(0, torch.float64), (0, torch.float32), (1, torch.float32)]
+    s = torch.cuda.Stream()
+    opts = ebe.default_opts(precond=ebe.PREC_MG2, mode=ebe.MODE_MIXED, tol=1e-8, graphs=1)
+    try:
+        with torch.cuda.stream(s):
+            for form, fresh in ((ebe.FORM_GATHER, True), (ebe.FORM_GATHER, False), (ebe.FORM_PIPELINED, True),
+                                (ebe.FORM_GATHER, False)):
+                for level, dt in keys:
+                    gm.set_form(level, dt, 4, form)
+                u, st = gm.solve(fd, opts=opts, stream=s)
+                s.synchronize()
+                print(f"[graph keys form={form}] {st}", flush=True)
+                assert st["status"] == ebe.OK
+                assert (st["graphs_captured"] > 0) == fresh, st
+                assert rel_err(u.cpu().numpy(), ref) <= 1e-6
+    finally:
+        for level, dt in keys:
+            gm.set_form(level, dt, 4, ebe.FORM_AUTO)
+
+
+def test_mg3_falls_back_to_mg2_on_long_coarse_rows(gpu_lib):
+    """A hub corner shared by 850 two-element arms makes every level-2 row
+    couple 850 aggregates, past what the level-2 set-up can sum: a solve asked
+    for MG3 runs MG2, reports it, and still reaches the direct solution."""
+    m = meshgen.hub_mesh(850)
+    gm = ebe.Mesh.from_generated(m)
+    f = meshgen.random_vectors(meshgen.rng_for(9, 1), m.n_nodes, 3)
+    f[m.fixed.astype(bool)] = 0.0
+    K = fem.assemble(m.xyz, m.conn, m.young, m.poisson)
+    ud = solve.sparse_solve(K, f, m.fixed)
+    u, st = gm.solve(dev(f), precond=ebe.PREC_MG3, tol=1e-9)
+    print(f"[hub mesh, MG3 asked] {st}", flush=True)
+    assert st["status"] == ebe.OK and st["precond_used"] == ebe.PREC_MG2
+    assert rel_err(u.cpu().numpy(), ud) <= 1e-6
+    u, st = gm.solve(dev(f), precond=ebe.PREC_PCGE, mode=ebe.MODE_FP64, tol=1e-9)
+    assert st["status"] == ebe.OK and st["precond_used"] == ebe.PREC_PCGE
+
+
+@pytest.mark.parametrize("precond,mode,tol,bound", [(ebe.PREC_MG3, ebe.MODE_MIXED, 1e-8, 1e-6),
+                                                    (ebe.PREC_MG3, ebe.MODE_FP64, 1e-13, 1e-10),
+                                                    (ebe.PREC_MG2, ebe.MODE_MIXED, 1e-8, 1e-6)])
+def test_shuffled_mesh_solves(gpu_lib, precond, mode, tol, bound):
+    """Algorithm 1 on a mesh with shuffled elements and node ids: patches cut
+    by the node limit on every level, aggregates of an unordered corner graph."""
+    m = meshgen.shuffled(meshgen.crust_mesh(10, 10, 5, jitter=0.2), meshgen.rng_for(3, 77))
+    f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(3, 78), nrhs=5)
+    K = fem.assemble(m.xyz, m.conn, m.young, m.poisson)
+    ud = solve.sparse_solve(K, f, m.fixed)
+    gm = ebe.Mesh.from_generated(m)
+    u, st = gm.solve(dev(f), precond=precond, mode=mode, tol=tol)
+    print(f"[shuffled crust precond={precond} mode={mode}] {st}", flush=True)
+    assert st["status"] == ebe.OK and st["precond_used"] == precond
+    assert rel_err(u.cpu().numpy(), ud) <= bound
+
+
 def test_full_size_crust_mixed_solve(gpu_lib):
     """The 96x96x48 crust workload (10.8M DOF, 16 cases) as bench.py solves it:
     the FP64 residual of the mixed solution meets the tolerance, and that
@@ -270,3 +334,46 @@ def test_gradient_central_differences_on_gpu(adj):
                 vals.append(float(surface_misfit(dev(Ep), gm, dev(m.poisson), dev(f), Sd, dev(d), opts)))
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - gg[e]) <= 1e-5 * np.max(np.abs(gg))
+
+
+def test_adjoint_workload_central_differences(gpu_lib):
+    """The adjoint workload at its stated size (64x64x32 hexes x 6 = 786,432
+    tets, 4 cases, lognormal moduli, top-surface misfit): dL/dE from the FP64
+    and the FP32 element-gradient kernels against central differences of L
+    on 20 seeded elements, every solve FP64 to 1e-13."""
+    m = meshgen.adjoint_mesh(64, 64, 32)
+    f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(4, 3), nrhs=4)
+    S = meshgen.top_surface_dofs(m)
+    gm = ebe.Mesh.from_generated(m)
+    print(f"[adjoint workload] E={m.n_elem} DOF={m.n_dof}", flush=True)
+    opts = ebe.default_opts(precond=ebe.PREC_MG3, mode=ebe.MODE_FP64, tol=1e-13)
+    Sd = torch.from_numpy(S).cuda()
+    # targets: the unperturbed layered model's surface response plus 1% noise
+    base = copy.copy(m)
+    meshgen.set_layers_sinusoidal(base, meshgen.rng_for(4, 1))  # rebinds base.young / base.poisson only
+    assert np.array_equal(base.poisson, m.poisson) and not np.array_equal(base.young, m.young)
+    gm.set_material(dev(base.young), dev(base.poisson))
+    u0, _ = gm.solve(dev(f), opts=opts)
+    s0 = u0.view(-1, 4)[Sd]
+    d = s0 + 0.01 * float(s0.abs().mean()) * dev(meshgen.rng_for(4, 4).standard_normal((S.size, 4)))
+    grads = {}
+    for gdt in (torch.float64, torch.float32):
+        E = dev(m.young).requires_grad_(True)
+        loss = surface_misfit(E, gm, dev(m.poisson), dev(f), Sd, d, opts, gdt)
+        loss.backward()
+        grads[gdt] = E.grad.cpu().numpy()
+    g64, g32 = grads[torch.float64], grads[torch.float32]
+    scale = float(np.max(np.abs(g64)))
+    assert np.max(np.abs(g32 - g64)) <= 1e-4 * scale
+    for k, e in enumerate(meshgen.rng_for(4, 5).choice(m.n_elem, size=20, replace=False)):
+        h = 1e-4 * m.young[e]
+        vals = []
+        for sgn in (1, -1):
+            Ep = m.young.copy()
+            Ep[e] += sgn * h
+            with torch.no_grad():
+                vals.append(float(surface_misfit(dev(Ep), gm, dev(m.poisson), dev(f), Sd, d, opts)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        print(f"[adjoint fd {k}] e={e} fd={fd:.6e} g64={g64[e]:.6e} g32={g32[e]:.6e}", flush=True)
+        assert abs(fd - g64[e]) <= 1e-5 * scale
+        assert abs(fd - g32[e]) <= 1e-5 * scale
