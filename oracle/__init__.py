@@ -18,6 +18,8 @@ alg1     Algorithm 1 (outer flexible CG, inner CG levels 0, 1 and optionally 2).
 amg      level 2: aggregation of the corner graph, P2, A2 = P2^T K1 P2 (Section 2,
          "inner loop level 2"; the coarsening itself is a reading, see the module).
 adjoint  misfit, adjoint solve and dL/dE_e (extension beyond the paper).
+greens   split-node forces of unit fault slips, Green's functions at surface
+         stations, the regularised inversion of Eq. (5) with the L-curve (Section 5).
 material Lame parameters; (Vp, Vs, rho) -> (E, nu) for Table 3.
 
 Parity status: every function here is pinned by tests under ``tests/`` against

@@ -327,6 +327,106 @@ def hub_mesh(arms: int) -> Mesh:
     return Mesh(xyz=xyz, conn=conn, n_vertices=nv, young=np.ones(E), poisson=np.full(E, 0.25), fixed=fixed)
 
 
+# --------------------------------------------------------------------------
+# a fault for unit-slip loading, and surface observation stations
+# --------------------------------------------------------------------------
+@dataclass
+class Fault:
+    """A planar fault patch made of element faces: the plane y - z = c of a
+    Kuhn lattice (refined coordinates r_y - r_z = k, k even), dipping 45
+    degrees, striking along x, with unit slip basis functions on it.
+
+    nodes    fault-patch node ids (on the plane, inside the patch rectangle)
+    coords   (n_fault, 2) in-plane coordinates (x, eta), eta = (y + z) / sqrt 2
+    sides    (E,) int8: +1 / -1 for elements touching a fault-patch node on
+             the side y - z > c / y - z < c, 0 for the others
+    basis    (n_fault, n_basis) basis values at the fault nodes
+    dirs     (n_basis, 3) slip direction (unit vector) of each basis function
+    """
+    k: int
+    normal: np.ndarray
+    strike: np.ndarray
+    dip: np.ndarray
+    nodes: np.ndarray
+    coords: np.ndarray
+    sides: np.ndarray
+    basis: np.ndarray
+    dirs: np.ndarray
+    knots: tuple
+
+    @property
+    def n_basis(self) -> int:
+        return int(self.basis.shape[1])
+
+    def slip(self, n_nodes: int, cols) -> np.ndarray:
+        """(n_nodes, 3, len(cols)) nodal slip vectors of the chosen basis
+        functions: B_i(x, eta) times the slip direction at fault nodes, zero
+        elsewhere."""
+        cols = np.asarray(cols)
+        out = np.zeros((n_nodes, 3, cols.size))
+        out[self.nodes] = self.basis[:, None, cols] * self.dirs[cols].T[None, :, :]
+        return out
+
+
+def cubic_bspline(t: np.ndarray) -> np.ndarray:
+    """Uniform cubic B-spline of unit knot spacing centred at 0 (support [-2, 2])."""
+    a = np.abs(np.asarray(t, dtype=np.float64))
+    return np.where(a < 1.0, (4.0 - 6.0 * a ** 2 + 3.0 * a ** 3) / 6.0,
+                    np.where(a < 2.0, (2.0 - a) ** 3 / 6.0, 0.0))
+
+
+def dipping_fault(mesh: Mesh, c: float, strike_range, dip_range, knots) -> Fault:
+    """Unit-slip basis on the fault patch {y - z = c, x in strike_range,
+    eta in dip_range} of a Kuhn lattice with equal spacing h on y and z:
+    knots = (n_strike, n_dip) tensor-product cubic B-splines, each entirely
+    inside the patch (so slip vanishes on its edges), each in the strike
+    (1, 0, 0) and the up-dip (0, 1, 1)/sqrt 2 direction: 2 n_strike n_dip
+    basis functions, strike ones first."""
+    h = mesh.h
+    if not np.isclose(h[1], h[2]):
+        raise ValueError("the 45-degree fault needs equal y and z spacing")
+    k = int(round(2.0 * c / h[1]))
+    if k % 2 or not np.isclose(k * h[1] / 2.0, c):
+        raise ValueError("c must be a whole number of lattice spacings")
+    r = mesh.refined
+    on = (r[:, 1] - r[:, 2]) == k
+    x = mesh.xyz[:, 0]
+    eta = (mesh.xyz[:, 1] + mesh.xyz[:, 2]) / np.sqrt(2.0)
+    inside = on & (x >= strike_range[0] - 1e-12) & (x <= strike_range[1] + 1e-12) & \
+        (eta >= dip_range[0] - 1e-12) & (eta <= dip_range[1] + 1e-12)
+    nodes = np.nonzero(inside)[0]
+    coords = np.stack([x[nodes], eta[nodes]], axis=1)
+    touch = inside[mesh.conn].any(axis=1)
+    d = (r[mesh.conn[:, :4], 1] - r[mesh.conn[:, :4], 2] - k).sum(axis=1)
+    sides = np.where(touch, np.sign(d), 0).astype(np.int8)
+    ns, nd = int(knots[0]), int(knots[1])
+    hs = (strike_range[1] - strike_range[0]) / (ns + 3)
+    hd = (dip_range[1] - dip_range[0]) / (nd + 3)
+    cs = strike_range[0] + hs * (2 + np.arange(ns))
+    cd = dip_range[0] + hd * (2 + np.arange(nd))
+    bs = cubic_bspline((coords[:, 0:1] - cs[None, :]) / hs)  # (n_fault, ns)
+    bd = cubic_bspline((coords[:, 1:2] - cd[None, :]) / hd)  # (n_fault, nd)
+    one = (bs[:, :, None] * bd[:, None, :]).reshape(nodes.size, ns * nd)
+    strike = np.array([1.0, 0.0, 0.0])
+    dip = np.array([0.0, 1.0, 1.0]) / np.sqrt(2.0)
+    normal = np.array([0.0, 1.0, -1.0]) / np.sqrt(2.0)
+    basis = np.concatenate([one, one], axis=1)
+    dirs = np.concatenate([np.tile(strike, (ns * nd, 1)), np.tile(dip, (ns * nd, 1))])
+    return Fault(k=k, normal=normal, strike=strike, dip=dip, nodes=nodes, coords=coords, sides=sides,
+                 basis=basis, dirs=dirs, knots=(ns, nd))
+
+
+def surface_stations(mesh: Mesh, step: int) -> np.ndarray:
+    """Top-surface nodes on every `step`-th corner line in x and y (refined
+    coordinates multiples of 2 step, not on the domain's side faces): the
+    observation points; each contributes its three displacement components."""
+    r = mesh.refined
+    top = r[:, 2] == 2 * mesh.grid[2]
+    sel = top & (r[:, 0] % (2 * step) == 0) & (r[:, 1] % (2 * step) == 0) & \
+        (r[:, 0] > 0) & (r[:, 1] > 0) & (r[:, 0] < 2 * mesh.grid[0]) & (r[:, 1] < 2 * mesh.grid[1])
+    return np.nonzero(sel)[0]
+
+
 def random_vectors(rng: np.random.Generator, n_nodes: int, nrhs: int, dtype=np.float64) -> np.ndarray:
     """(N, 3, nrhs) N(0, 1) input vectors (RHS index fastest)."""
     return rng.standard_normal((n_nodes, 3, nrhs)).astype(dtype)
