@@ -176,6 +176,24 @@ ebe_status ebe_matvec(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void*
 ebe_status ebe_matvec_add(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* x_dev,
                           void* y_dev, int32_t apply_bc, void* stream);
 
+/* y = K x (or P K P x) like ebe_matvec, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): this call allocates nothing.  The
+ * shared-node partial sums are staged in a fixed device array of the library
+ * (64 MiB per GPU, held until the process ends); the call is refused with
+ * EBE_ERR_ARG when the mesh needs more than that at this nrhs and dtype
+ * (one staged row per (patch, shared node) pair, 3 x nrhs values of 8 or 4
+ * bytes each: at FP32 with 16 cases at most 349,525 rows, which a 24^3-hex
+ * cube of 82,944 tetrahedra, about 180k rows, fits).  Always the gather
+ * form; element geometry from the mesh's geometry cache when an earlier call
+ * filled it, else from the corner coordinates.  Every call on a GPU shares
+ * that GPU's array: calls that overlap in time on one GPU (other streams,
+ * other threads) race and give wrong results; calls in one stream order are
+ * safe.  Asynchronous; same arguments and result as ebe_matvec up to
+ * rounding. */
+ebe_status ebe_matvec_noalloc(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* x_dev,
+                              void* y_dev, int32_t apply_bc, void* stream);
+
 /* y = K1 x on the linear (4-node) mesh made of the corners, the coarse
  * operator of inner loop level 1 (Section 2, multigrid; Table 4 "1st order EBE").
  * x_dev, y_dev: [n_vertices][3][nrhs]. */

@@ -146,6 +146,23 @@ ebe_status ebe_matvec(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, vo
                                                 static_cast<hipStream_t>(stream)));
 }
 
+ebe_status ebe_matvec_noalloc(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, int32_t apply_bc,
+                              void* stream) {
+  ebe_status st = check_common("ebe_matvec_noalloc", m, dt, nrhs, x, y);
+  if (st != EBE_OK) return st;
+  const size_t need = size_t(m->pl[0].nslots) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4);
+  if (need > kNoAllocScratchBytes) {
+    set_error("ebe_matvec_noalloc: this mesh stages %zu bytes of shared-node sums at nrhs %d; the "
+              "allocation-free scratch holds %zu (use ebe_matvec, or fewer cases per call)",
+              need, nrhs, kNoAllocScratchBytes);
+    return EBE_ERR_ARG;
+  }
+  void* stage = nullptr;
+  if ((st = noalloc_scratch(m->device, &stage)) != EBE_OK) return st;
+  return hip_status("ebe_matvec_noalloc", launch_ebe_noalloc(m, dt, nrhs, x, y, apply_bc && m->has_bc, stage,
+                                                             static_cast<hipStream_t>(stream)));
+}
+
 ebe_status ebe_matvec_add(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* x, void* y, int32_t apply_bc,
                           void* stream) {
   ebe_status st = check_common("ebe_matvec_add", m, dt, nrhs, x, y);

@@ -297,4 +297,16 @@ ebe_status ensure_level2(ebe_mesh* m, ebe_dtype dt, hipStream_t s);
 // grow the staging buffers for products with up to nrhs cases of the given element size
 ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes);
 
+// ---- allocation-free product (ebe_kernels.hip) ------------------------------
+// Size of the fixed device array that stages shared-node partial sums for
+// ebe_matvec_noalloc (nslots * 3 * nrhs values of the dtype must fit).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+// device address of that array on `device` (looked up once per device)
+ebe_status noalloc_scratch(int device, void** ptr);
+// y = K x (or P K P x) in the gather form with the staging in `stage` (the
+// scratch array's device address); geometry from the mesh's cache when it
+// exists, else from the corner coordinates; allocates nothing
+hipError_t launch_ebe_noalloc(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,
+                              void* stage, hipStream_t s);
+
 }  // namespace ebe

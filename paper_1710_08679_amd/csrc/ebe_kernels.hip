@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "ebe_internal.h"
@@ -994,7 +995,75 @@ hipError_t ebe_dispatch(int order, int form, const ebe_mesh* m, int nrhs, const 
   }
 }
 
+// ---- allocation-free product -------------------------------------------
+// Staging memory of ebe_matvec_noalloc: a fixed array in the code object, so
+// that the call needs no device allocation.  Each device the library runs on
+// holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address comes from hipGetSymbolAddress, looked up once
+// per device with that device current, and kept below.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kMaxDevices] = {};
+
+template <typename T, int NR>
+hipError_t launch_noalloc_p(const ebe_mesh* m, const void* x, void* y, bool bc, void* stage, hipStream_t s) {
+  const PatchLevel& L = m->pl[0];
+  T* st = static_cast<T*>(stage);
+  if (bc) launch_patch_m<T, NR, 2, false, true>(m, L, x, y, st, false, bc, false, nullptr, s, nullptr);
+  else launch_patch_m<T, NR, 2, false, false>(m, L, x, y, st, false, bc, false, nullptr, s, nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || L.nshared == 0) return e;
+  const int64_t work = L.nshared * (3 * NR / reduce_width<T, NR>());
+  hipLaunchKernelGGL((k_reduce_shared<T, NR>), dim3(unsigned((work + 255) / 256)), dim3(256), 0, s,
+                     L.snode.as<int32_t>(), L.soff.as<int32_t>(), st, 0, static_cast<T*>(y), int32_t(L.nshared),
+                     int(bc), 0, nullptr);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+ebe_status noalloc_scratch(int device, void** ptr) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("no-allocation scratch: device %d outside 0..%d", device, kMaxDevices - 1);
+    return EBE_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[device]) {
+    int prev = 0;
+    EBE_TRY_HIP(hipGetDevice(&prev));
+    EBE_TRY_HIP(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess || !p) {
+      set_error("hipGetSymbolAddress(scratch) on device %d failed: %s", device, hipGetErrorString(e));
+      return EBE_ERR_HIP;
+    }
+    scratch_dev[device] = p;
+  }
+  *ptr = scratch_dev[device];
+  return EBE_OK;
+}
+
+hipError_t launch_ebe_noalloc(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,
+                              void* stage, hipStream_t s) {
+  if (nrhs < 1 || nrhs > EBE_MAX_RHS || m->pl[0].npatch < 1 ||
+      size_t(m->pl[0].nslots) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4) > kNoAllocScratchBytes)
+    return hipErrorInvalidValue;  // checked by the entry point: host bug
+  switch (nrhs) {
+#define EBE_CASE(n)                                                              \
+  case n:                                                                        \
+    return dt == EBE_F64 ? launch_noalloc_p<double, n>(m, x, y, bc, stage, s)    \
+                         : launch_noalloc_p<float, n>(m, x, y, bc, stage, s);
+    EBE_CASE(1) EBE_CASE(2) EBE_CASE(3) EBE_CASE(4) EBE_CASE(5) EBE_CASE(6) EBE_CASE(7) EBE_CASE(8)
+    EBE_CASE(9) EBE_CASE(10) EBE_CASE(11) EBE_CASE(12) EBE_CASE(13) EBE_CASE(14) EBE_CASE(15) EBE_CASE(16)
+#undef EBE_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
 
 ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes) {
   for (int l = 0; l < 2; ++l) {

@@ -32,7 +32,7 @@ EXPORTED = (
     "ebe_pcg_default_opts", "ebe_pcg_solve", "ebe_adjoint_grad", "ebe_batch_create", "ebe_batch_solve",
     "ebe_batch_destroy", "ebe_status_string", "ebe_last_error", "ebe_build_info", "ebe_autotune",
     "ebe_set_product_form", "ebe_get_product_form", "ebe_level2_info", "ebe_matvec_l2", "ebe_prolong_l2",
-    "ebe_restrict_l2",
+    "ebe_restrict_l2", "ebe_matvec_noalloc",
 )
 
 
@@ -84,6 +84,7 @@ def load():
         "ebe_mesh_destroy": ([_vp], None),
         "ebe_matvec": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
         "ebe_matvec_add": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
+        "ebe_matvec_noalloc": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
         "ebe_matvec_p1": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
         "ebe_prolong_p1": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
         "ebe_restrict_p1": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
@@ -260,6 +261,10 @@ class Mesh:
     def matvec(self, x, apply_bc=False, out=None, stream=None):
         """y = K x (quadratic elements); x (N, 3, nrhs) float64/float32."""
         return self._vec_op(load().ebe_matvec, x, self.n_nodes, self.n_nodes, apply_bc, out, stream)
+
+    def matvec_noalloc(self, x, apply_bc=False, out=None, stream=None):
+        """y = K x through the allocation-free entry point (out may be preallocated)."""
+        return self._vec_op(load().ebe_matvec_noalloc, x, self.n_nodes, self.n_nodes, apply_bc, out, stream)
 
     def matvec_add(self, x, y, apply_bc=False, stream=None):
         """y += K x (in place); returns y."""
