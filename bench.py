@@ -179,7 +179,7 @@ def solver_block(torch, ebe, meshgen, modes):
     return out, (m, f, sols)
 
 
-FORM_NAMES = {0: "gather", 1: "staged", 2: "pipelined", 3: "assembled"}
+FORM_NAMES = {0: "gather", 1: "staged", 2: "pipelined", 3: "assembled", 4: "coloured"}
 
 
 def adjoint_block(torch, ebe, meshgen, steps, warmup):

@@ -81,7 +81,14 @@ typedef int32_t ebe_dtype;
  * applies K1 assembled once (per material) into 3x3 blocks over the corner
  * graph instead of forming element products, so a product reads each block
  * once for all cases: a departure from the paper's element-by-element
- * coarse level, chosen only where it measures faster.
+ * coarse level, chosen only where it measures faster.  COLOURED (quadratic
+ * level only) colours the element patches so that no two patches of a
+ * colour share a node and runs the colours one after another, each patch
+ * adding its sums straight into y (the multi-colouring Section 2 uses on
+ * CPUs, where Section 3.2 takes atomics on GPUs; here over patches): no
+ * staging buffer, and the sum at every node is formed in a fixed order.
+ * PIPELINED and COLOURED need a mesh below 2^25 nodes whose vectors at this
+ * (dtype, nrhs) are below 4 GiB; elsewhere GATHER runs in their place.
  * AUTO: the mesh's tuned choice, else a fixed default. */
 typedef enum {
   EBE_FORM_AUTO = -1,
@@ -89,7 +96,8 @@ typedef enum {
   EBE_FORM_STAGED = 1,
   EBE_FORM_PIPELINED = 2,
   EBE_FORM_ASSEMBLED = 3,
-  EBE_NUM_FORMS = 4
+  EBE_FORM_COLOURED = 4,
+  EBE_NUM_FORMS = 5
 } ebe_form;
 
 typedef struct ebe_mesh ebe_mesh;   /* opaque; owns device copies of the mesh and workspace */
@@ -161,6 +169,15 @@ ebe_status ebe_mesh_info(const ebe_mesh* mesh, int64_t* n_nodes, int64_t* n_vert
                          int64_t* n_elem);
 
 void ebe_mesh_destroy(ebe_mesh* mesh);
+
+/* Work decomposition of the EBE products on level 0 (quadratic mesh) or 1
+ * (corners): element patches (consecutive elements whose nodal sums fit a
+ * workgroup's LDS), nodes shared by several patches, staged partial-sum rows
+ * (one per (patch, shared node) pair: what the staging forms write and the
+ * node-centric pass reads back), and colours of the COLOURED form (0 at
+ * level 1).  Any out pointer may be NULL. */
+ebe_status ebe_patch_info(const ebe_mesh* mesh, int32_t level, int64_t* n_patches, int64_t* n_shared,
+                          int64_t* n_staged, int32_t* n_colours);
 
 /* ---- operators (asynchronous) ---------------------------------------- */
 
@@ -274,21 +291,34 @@ ebe_status ebe_adjoint_grad(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const
 /* ---- product forms and the autotuner ------------------------------------ */
 
 /* Time every product form of y = K x (level 0: quadratic mesh, level 1:
- * linear mesh) for (dtype, nrhs) on this mesh and keep the fastest for
- * every later product with these parameters; ms_out[EBE_NUM_FORMS] (or
- * NULL) receives the times in milliseconds, indexed by form, -1 for a form
- * that does not exist at this level.  Synchronous;
+ * linear mesh) for (dtype, nrhs) on this mesh, and for PIPELINED and
+ * COLOURED both kernel variants (element geometry kept in LDS, or read by
+ * each work-item), and keep the fastest for every later product with these
+ * parameters (Section 4 tunes its kernels' parameters by hand; here the
+ * search is measured on the mesh); ms_out[EBE_NUM_FORMS] (or NULL) receives
+ * the times in milliseconds, indexed by form (the faster variant), -1 for a
+ * form that does not exist at this level or cannot run on this mesh.
+ * Synchronous;
  * allocates temporary vectors.  ebe_pcg_solve tunes the products it uses by
  * itself. */
 ebe_status ebe_autotune(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, void* stream,
                         double* ms_out);
 
-/* Force (EBE_FORM_GATHER / _STAGED / _PIPELINED, or _ASSEMBLED for level 1)
- * or reset (EBE_FORM_AUTO) the form used
+/* Force (EBE_FORM_GATHER / _STAGED / _PIPELINED, _COLOURED for level 0,
+ * _ASSEMBLED for level 1) or reset (EBE_FORM_AUTO) the form used
  * for (level, dtype, nrhs), and read the form that would be used. */
 ebe_status ebe_set_product_form(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, int32_t form);
 ebe_status ebe_get_product_form(const ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs,
                                 int32_t* form);
+
+/* Kernel variant of the PIPELINED and COLOURED forms for (level, dtype,
+ * nrhs): 0 = element geometry prefetched with the patch metadata and kept
+ * in LDS (the default), 1 = read from the geometry cache by each work-item
+ * of the element phase.  Same result up to rounding; ebe_autotune sets it,
+ * ebe_set_product_form resets it to 0; other forms ignore it. */
+ebe_status ebe_set_product_variant(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, int32_t variant);
+ebe_status ebe_get_product_variant(const ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs,
+                                   int32_t* variant);
 
 /* ---- batches: many meshes / case sets solved together ------------------ */
 

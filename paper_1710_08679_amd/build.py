@@ -32,7 +32,8 @@ COMMON = [
 
 SOURCES = [
     "mesh.cpp", "patches.cpp", "assembled.cpp", "api.cpp", "solver.cpp", "batch.cpp", "autotune.cpp",
-    "ebe_kernels.hip", "setup_kernels.hip", "ebe_vec.hip", "ebe_adjoint.hip", "solver_kernels.hip",
+    "ebe_kernels.hip", "ebe_pipe_f32_lds.hip", "ebe_pipe_f32_row.hip", "ebe_pipe_f64_lds.hip",
+    "ebe_pipe_f64_row.hip", "setup_kernels.hip", "ebe_vec.hip", "ebe_adjoint.hip", "solver_kernels.hip",
 ]
 
 

@@ -198,6 +198,20 @@ ebe_status ebe_restrict_p1(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* 
                                                        static_cast<hipStream_t>(stream)));
 }
 
+ebe_status ebe_patch_info(const ebe_mesh* m, int32_t level, int64_t* n_patches, int64_t* n_shared,
+                          int64_t* n_staged, int32_t* n_colours) {
+  if (!m || (level != 0 && level != 1)) {
+    set_error("ebe_patch_info: null mesh or level not 0/1");
+    return EBE_ERR_ARG;
+  }
+  const PatchLevel& L = m->pl[level];
+  if (n_patches) *n_patches = L.npatch;
+  if (n_shared) *n_shared = L.nshared;
+  if (n_staged) *n_staged = L.nslots;
+  if (n_colours) *n_colours = L.coff.empty() ? 0 : int32_t(L.coff.size() - 1);
+  return EBE_OK;
+}
+
 ebe_status ebe_level2_info(const ebe_mesh* m, int64_t* n_agg, int32_t* agg_host) {
   if (!m) {
     set_error("ebe_level2_info: null mesh");

@@ -39,33 +39,46 @@ ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const vo
   hipEvent_t a = nullptr, b = nullptr;
   EBE_TRY_HIP(hipEventCreate(&a));
   hipError_t e = hipEventCreate(&b);
+  const int lv = level, k = dt == EBE_F64 ? 0 : 1;
   double best[EBE_NUM_FORMS];
+  int best_var[EBE_NUM_FORMS] = {};
   for (int f = 0; f < EBE_NUM_FORMS; ++f) best[f] = DBL_MAX;
   for (int form = 0; form < EBE_NUM_FORMS && e == hipSuccess; ++form) {
-    if (!form_available(order, form)) continue;
-    e = launch_ebe_form(m, order, form, dt, nrhs, x, y, false, m->has_bc, false, nullptr, s);  // warm-up
-    for (int r = 0; r < kRuns && e == hipSuccess; ++r) {
-      e = hipEventRecord(a, s);
-      if (e == hipSuccess) e = launch_ebe_form(m, order, form, dt, nrhs, x, y, false, m->has_bc, false, nullptr, s);
-      if (e == hipSuccess) e = hipEventRecord(b, s);
-      if (e == hipSuccess) e = hipEventSynchronize(b);
-      float t = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
-      if (e == hipSuccess) best[form] = std::min(best[form], double(t));
+    if (!form_usable(m, order, form, dt, nrhs)) continue;
+    // the pipelined and coloured kernels come in two variants (element
+    // geometry kept in LDS, or read per work-item): measure both
+    const int nvar = (form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED) ? 2 : 1;
+    for (int var = 0; var < nvar && e == hipSuccess; ++var) {
+      m->fvar[lv][k][nrhs] = int8_t(var);
+      e = launch_ebe_form(m, order, form, dt, nrhs, x, y, false, m->has_bc, false, nullptr, s);  // warm-up
+      for (int r = 0; r < kRuns && e == hipSuccess; ++r) {
+        e = hipEventRecord(a, s);
+        if (e == hipSuccess) e = launch_ebe_form(m, order, form, dt, nrhs, x, y, false, m->has_bc, false, nullptr, s);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+        if (e == hipSuccess && double(t) < best[form]) {
+          best[form] = double(t);
+          best_var[form] = var;
+        }
+      }
     }
   }
   (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
   if (e != hipSuccess) {
+    m->fvar[lv][k][nrhs] = 0;
     set_error("autotune: %s", hipGetErrorString(e));
     return EBE_ERR_HIP;
   }
   int pick = 0;
   for (int f = 1; f < EBE_NUM_FORMS; ++f)
     if (best[f] < best[pick]) pick = f;
-  m->form[level][dt == EBE_F64 ? 0 : 1][nrhs] = int8_t(pick);
+  m->form[lv][k][nrhs] = int8_t(pick);
+  m->fvar[lv][k][nrhs] = int8_t(best_var[pick]);
   if (ms)
-    for (int f = 0; f < EBE_NUM_FORMS; ++f) ms[f] = form_available(order, f) ? best[f] : -1.0;
+    for (int f = 0; f < EBE_NUM_FORMS; ++f) ms[f] = form_usable(m, order, f, dt, nrhs) ? best[f] : -1.0;
   return EBE_OK;
 }
 
@@ -98,6 +111,26 @@ ebe_status ebe_set_product_form(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_
     return EBE_ERR_ARG;
   }
   m->form[level][dt == EBE_F64 ? 0 : 1][nrhs] = int8_t(form);
+  m->fvar[level][dt == EBE_F64 ? 0 : 1][nrhs] = 0;
+  return EBE_OK;
+}
+
+ebe_status ebe_set_product_variant(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, int32_t variant) {
+  if (!valid_args(m, level, dt, nrhs, "ebe_set_product_variant")) return EBE_ERR_ARG;
+  if (variant != 0 && variant != 1) {
+    set_error("ebe_set_product_variant: variant %d is not 0 or 1", variant);
+    return EBE_ERR_ARG;
+  }
+  m->fvar[level][dt == EBE_F64 ? 0 : 1][nrhs] = int8_t(variant);
+  return EBE_OK;
+}
+
+ebe_status ebe_get_product_variant(const ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, int32_t* variant) {
+  if (!valid_args(m, level, dt, nrhs, "ebe_get_product_variant") || !variant) {
+    if (m && !variant) set_error("ebe_get_product_variant: variant is NULL");
+    return EBE_ERR_ARG;
+  }
+  *variant = m->fvar[level][dt == EBE_F64 ? 0 : 1][nrhs];
   return EBE_OK;
 }
 

@@ -144,7 +144,21 @@ struct PatchLevel {
   DBuf stage;   // staging buffer [nslots][3][nrhs] of the product's dtype
   int64_t nslots = 0, nshared = 0, entries = 0;
   int max_nodes = 0;
+  // element node words [E][10] (quadratic) or [E][4] (linear): node id |
+  // patch-local id << kPtabLocalShift; empty on meshes of 2^25 nodes or more
+  DBuf ptab;
+  // colouring of the patches (quadratic level): no two patches of a colour
+  // share a node; cperm lists the patches colour by colour (increasing id
+  // within a colour), colour c is cperm[coff[c] .. coff[c+1]); cword is
+  // pnode with bit 31 meaning "an earlier colour wrote this node"
+  DBuf cperm;
+  DBuf cword;
+  std::vector<int64_t> coff;
 };
+// element node words: 25 bits of node id, 7 bits of patch-local id
+constexpr int kPtabLocalShift = 25;
+constexpr uint32_t kPtabIdMask = (1u << kPtabLocalShift) - 1;
+static_assert(kPatchNodes <= 128 && kLinPatchCorners <= 128, "patch-local ids must fit 7 bits");
 
 }  // namespace ebe
 
@@ -172,7 +186,13 @@ struct ebe_mesh {
   // EBE product form per [level][dtype F64, F32][nrhs]: one of the forms, or
   // EBE_FORM_AUTO (untuned: a fixed default)
   int8_t form[2][2][EBE_MAX_RHS + 1];
-  ebe_mesh() { std::memset(form, EBE_FORM_AUTO, sizeof(form)); }
+  // variant of the pipelined / coloured kernels per [level][dtype][nrhs]
+  // (0: element geometry kept in LDS, 1: read per work-item), set by the tuner
+  int8_t fvar[2][2][EBE_MAX_RHS + 1];
+  ebe_mesh() {
+    std::memset(form, EBE_FORM_AUTO, sizeof(form));
+    std::memset(fvar, 0, sizeof(fvar));
+  }
   // 3x3 block Jacobi: inverted symmetric blocks (xx yy zz yz zx xy), per level
   // (levels 0 and 1 with the material; level 2 with its operator)
   ebe::DBuf minv64[3], minv32[3];
@@ -234,7 +254,17 @@ hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt,
 // the form launch_ebe uses for (order, dtype, nrhs)
 // form is one of the EBE_FORM_* values and exists at this order (assembled: linear only)
 bool form_available(int order, int form);
+// ... and it can run on this mesh for (dtype, nrhs): the pipelined and
+// coloured forms need the element node words (meshes below 2^25 nodes) and
+// node rows addressable with 32-bit byte offsets; the coloured form needs
+// the patch colouring
+bool form_usable(const ebe_mesh* m, int order, int form, ebe_dtype dt, int nrhs);
 int product_form(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs);
+// the form and its kernel variant as one key (graph keys: a replay must run the same kernels)
+inline uintptr_t product_key(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs) {
+  return uintptr_t(product_form(m, order, dt, nrhs)) |
+         (uintptr_t(m->fvar[order == 2 ? 0 : 1][dt == EBE_F64 ? 0 : 1][nrhs]) << 8);
+}
 // time every form of y = K x on this mesh (x, y: device vectors of the
 // level's size; y is overwritten) and record the fastest; synchronous.
 ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const void* x, void* y, hipStream_t s,

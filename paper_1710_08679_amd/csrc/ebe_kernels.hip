@@ -34,183 +34,10 @@
 
 #include "ebe_internal.h"
 #include "p2_element.h"
+#include "patch_common.h"
 
 namespace ebe {
 namespace {
-
-// Size of the MI355X last-level (Infinity) cache shared by all XCDs.
-constexpr int64_t kStreamStageBytes = int64_t(256) << 20;
-
-template <typename T, int VW>
-struct alignas(sizeof(T) * VW) VecT {
-  T v[VW];
-};
-
-// Non-temporal (streaming) vector store and load, for the staged partial
-// sums of shared nodes when a product's staging area is larger than the
-// last-level cache and would only push the input vector out of the caches.
-template <typename T, int VW>
-__device__ __forceinline__ void store_stream(T* p, const VecT<T, VW>& v) {
-  typedef T NV __attribute__((ext_vector_type(VW)));
-  static_assert(sizeof(NV) == sizeof(VecT<T, VW>), "vector widths 1, 2, 4 only");
-  NV r;
-  __builtin_memcpy(&r, &v, sizeof(r));
-  __builtin_nontemporal_store(r, reinterpret_cast<NV*>(p));
-}
-template <typename T, int VW>
-__device__ __forceinline__ VecT<T, VW> load_stream(const T* p) {
-  typedef T NV __attribute__((ext_vector_type(VW)));
-  static_assert(sizeof(NV) == sizeof(VecT<T, VW>), "vector widths 1, 2, 4 only");
-  const NV r = __builtin_nontemporal_load(reinterpret_cast<const NV*>(p));
-  VecT<T, VW> out;
-  __builtin_memcpy(&out, &r, sizeof(out));
-  return out;
-}
-
-// widest vector (at most 16 bytes) whose width divides both n and the pass
-// width, so every vector of a node row lies inside one pass and is aligned
-constexpr int pass_vec(int nr, int cw, int value_bytes) {
-  int v = 16 / value_bytes;
-  while (v > 1 && (nr % v != 0 || cw % v != 0)) v /= 2;
-  return v;
-}
-
-template <typename T> struct Pair;
-template <> struct Pair<double> { using type = double2; };
-template <> struct Pair<float> { using type = float2; };
-
-// Cases per pass of the staged form on the quadratic mesh: at most
-// EBE_P2_PASS_F32 / _F64, in passes of equal width, so that a 192-node
-// patch's staged rows and FP64 accumulator fit the occupancy the form is
-// built for.  The gather form and the linear mesh (<= 64 corners) take all n
-// cases in one pass.
-#ifndef EBE_P2_PASS_F32
-#define EBE_P2_PASS_F32 8
-#endif
-#ifndef EBE_P2_PASS_F64
-#define EBE_P2_PASS_F64 8
-#endif
-constexpr int chunk_for(int nr, int order, int value_bytes, bool stage) {
-  const int widest = value_bytes == 8 ? EBE_P2_PASS_F64 : EBE_P2_PASS_F32;
-  const int passes = (nr + widest - 1) / widest;
-  return (order == 1 || !stage) ? nr : (nr + passes - 1) / passes;
-}
-
-// one work-item per (element, case) of a pass, at most kPatchThreads
-// (kPatchThreadsF64 for quadratic FP64 patches)
-constexpr int threads_for(int nr, int order, int value_bytes, bool stage) {
-  const int want = ((order == 2 ? kPatchElems : kLinPatchElems) * chunk_for(nr, order, value_bytes, stage) + 63) /
-                   64 * 64;
-  const int cap = (order == 2 && value_bytes == 8) ? kPatchThreadsF64 : kPatchThreads;
-  return want > cap ? cap : want;
-}
-
-// LDS of one patch workgroup and the wavefronts per SIMD that LDS leaves
-// room for (160 KiB per CU, 4 SIMDs); the kernel asks the compiler for no
-// more registers than that occupancy allows, but never for fewer than the
-// element arithmetic needs without spilling: 128 (FP32, and the linear
-// element) or 256 (quadratic FP64).
-template <typename T>
-constexpr int patch_lds_bytes(int nr, int order, bool stage) {
-  const int maxn = order == 2 ? kPatchNodes : kLinPatchCorners;
-  const int wc = 3 * chunk_for(nr, order, int(sizeof(T)), stage);
-  return maxn * wc * 8 + (stage ? maxn * wc * int(sizeof(T)) : 0) +
-         (order == 2 ? kPatchElems : kLinPatchElems) * (14 * int(sizeof(T)) + (order == 2 ? 16 : 4)) +
-         8 * maxn + 8 * nr + 16;
-}
-template <typename T>
-constexpr int patch_waves_per_simd(int nr, int order, bool stage) {
-  const int lds = (patch_lds_bytes<T>(nr, order, stage) + 511) / 512 * 512;  // allocation granule
-  const int wg = 163840 / lds;
-  const int w = (wg > 0 ? wg : 1) * (threads_for(nr, order, int(sizeof(T)), stage) / 64) / 4;
-  const int most = (sizeof(T) == 8 && order == 2) ? 2 : 4;
-  return w > most ? most : (w < 1 ? 1 : w);
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2.  Give XCD x the contiguous patch range [start_x, start_x + count_x), so
-// that neighbouring patches, which share about half their nodes, read those
-// nodes through the same L2.  A bijection on [0, npatch).
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_patch(int b, int npatch) {
-  const int x = b % kXcds, i = b / kXcds;
-  const int q = npatch / kXcds, rr = npatch % kXcds;
-  return x * q + (x < rr ? x : rr) + i;
-}
-
-// Within a wave the cases of an element occupy adjacent lanes, so a wave
-// holds 64 / n elements.  Consecutive elements of a patch (tetrahedra of one
-// hexahedron in a structured mesh) share many nodes, and their LDS atomics
-// then hit the same address in one instruction.  Interleaving by a stride of
-// ceil(ne / G) spreads a wave's elements over the patch.
-// Items j in [0, spread_count) map to elements spread_element(j) (>= ne: skip).
-template <int NR>
-__device__ __forceinline__ int spread_count(int ne) {
-  constexpr int G = 64 / NR;  // elements per wave
-  return G <= 1 ? ne : ((ne + G - 1) / G) * G;
-}
-template <int NR>
-__device__ __forceinline__ int spread_element(int j, int ne) {
-  constexpr int G = 64 / NR;
-  if constexpr (G <= 1) {
-    return j;
-  } else {
-    const int K = (ne + G - 1) / G;
-    return (j % G) * K + j / G;
-  }
-}
-
-// Element geometry into LDS: barycentric gradients G (rows 0..3), then
-// lambda s and mu s with s = V / 20 (quadratic: int L_k L_l dV = V (1 +
-// delta_kl) / 20) or s = V (linear).
-template <typename T, int ORDER>
-__device__ __forceinline__ void store_geometry(T* __restrict__ g, const double4& p0, const double4& p1,
-                                               const double4& p2, const double4& p3,
-                                               const typename Pair<T>::type& lm) {
-  T G[4][3];
-  const T V = tet_geometry<T>(p0, p1, p2, p3, G);
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) g[3 * k + d] = G[k][d];
-  const T s = ORDER == 2 ? V * T(0.05) : V;
-  g[12] = T(lm.x) * s;
-  g[13] = T(lm.y) * s;
-}
-
-// End of a patch kernel that formed (x, K x): gsum[NR] (LDS, complete) holds
-// this workgroup's per-case sums.  The device-scope additions are spread over
-// kGammaSlots lines (thousands of workgroups adding to one line serialise on
-// it); the last workgroup to arrive folds the slots into gamma, clearing them
-// as it reads.  Every access of this protocol is a device-scope atomic, so no
-// fence is needed (an agent-scope fence writes back the XCD's L2, which costs
-// far more than the product when every workgroup does it): a work-item waits
-// for the value its addition returns, which proves the addition done, before
-// the workgroup arrives at the counter.  Called by every work-item.
-template <int NR, int TPB>
-__device__ void fold_gamma(double* __restrict__ gsum, double* __restrict__ gamma, double* __restrict__ gslot,
-                           unsigned* __restrict__ gcount) {
-  __shared__ bool last;
-  const int tid = threadIdx.x;
-  if (tid < NR) {
-    const double old = __hip_atomic_fetch_add(gslot + (blockIdx.x % kGammaSlots) * EBE_MAX_RHS + tid, gsum[tid],
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    asm volatile("" ::"v"(old));
-  }
-  __syncthreads();
-  if (tid == 0) last = atomicAdd(gcount, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  if (tid < NR) gsum[tid] = 0.0;
-  __syncthreads();
-  for (int i = tid; i < kGammaSlots * NR; i += TPB) {
-    const int sl = i / NR, r = i - sl * NR;
-    atomicAdd(&gsum[r], atomicExch(gslot + sl * EBE_MAX_RHS + r, 0.0));
-  }
-  __syncthreads();
-  if (tid < NR) unsafeAtomicAdd(gamma + tid, gsum[tid]);
-  if (tid == 0) atomicExch(gcount, 0u);
-}
 
 // STAGE: the staged form (else the gather form).  MASK: zero the fixed
 // DOFs of x while reading it (y = P K P x); callers whose x is already zero
@@ -411,297 +238,6 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
   if (gamma) fold_gamma<NR, TPB>(gsum, gamma, gslot, gcount);
 }
 
-// Pipelined gather form: a persistent workgroup works through a sequence of
-// patches (those of its XCD's contiguous range, in steps of the number of
-// workgroups on that XCD) and keeps the next patch's metadata in flight
-// while it computes the current one, so the chain of dependent loads (patch
-// bounds -> node words, geometry, local ids) leaves the critical path.  The
-// element geometry comes from the mesh's geometry cache (gradients, volume,
-// lambda, mu per element, formed from the corner coordinates exactly as the
-// other forms form them), one coalesced row per element.  Per patch:
-//   A. commit the prefetched node words, slots, geometry and local ids to LDS,
-//      clear F;
-//   B. issue the next patch's bounds, node words, slots and geometry rows;
-//   C. element phase (as the gather form);
-//   D. issue this work-item's local ids of the next patch;
-//   E. write back (exclusive nodes to y, shared ones to their staging slot).
-template <typename T, int NR, int ORDER, bool MASK>
-__global__ __launch_bounds__(threads_for(NR, ORDER, int(sizeof(T)), false))
-__attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, false)))) void k_ebe_patch_pipe(
-    const T* __restrict__ gcache, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
-    const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
-    const T* __restrict__ x,
-    T* __restrict__ y, T* __restrict__ stage, int stream, int npatch, int bc, int add,
-    double* __restrict__ gamma, double* __restrict__ gslot, unsigned* __restrict__ gcount,
-    const int* __restrict__ gate) {
-  using LW = typename std::conditional<ORDER == 2, uint4, uint32_t>::type;  // an element's local ids
-  constexpr int GV = 16 / int(sizeof(T));   // values per 16-byte piece of a geometry row
-  using GR = VecT<T, GV>;
-  constexpr int NLOC = ORDER == 2 ? 10 : 4;
-  constexpr int W = 3 * NR;
-  constexpr int TPB = threads_for(NR, ORDER, int(sizeof(T)), false);
-  constexpr int MAXN = ORDER == 2 ? kPatchNodes : kLinPatchCorners;
-  constexpr int PE = ORDER == 2 ? kPatchElems : kLinPatchElems;
-  constexpr int KW = (MAXN + TPB - 1) / TPB;           // node entries per work-item
-  constexpr int KE = (PE + TPB - 1) / TPB;             // elements per work-item (geometry)
-  constexpr int GW = 64 / NR > 1 ? 64 / NR : 1;        // elements per wave in the element phase
-  constexpr int KI = ((PE + GW - 1) / GW * GW * NR + TPB - 1) / TPB;  // element-phase items per work-item
-  constexpr int VEC = pass_vec(NR, NR, int(sizeof(T)));
-  constexpr int NV = W / VEC;
-  constexpr int EPK = TPB / NV;
-  constexpr int KIT = (MAXN + EPK - 1) / EPK;
-  using V = VecT<T, VEC>;
-  __shared__ double F[MAXN * W];
-  __shared__ T geo[PE][14];
-  __shared__ LW lids[PE];  // the elements' local ids (registers are the scarce resource here)
-  __shared__ int32_t words[MAXN];
-  __shared__ int32_t slots[MAXN];
-  __shared__ double gsum[NR];
-  if (gate && *gate == 0) return;
-  const int tid = threadIdx.x;
-  // this workgroup's patches: XCD x owns [start, start + count); its g-th
-  // workgroup takes start + g, start + g + wx, ...
-  const int G = gridDim.x, xcd = blockIdx.x % kXcds;
-  const int wx = (G - xcd + kXcds - 1) / kXcds;  // workgroups on this XCD
-  const int q = npatch / kXcds, rr = npatch % kXcds;
-  const int start = xcd * q + (xcd < rr ? xcd : rr), stop = start + q + (xcd < rr ? 1 : 0);
-  int p = start + int(blockIdx.x) / kXcds;
-  if (tid < NR) gsum[tid] = 0.0;
-  const int sv = tid % NV, sent = tid < EPK * NV ? tid / NV : MAXN, sq = sv * VEC, sc = sq / NR, scc = sq - sc * NR;
-
-  // prefetched state of patch p
-  int e0 = 0, ne = 0, o0 = 0, nn = 0;
-  int pw[KW], ps[KW];
-  GR pg[KE][16 / GV];
-  LW pl[KE];
-  auto fetch_meta = [&](int pp) {  // bounds, node words, slots, geometry rows of patch pp
-    e0 = pelem[pp];
-    ne = pelem[pp + 1] - e0;
-    o0 = poff[pp];
-    nn = poff[pp + 1] - o0;
-#pragma unroll
-    for (int k = 0; k < KW; ++k) {
-      const int i = tid + k * TPB;
-      pw[k] = i < nn ? pnode[o0 + i] : 0;
-      ps[k] = i < nn ? pslot[o0 + i] : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < KE; ++k) {
-      const int el = tid + k * TPB;
-      if (el < ne) {
-        const GR* row = reinterpret_cast<const GR*>(gcache + (int64_t(e0) + el) * 16);
-#pragma unroll
-        for (int v = 0; v < 16 / GV; ++v) pg[k][v] = row[v];
-      }
-    }
-  };
-  auto fetch_late = [&]() {  // local ids of this work-item's elements of the prefetched patch
-#pragma unroll
-    for (int k = 0; k < KE; ++k) {
-      const int el = tid + k * TPB;
-      if (el < ne) pl[k] = *reinterpret_cast<const LW*>(lconn + (int64_t(e0) + el) * (ORDER == 2 ? 16 : 4));
-    }
-  };
-  if (p < stop) {
-    fetch_meta(p);
-    fetch_late();
-  }
-  double en_acc = 0.0;
-  constexpr bool kLaneCase = (64 % NR) == 0 && (TPB % NR) == 0;
-#pragma unroll 1
-  for (; p < stop; p += wx) {
-    // A. commit this patch
-#pragma unroll
-    for (int k = 0; k < KW; ++k) {
-      const int i = tid + k * TPB;
-      if (i < nn) {
-        words[i] = pw[k];
-        slots[i] = ps[k];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < KE; ++k) {
-      const int el = tid + k * TPB;
-      if (el < ne) {
-        T g[16];
-#pragma unroll
-        for (int v = 0; v < 16 / GV; ++v)
-#pragma unroll
-          for (int t = 0; t < GV; ++t) g[v * GV + t] = pg[k][v].v[t];
-#pragma unroll
-        for (int i = 0; i < 12; ++i) geo[el][i] = g[i];
-        const T sv = ORDER == 2 ? g[12] * T(0.05) : g[12];  // as store_geometry
-        geo[el][12] = g[13] * sv;
-        geo[el][13] = g[14] * sv;
-        lids[el] = pl[k];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < KIT; ++k) {
-      const int ent = sent + k * EPK;
-      if (ent < nn) {
-#pragma unroll
-        for (int t = 0; t < VEC; ++t) F[ent * W + sq + t] = 0.0;
-      }
-    }
-    const int cne = ne, cnn = nn;
-    __syncthreads();
-    // B. the next patch's metadata
-    const int pn = p + wx;
-    if (pn < stop) fetch_meta(pn);
-    // C. element phase of this patch
-    const int nj = spread_count<NR>(cne);
-#pragma unroll
-    for (int k = 0; k < KI; ++k) {
-      const int w = tid + k * TPB;
-      const int j = w / NR, r = w - j * NR;
-      const int el = spread_element<NR>(j, cne);
-      if (w >= nj * NR || el >= cne) continue;
-      int lid[NLOC], gw[NLOC];
-      const LW cl = lids[el];
-      if constexpr (ORDER == 2) {
-        const uint32_t qw[3] = {cl.x, cl.y, cl.z};
-#pragma unroll
-        for (int a = 0; a < NLOC; ++a) lid[a] = (qw[a >> 2] >> (8 * (a & 3))) & 0xff;
-      } else {
-#pragma unroll
-        for (int a = 0; a < NLOC; ++a) lid[a] = (cl >> (8 * a)) & 0xff;
-      }
-#pragma unroll
-      for (int a = 0; a < NLOC; ++a) {
-        gw[a] = words[lid[a]];
-        lid[a] = lid[a] * W + r;
-      }
-      T Gm[4][3];
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) Gm[kk][d] = geo[el][3 * kk + d];
-      const T clam = geo[el][12], cmu = geo[el][13];
-      T en = T(0);
-      auto u = [&](int a, int c) -> T {
-        const T v = x[size_t(uint32_t(gw[a]) & uint32_t(kIdxMask)) * W + c * NR + r];
-        return (MASK && ((gw[a] >> (kIdxBits + c)) & 1)) ? T(0) : v;
-      };
-      auto emit = [&](int a, const T f[3]) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) atomicAdd(F + lid[a] + c * NR, double(f[c]));
-      };
-      if constexpr (ORDER == 2) p2_apply<T>(Gm, clam, cmu, u, emit, gamma != nullptr, en);
-      else p1_apply<T>(Gm, clam, cmu, u, emit, gamma != nullptr, en);
-      if (gamma) {
-        if constexpr (kLaneCase) en_acc += double(en);
-        else atomicAdd(&gsum[r], double(en));
-      }
-    }
-    __syncthreads();
-    // D. the next patch's local ids (in flight during E)
-    if (pn < stop) fetch_late();
-    // E. write back this patch
-#pragma unroll
-    for (int k = 0; k < KIT; ++k) {
-      const int ent = sent + k * EPK;
-      if (ent < cnn) {
-        const int32_t wd = words[ent];
-        const int col = sc * NR + scc;
-        V v;
-#pragma unroll
-        for (int t = 0; t < VEC; ++t) v.v[t] = T(F[ent * W + sq + t]);
-        if (wd < 0) {
-          T* sp = stage + size_t(slots[ent]) * W + col;
-          if (stream) store_stream<T, VEC>(sp, v);
-          else *reinterpret_cast<V*>(sp) = v;
-        } else {
-          V* yp = reinterpret_cast<V*>(y + size_t(wd & kIdxMask) * W + col);
-          const bool fixed = bc && ((wd >> (kIdxBits + sc)) & 1);
-          if (add) {
-            if (!fixed) {
-              V o = *yp;
-#pragma unroll
-              for (int t = 0; t < VEC; ++t) o.v[t] += v.v[t];
-              *yp = o;
-            }
-          } else {
-            if (fixed) {
-#pragma unroll
-              for (int t = 0; t < VEC; ++t) v.v[t] = T(0);
-            }
-            *yp = v;
-          }
-        }
-      }
-    }
-    __syncthreads();  // words, slots, geometry and F are refilled by the next patch
-  }
-  if constexpr (kLaneCase) {
-    if (gamma) {
-#pragma unroll
-      for (int off = 32; off >= NR; off >>= 1) en_acc += __shfl_xor(en_acc, off, 64);
-      if ((tid & 63) < NR) atomicAdd(&gsum[tid & 63], en_acc);
-    }
-  }
-  __syncthreads();
-  if (gamma) fold_gamma<NR, TPB>(gsum, gamma, gslot, gcount);
-}
-
-// y[shared node] (=|+=) sum of its consecutive staged partials (patch order).
-// The host guarantees nshared * 3 * NR < 2^31 and nslots * 3 * NR < 2^31.
-
-// values per 16-byte vector that divide a node row of 3 n values
-template <typename T, int NR>
-constexpr int reduce_width() {
-  return (16 / int(sizeof(T)) == 4 && (3 * NR) % 4 == 0) ? 4 : ((3 * NR) % 2 == 0 ? 2 : 1);
-}
-
-template <typename T, int NR>
-__global__ __launch_bounds__(256) void k_reduce_shared(const int32_t* __restrict__ snode,
-                                                       const int32_t* __restrict__ soff,
-                                                       const T* __restrict__ stage, int stream,
-                                                       T* __restrict__ y, int32_t nshared, int bc, int add,
-                                                       const int* __restrict__ gate) {
-  constexpr int W = 3 * NR;
-  constexpr int VW = reduce_width<T, NR>();
-  constexpr int U = W / VW;  // work-items per shared node
-  using V = VecT<T, VW>;
-  if (gate && *gate == 0) return;
-  const int32_t i = int32_t(blockIdx.x) * 256 + int32_t(threadIdx.x);
-  if (i >= nshared * U) return;
-  const int32_t k = i / U;
-  const int32_t rem = (i - k * U) * VW;
-  const int32_t wd = snode[k];
-  const int32_t j0 = soff[k], j1 = soff[k + 1];
-  const T* sp = stage + rem;
-  double acc[VW];
-#pragma unroll
-  for (int t = 0; t < VW; ++t) acc[t] = 0.0;
-  auto ld = [&](int32_t jj) { return stream ? load_stream<T, VW>(sp + jj * W) : *reinterpret_cast<const V*>(sp + jj * W); };
-  int32_t j = j0;
-  for (; j + 2 <= j1; j += 2) {
-    const V a = ld(j);
-    const V b = ld(j + 1);
-#pragma unroll
-    for (int t = 0; t < VW; ++t) acc[t] += double(a.v[t]) + double(b.v[t]);
-  }
-  if (j < j1) {
-    const V a = ld(j);
-#pragma unroll
-    for (int t = 0; t < VW; ++t) acc[t] += double(a.v[t]);
-  }
-  V* yp = reinterpret_cast<V*>(y + size_t(wd & kIdxMask) * W + rem);
-  V out = add ? *yp : V{};
-#pragma unroll
-  for (int t = 0; t < VW; ++t) {
-    const int c = (rem + t) / NR;
-    const bool fixed = bc && ((wd >> (kIdxBits + c)) & 1);
-    if (add) {
-      if (!fixed) out.v[t] += T(acc[t]);
-    } else {
-      out.v[t] = fixed ? T(0) : T(acc[t]);
-    }
-  }
-  *yp = out;
-}
-
 // Assembled linear-level form: y = K1 x with the 3x3 blocks of K1 in slices
 // of kSliceRows rows (slot j of row r at entry j * kSliceRows + r, values
 // value-major within the slot, so the rows of a wavefront read each value
@@ -899,41 +435,6 @@ void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y
   if (mask_in) launch_patch_m<T, NR, ORDER, STAGE, true>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
   else launch_patch_m<T, NR, ORDER, STAGE, false>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
 }
-
-// Pipelined form: as many persistent workgroups as fit on the device at once
-// (measured occupancy x CUs), at most one per patch.
-template <typename T, int NR, int ORDER, bool MASK>
-void launch_patch_pipe_m(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool stream,
-                         bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
-  constexpr int TPB = threads_for(NR, ORDER, int(sizeof(T)), false);
-  static const int per_cu = [] {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ebe_patch_pipe<T, NR, ORDER, MASK>, TPB, 0) !=
-            hipSuccess ||
-        n < 1)
-      n = 1;
-    return n;
-  }();
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess || cus < 1)
-    cus = 256;
-  const int64_t grid = std::min<int64_t>(L.npatch, int64_t(per_cu) * cus);
-  hipLaunchKernelGGL((k_ebe_patch_pipe<T, NR, ORDER, MASK>), dim3(unsigned(grid)), dim3(TPB), 0, s,
-                     m->geo[sizeof(T) == 8 ? 0 : 1].as<T>(),
-                     ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(), L.pelem.as<int32_t>(),
-                     L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(),
-                     static_cast<const T*>(x), static_cast<T*>(y), stage, int(stream), int(L.npatch), int(bc),
-                     int(add), gamma,
-                     m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64), gate);
-}
-
-template <typename T, int NR, int ORDER>
-void launch_patch_pipe(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool stream,
-                       bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
-  if (mask_in) launch_patch_pipe_m<T, NR, ORDER, true>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
-  else launch_patch_pipe_m<T, NR, ORDER, false>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
-}
-
 // y = A x for an assembled operator whose row fix bits are `fix`
 template <typename T, int NR>
 hipError_t launch_asm_p(const ebe_mesh* m, const AsmOp& op, const uint8_t* fix, const void* x, void* y,
@@ -957,20 +458,25 @@ hipError_t ebe_dispatch_p(int order, int form, const ebe_mesh* m, const void* x,
                           bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   T* stage = L.stage.as<T>();
+  if (form == EBE_FORM_ASSEMBLED)  // linear level only (checked by the caller)
+    return launch_asm_p<T, NR>(m, m->k1, m->fix.as<uint8_t>(), x, y, mask_in, bc, add, gate, s, gamma);
+  if (form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED) {
+    const bool colour = form == EBE_FORM_COLOURED;
+    const bool geo_lds = m->fvar[order == 2 ? 0 : 1][sizeof(T) == 8 ? 0 : 1][NR] == 0;
+    if (order == 2)
+      return geo_lds ? launch_pipe<T, NR, 2, true>(m, x, y, mask_in, bc, add, gate, s, gamma, colour)
+                     : launch_pipe<T, NR, 2, false>(m, x, y, mask_in, bc, add, gate, s, gamma, colour);
+    return geo_lds ? launch_pipe<T, NR, 1, true>(m, x, y, mask_in, bc, add, gate, s, gamma, colour)
+                   : launch_pipe<T, NR, 1, false>(m, x, y, mask_in, bc, add, gate, s, gamma, colour);
+  }
   // stream the staged partials past the caches when they cannot stay in the
   // last-level cache until the shared-node pass reads them back
   const bool st = int64_t(L.nslots) * 3 * NR * int64_t(sizeof(T)) > kStreamStageBytes;
-  if (form == EBE_FORM_ASSEMBLED)  // linear level only (checked by the caller)
-    return launch_asm_p<T, NR>(m, m->k1, m->fix.as<uint8_t>(), x, y, mask_in, bc, add, gate, s, gamma);
   if (order == 2) {
     if (form == EBE_FORM_STAGED) launch_patch<T, NR, 2, true>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
-    else if (form == EBE_FORM_PIPELINED)
-      launch_patch_pipe<T, NR, 2>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
     else launch_patch<T, NR, 2, false>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
   } else {
     if (form == EBE_FORM_STAGED) launch_patch<T, NR, 1, true>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
-    else if (form == EBE_FORM_PIPELINED)
-      launch_patch_pipe<T, NR, 1>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
     else launch_patch<T, NR, 1, false>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
   }
   hipError_t e = hipGetLastError();
@@ -1081,12 +587,24 @@ ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes) {
 }
 
 bool form_available(int order, int form) {
-  return form >= 0 && form < EBE_NUM_FORMS && (form != EBE_FORM_ASSEMBLED || order == 1);
+  return form >= 0 && form < EBE_NUM_FORMS && (form != EBE_FORM_ASSEMBLED || order == 1) &&
+         (form != EBE_FORM_COLOURED || order == 2);
+}
+
+bool form_usable(const ebe_mesh* m, int order, int form, ebe_dtype dt, int nrhs) {
+  if (!form_available(order, form)) return false;
+  if (form != EBE_FORM_PIPELINED && form != EBE_FORM_COLOURED) return true;
+  const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
+  // node tables hold 32-bit byte offsets of node rows
+  const int64_t rows = order == 2 ? m->n_nodes : m->n_vertices;
+  const int64_t row_bytes = int64_t(3) * nrhs * (dt == EBE_F64 ? 8 : 4);
+  if (L.ptab.bytes() == 0 || rows * row_bytes >= (int64_t(1) << 32)) return false;
+  return form != EBE_FORM_COLOURED || L.coff.size() > 1;
 }
 
 int product_form(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs) {
   const int f = m->form[order == 2 ? 0 : 1][dt == EBE_F64 ? 0 : 1][nrhs];
-  if (form_available(order, f)) return f;
+  if (form_usable(m, order, f, dt, nrhs)) return f;
   return EBE_FORM_GATHER;  // untuned: the form measured fastest on the reference workloads
 }
 
@@ -1095,8 +613,11 @@ hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt,
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   const size_t need = size_t(L.nslots) * 3 * size_t(nrhs) * (dt == EBE_F64 ? 8 : 4);
   const int k = dt == EBE_F64 ? 0 : 1;
-  if (L.stage.bytes() < need || L.npatch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS || !form_available(order, form) ||
-      (form == EBE_FORM_PIPELINED && !m->geo_ready[k]) || (form == EBE_FORM_ASSEMBLED && !m->k1.ready[k]))
+  const bool staged = form != EBE_FORM_COLOURED && form != EBE_FORM_ASSEMBLED;
+  if ((staged && L.stage.bytes() < need) || L.npatch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS ||
+      !form_usable(m, order, form, dt, nrhs) ||
+      ((form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED) && !m->geo_ready[k]) ||
+      (form == EBE_FORM_ASSEMBLED && !m->k1.ready[k]))
     return hipErrorInvalidValue;  // staging, geometry or assembled values not prepared, or bad form: host bug
   return dt == EBE_F64 ? ebe_dispatch<double>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma)
                        : ebe_dispatch<float>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma);

@@ -110,6 +110,70 @@ std::vector<int32_t> cut_patches(int64_t E, int nloc, int64_t n_nodes, int max_e
   return pelem;
 }
 
+// Element node words: node id | patch-local id << kPtabLocalShift, [E][nloc].
+template <class NodeOf>
+std::vector<uint32_t> node_words(int64_t E, int nloc, NodeOf node_of, const std::vector<uint8_t>& lconn,
+                                 int lstride) {
+  std::vector<uint32_t> w(size_t(E) * nloc);
+  for (int64_t e = 0; e < E; ++e)
+    for (int a = 0; a < nloc; ++a)
+      w[size_t(e) * nloc + a] =
+          uint32_t(node_of(e, a)) | (uint32_t(lconn[size_t(e) * lstride + a]) << kPtabLocalShift);
+  return w;
+}
+
+// Greedy colouring of the patches (in patch order, each takes the smallest
+// colour no patch sharing a node with it has), the patches listed colour by
+// colour, and the node words with bit 31 set where an earlier patch in that
+// order already wrote the node.
+void colour_patches(int64_t n_nodes, const LevelTables& t, std::vector<int32_t>& cperm, std::vector<int64_t>& coff,
+                    std::vector<int32_t>& cword) {
+  const int64_t npatch = int64_t(t.poff.size()) - 1;
+  // node -> patches (CSR)
+  std::vector<int32_t> nstart(n_nodes + 1, 0);
+  for (int32_t w : t.pnode) nstart[(w & kIdxMask) + 1]++;
+  for (int64_t v = 0; v < n_nodes; ++v) nstart[v + 1] += nstart[v];
+  std::vector<int32_t> npatches(t.pnode.size()), fillp(nstart.begin(), nstart.end() - 1);
+  for (int64_t p = 0; p < npatch; ++p)
+    for (int32_t i = t.poff[p]; i < t.poff[p + 1]; ++i) npatches[fillp[t.pnode[i] & kIdxMask]++] = int32_t(p);
+  std::vector<int32_t> colour(npatch, -1);
+  std::vector<int64_t> taken;  // taken[c] == p: colour c is used by a neighbour of patch p
+  int ncol = 0;
+  for (int64_t p = 0; p < npatch; ++p) {
+    for (int32_t i = t.poff[p]; i < t.poff[p + 1]; ++i) {
+      const int32_t v = t.pnode[i] & kIdxMask;
+      for (int32_t k = nstart[v]; k < nstart[v + 1]; ++k) {
+        const int32_t c = colour[npatches[k]];
+        if (c >= 0) taken[c] = p;
+      }
+    }
+    int c = 0;
+    while (c < ncol && taken[c] == p) ++c;
+    if (c == ncol) {
+      ++ncol;
+      taken.push_back(-1);
+    }
+    colour[p] = c;
+  }
+  coff.assign(ncol + 1, 0);
+  for (int64_t p = 0; p < npatch; ++p) coff[colour[p] + 1]++;
+  for (int c = 0; c < ncol; ++c) coff[c + 1] += coff[c];
+  cperm.assign(npatch, 0);
+  std::vector<int64_t> fillc(coff.begin(), coff.end() - 1);
+  for (int64_t p = 0; p < npatch; ++p) cperm[fillc[colour[p]]++] = int32_t(p);
+  cword.assign(t.pnode.size(), 0);
+  std::vector<uint8_t> written(n_nodes, 0);
+  for (int64_t k = 0; k < npatch; ++k) {
+    const int32_t p = cperm[k];
+    for (int32_t i = t.poff[p]; i < t.poff[p + 1]; ++i) {
+      const int32_t w = t.pnode[i] & 0x7fffffff;  // id | fix bits
+      const int32_t v = w & kIdxMask;
+      cword[i] = w | (written[v] ? int32_t(1u << 31) : 0);
+      written[v] = 1;
+    }
+  }
+}
+
 template <class T>
 ebe_status up(DBuf& b, const std::vector<T>& h, hipStream_t s) {
   ebe_status st = b.alloc(std::max<size_t>(h.size(), 1) * sizeof(T));
@@ -140,6 +204,16 @@ ebe_status build_patches(ebe_mesh* m, const int32_t* conn10, const uint8_t* fix,
   ebe_status st = EBE_OK;
   if ((st = up(m->lconn, lconn, s)) != EBE_OK) return st;
   if ((st = up(m->lconn1, lconn1, s)) != EBE_OK) return st;
+  if (m->n_nodes <= int64_t(kPtabIdMask)) {  // element node words (pipelined and coloured forms)
+    if ((st = up(m->pl[0].ptab, node_words(E, 10, node_of, lconn, 16), s)) != EBE_OK) return st;
+    if ((st = up(m->pl[1].ptab, node_words(E, 4, node_of, lconn1, 4), s)) != EBE_OK) return st;
+  }
+  {
+    std::vector<int32_t> cperm, cword;
+    colour_patches(m->n_nodes, t[0], cperm, m->pl[0].coff, cword);
+    if ((st = up(m->pl[0].cperm, cperm, s)) != EBE_OK) return st;
+    if ((st = up(m->pl[0].cword, cword, s)) != EBE_OK) return st;
+  }
   for (int l = 0; l < 2; ++l) {
     PatchLevel& L = m->pl[l];
     if ((st = up(L.pelem, pelem[l], s)) != EBE_OK) return st;

@@ -159,7 +159,7 @@ ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int
   while (enq < nmax - 1) {
     const int k = std::min(chunk, nmax - 1 - enq);
     const void* data = level == 2 ? m->a2.val[sizeof(T) == 8 ? 0 : 1].as<void>() : m->pl[level].stage.as<void>();
-    const int form = level == 2 ? EBE_FORM_ASSEMBLED : product_form(m, level == 0 ? 2 : 1, dtype_of<T>(), nr);
+    const uintptr_t form = level == 2 ? uintptr_t(EBE_FORM_ASSEMBLED) : product_key(m, level == 0 ? 2 : 1, dtype_of<T>(), nr);
     ebe_status rs = enqueue_steps(
         m,
         {1, uintptr_t(level), uintptr_t(k), uintptr_t(nr), sizeof(T), uintptr_t(form), addr(e), addr(p), addr(q),
@@ -355,7 +355,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
       }
     } else {
       rs = enqueue_steps(m,
-                         {2, uintptr_t(k), uintptr_t(nr), uintptr_t(product_form(m, 2, EBE_F64, nr)), addr(b.r),
+                         {2, uintptr_t(k), uintptr_t(nr), product_key(m, 2, EBE_F64, nr), addr(b.r),
                           addr(b.p), addr(b.q), addr(u), addr(st.sc),
                           addr(st.partials), addr(st.counter), addr(m->pl[0].stage.as<void>()),
                           addr(m->gacc.as<void>()), addr(m->minv64[0].as<void>()), bits_of(o.tol),

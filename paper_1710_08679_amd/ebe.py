@@ -22,8 +22,8 @@ F64, F32 = 0, 1
 PREC_PCGE, PREC_MG2, PREC_MG3 = 0, 1, 2
 MODE_FP64, MODE_MIXED = 0, 1
 MAX_RHS = 16
-FORM_AUTO, FORM_GATHER, FORM_STAGED, FORM_PIPELINED, FORM_ASSEMBLED = -1, 0, 1, 2, 3
-NUM_FORMS = 4
+FORM_AUTO, FORM_GATHER, FORM_STAGED, FORM_PIPELINED, FORM_ASSEMBLED, FORM_COLOURED = -1, 0, 1, 2, 3, 4
+NUM_FORMS = 5
 
 EXPORTED = (
     "ebe_mesh_create", "ebe_mesh_set_material", "ebe_mesh_info", "ebe_mesh_destroy", "ebe_matvec",
@@ -32,7 +32,8 @@ EXPORTED = (
     "ebe_pcg_default_opts", "ebe_pcg_solve", "ebe_adjoint_grad", "ebe_batch_create", "ebe_batch_solve",
     "ebe_batch_destroy", "ebe_status_string", "ebe_last_error", "ebe_build_info", "ebe_autotune",
     "ebe_set_product_form", "ebe_get_product_form", "ebe_level2_info", "ebe_matvec_l2", "ebe_prolong_l2",
-    "ebe_restrict_l2", "ebe_matvec_noalloc",
+    "ebe_restrict_l2", "ebe_matvec_noalloc", "ebe_patch_info", "ebe_set_product_variant",
+    "ebe_get_product_variant",
 )
 
 
@@ -82,6 +83,8 @@ def load():
         "ebe_mesh_set_material": ([_vp, _vp, _vp, _vp], _i32),
         "ebe_mesh_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _i32),
         "ebe_mesh_destroy": ([_vp], None),
+        "ebe_patch_info": ([_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                            ctypes.POINTER(_i32)], _i32),
         "ebe_matvec": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
         "ebe_matvec_add": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
         "ebe_matvec_noalloc": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
@@ -103,6 +106,8 @@ def load():
         "ebe_autotune": ([_vp, _i32, _i32, _i32, _vp, ctypes.POINTER(ctypes.c_double)], _i32),
         "ebe_set_product_form": ([_vp, _i32, _i32, _i32, _i32], _i32),
         "ebe_get_product_form": ([_vp, _i32, _i32, _i32, ctypes.POINTER(_i32)], _i32),
+        "ebe_set_product_variant": ([_vp, _i32, _i32, _i32, _i32], _i32),
+        "ebe_get_product_variant": ([_vp, _i32, _i32, _i32, ctypes.POINTER(_i32)], _i32),
         "ebe_level2_info": ([_vp, ctypes.POINTER(_i64), _vp], _i32),
         "ebe_matvec_l2": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
         "ebe_prolong_l2": ([_vp, _i32, _i32, _vp, _vp, _vp], _i32),
@@ -230,6 +235,13 @@ class Mesh:
         _check(load().ebe_mesh_info(self.handle, ctypes.byref(n), ctypes.byref(nv), ctypes.byref(ne)))
         return n.value, nv.value, ne.value
 
+    def patch_info(self, level=0):
+        """dict: patches, shared nodes, staged partial-sum rows and colours of a level's products."""
+        npat, nsh, nst, ncol = _i64(), _i64(), _i64(), _i32()
+        _check(load().ebe_patch_info(self.handle, int(level), ctypes.byref(npat), ctypes.byref(nsh),
+                                     ctypes.byref(nst), ctypes.byref(ncol)))
+        return {"patches": npat.value, "shared": nsh.value, "staged": nst.value, "colours": ncol.value}
+
     # ---- operators -------------------------------------------------------
     def _vec_op(self, fn, x, rows_in, rows_out, apply_bc, out, stream):
         import torch
@@ -245,13 +257,22 @@ class Mesh:
     def autotune(self, level, dtype, nrhs, stream=None):
         """Time every product form for (level, dtype, nrhs) and keep the fastest;
         returns the times in ms, indexed by form (-1: no such form at this level;
-        FORM_ASSEMBLED exists at the linear level only)."""
+        FORM_ASSEMBLED exists at the linear level only, FORM_COLOURED at the quadratic level only)."""
         ms = (ctypes.c_double * NUM_FORMS)()
         _check(load().ebe_autotune(self.handle, int(level), _dtype_code(dtype), int(nrhs), _stream(stream), ms))
         return tuple(float(v) for v in ms)
 
     def set_form(self, level, dtype, nrhs, form):
         _check(load().ebe_set_product_form(self.handle, int(level), _dtype_code(dtype), int(nrhs), int(form)))
+
+    def set_variant(self, level, dtype, nrhs, variant):
+        _check(load().ebe_set_product_variant(self.handle, int(level), _dtype_code(dtype), int(nrhs), int(variant)))
+
+    def variant(self, level, dtype, nrhs):
+        v = _i32()
+        _check(load().ebe_get_product_variant(self.handle, int(level), _dtype_code(dtype), int(nrhs),
+                                              ctypes.byref(v)))
+        return int(v.value)
 
     def form(self, level, dtype, nrhs):
         f = _i32()

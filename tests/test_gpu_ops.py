@@ -31,27 +31,33 @@ def small(gpu_lib):
     return m, ebe.Mesh.from_generated(m), oracle_K(m), oracle_K(m, order=1), kappa_max(m)
 
 
-FORMS = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED]  # quadratic level
-FORMS1 = FORMS + [ebe.FORM_ASSEMBLED]                            # linear level
+FORMS = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_COLOURED]  # quadratic level
+FORMS1 = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_ASSEMBLED]  # linear level
+# the pipelined and coloured kernels in their second variant (geometry read per work-item)
+FORMS_V = FORMS + [(ebe.FORM_PIPELINED, 1), (ebe.FORM_COLOURED, 1)]
+FORMS1_V = FORMS1 + [(ebe.FORM_PIPELINED, 1)]
 
 
 class forced_form:
     """Run the products of one (level, dtype, nrhs) in a given form."""
 
     def __init__(self, gm, level, dtype, nrhs, form):
+        form, variant = form if isinstance(form, tuple) else (form, 0)
         self.args = (gm, level, DT[dtype], nrhs, form)
+        self.variant = variant
 
     def __enter__(self):
         gm, level, dt, nrhs, form = self.args
         gm.set_form(level, dt, nrhs, form)
-        assert gm.form(level, dt, nrhs) == form
+        gm.set_variant(level, dt, nrhs, self.variant)
+        assert gm.form(level, dt, nrhs) == form and gm.variant(level, dt, nrhs) == self.variant
 
     def __exit__(self, *exc):
         gm, level, dt, nrhs, _ = self.args
-        gm.set_form(level, dt, nrhs, ebe.FORM_AUTO)
+        gm.set_form(level, dt, nrhs, ebe.FORM_AUTO)  # (resets the variant too)
 
 
-@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("form", FORMS_V)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nrhs", [1, 3, 4, 7, 9, 16])
 def test_matvec_matches_oracle(small, dtype, nrhs, form):
@@ -65,7 +71,7 @@ def test_matvec_matches_oracle(small, dtype, nrhs, form):
                        f"matvec {dtype.__name__} n={nrhs} form={form}")
 
 
-@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("form", FORMS_V)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_matvec_with_dirichlet_projection(small, dtype, form):
     m, gm, K, _, kap = small
@@ -77,7 +83,7 @@ def test_matvec_with_dirichlet_projection(small, dtype, form):
     assert_close_bound(y, ref, abs(K), x.astype(np.float64), dtype, kap, "matvec P K P")
 
 
-@pytest.mark.parametrize("form", FORMS1)
+@pytest.mark.parametrize("form", FORMS1_V)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nrhs", [4, 7, 16])
 def test_linear_matvec_matches_oracle(small, dtype, form, nrhs):
@@ -92,7 +98,7 @@ def test_linear_matvec_matches_oracle(small, dtype, form, nrhs):
     assert_close_bound(yb, refb, abs(K1), x.astype(np.float64), dtype, kap, "P K1 P x")
 
 
-@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("form", FORMS_V)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("apply_bc", [False, True])
 def test_matvec_add_accumulates(small, dtype, form, apply_bc):
@@ -123,13 +129,16 @@ def test_autotune_keeps_the_faster_form(small):
         print(f"[autotune level {level} n={nrhs}] ms by form: {ts}", flush=True)
         have = [t for t in ts if t >= 0]
         assert len(ts) == ebe.NUM_FORMS and min(have) > 0
-        assert len(have) == (3 if level == 0 else 4) and (level == 1 or ts[ebe.FORM_ASSEMBLED] == -1)
+        assert len(have) == 4
+        assert ts[ebe.FORM_ASSEMBLED if level == 0 else ebe.FORM_COLOURED] == -1
         assert gm.form(level, torch.float32, nrhs) == ts.index(min(have))
         gm.set_form(level, torch.float32, nrhs, ebe.FORM_AUTO)
     with pytest.raises(ebe.EbeError):
         gm.set_form(0, torch.float32, 4, 7)
     with pytest.raises(ebe.EbeError):
         gm.set_form(0, torch.float32, 4, ebe.FORM_ASSEMBLED)
+    with pytest.raises(ebe.EbeError):
+        gm.set_form(1, torch.float32, 4, ebe.FORM_COLOURED)
     with pytest.raises(ebe.EbeError):
         gm.autotune(2, torch.float32, 4)
 
@@ -355,7 +364,7 @@ def shuffled(gpu_lib):
     return m, ebe.Mesh.from_generated(m), oracle_K(m), oracle_K(m, order=1), kappa_max(m)
 
 
-@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("form", FORMS_V)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nrhs", [1, 4, 16])
 def test_shuffled_mesh_matvec_matches_oracle(shuffled, dtype, nrhs, form):
@@ -373,7 +382,7 @@ def test_shuffled_mesh_matvec_matches_oracle(shuffled, dtype, nrhs, form):
     assert_close_bound(yb, fem.matvec_bc(K, xr, m.fixed), abs(K), xr, dtype, kap, "shuffled P K P x")
 
 
-@pytest.mark.parametrize("form", FORMS1)
+@pytest.mark.parametrize("form", FORMS1_V)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_shuffled_mesh_linear_matvec_matches_oracle(shuffled, dtype, form):
     m, gm, _, K1, kap = shuffled
@@ -383,3 +392,25 @@ def test_shuffled_mesh_linear_matvec_matches_oracle(shuffled, dtype, form):
     xr = x.astype(np.float64)
     ref = (K1 @ xr.reshape(-1, 7)).reshape(y.shape)
     assert_close_bound(y, ref, abs(K1), xr, dtype, kap, f"shuffled K1 x form={form}")
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_coloured_form_is_bitwise_reproducible(shuffled, dtype, variant):
+    """The coloured form sums every node in a fixed order (patch colour by
+    colour, each patch's LDS sum is written once per node), so repeated
+    products agree bit for bit; and its colours are at least the two any
+    mesh with shared nodes needs."""
+    m, gm, K, _, kap = shuffled
+    info = gm.patch_info(0)
+    print(f"[shuffled patches] {info}", flush=True)
+    assert info["colours"] >= 2 and info["patches"] >= info["colours"]
+    x = to_dev(meshgen.rng_for(79, 200).standard_normal((m.n_nodes, 3, 5)), dtype)
+    with forced_form(gm, 0, dtype, 5, (ebe.FORM_COLOURED, variant)):
+        ys = [gm.matvec(x, apply_bc=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    for y in ys[1:]:
+        assert torch.equal(y, ys[0])
+    xr = x.cpu().numpy().astype(np.float64)
+    assert_close_bound(ys[0].cpu().numpy().astype(np.float64), fem.matvec_bc(K, xr, m.fixed), abs(K), xr, dtype, kap,
+                       "coloured P K P x")

@@ -59,17 +59,19 @@ def crust(gpu_lib):
     return m, ebe.Mesh.from_generated(m), f, K, solve.sparse_solve(K, f, m.fixed)
 
 
-@pytest.mark.parametrize("form", [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_ASSEMBLED])
+@pytest.mark.parametrize("form", [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_ASSEMBLED,
+                                  ebe.FORM_COLOURED])
 def test_crust_mixed_mg2_in_each_product_form(crust, form):
     """Every product of the solve (outer FP64, inner FP32 on both levels,
     each also forming (p, K p)) in one given form (the assembled form exists
-    at the linear level only: there, with gather products on the quadratic
-    level)."""
+    at the linear level only, the coloured form at the quadratic level only:
+    elsewhere the gather form runs)."""
     m, gm, f, K, ud = crust
     keys = [(0, torch.float64), (0, torch.float32), (1, torch.float32)]
     try:
         for level, dt in keys:
-            gm.set_form(level, dt, 16, ebe.FORM_GATHER if form == ebe.FORM_ASSEMBLED and level == 0 else form)
+            only = (form == ebe.FORM_ASSEMBLED and level == 0) or (form == ebe.FORM_COLOURED and level == 1)
+            gm.set_form(level, dt, 16, ebe.FORM_GATHER if only else form)
         u, st = gm.solve(dev(f), precond=ebe.PREC_MG2, mode=ebe.MODE_MIXED, tol=1e-8)
     finally:
         for level, dt in keys:
