@@ -86,7 +86,9 @@ typedef int32_t ebe_dtype;
  * colour share a node and runs the colours one after another, each patch
  * adding its sums straight into y (the multi-colouring Section 2 uses on
  * CPUs, where Section 3.2 takes atomics on GPUs; here over patches): no
- * staging buffer, and the sum at every node is formed in a fixed order.
+ * staging buffer and no second pass; the patches' sums reach a node in a
+ * fixed (colour) order, while inside a patch the sums are LDS atomics, as
+ * in the other forms, so results agree to rounding, not bit for bit.
  * PIPELINED and COLOURED need a mesh below 2^25 nodes whose vectors at this
  * (dtype, nrhs) are below 4 GiB; elsewhere GATHER runs in their place.
  * AUTO: the mesh's tuned choice, else a fixed default. */
@@ -287,6 +289,70 @@ ebe_status ebe_pcg_solve(ebe_mesh* mesh, int32_t nrhs, const double* f_dev, doub
  * overwritten.  No scatter: each element writes its own entry (asynchronous). */
 ebe_status ebe_adjoint_grad(ebe_mesh* mesh, ebe_dtype dtype, int32_t nrhs, const void* u_dev,
                             const void* lam_dev, void* g_dev, void* stream);
+
+/* ---- Green's functions of fault slip and their inversion (Section 5) ---- */
+
+typedef struct ebe_fault ebe_fault; /* opaque; a fault and its unit-slip basis on one mesh */
+
+/* A fault for split-node loading (Section 2 cites the split-node technique
+ * for the fault) with the unit-slip basis functions of Eq. (4).  Host
+ * inputs, copied (synchronous):
+ *   sides [n_elem]: +1 / -1 for elements touching a fault node, on the two
+ *     sides of the fault; 0 for every other element;
+ *   fault_nodes [n_fault_nodes]: the fault's node ids (distinct);
+ *   basis [n_fault_nodes][n_basis]: value of basis function i at fault node k;
+ *   dirs [n_basis][3]: slip direction (a vector) of basis function i.
+ * Slip of basis function i at fault node k: basis[k][i] * dirs[i]; zero at
+ * every other node.  The mesh must outlive the fault.  Errors: EBE_ERR_INDEX
+ * (node out of range or repeated), EBE_ERR_ARG (a side other than -1/0/1, or
+ * an element touching a fault node with side 0), EBE_ERR_NONFINITE. */
+ebe_status ebe_fault_create(ebe_mesh* mesh, const int8_t* sides, int64_t n_fault_nodes, const int32_t* fault_nodes,
+                            int32_t n_basis, const double* basis, const double* dirs, ebe_fault** out);
+void ebe_fault_destroy(ebe_fault* fault);
+
+/* Split-node forces of basis functions col0 .. col0 + nrhs - 1 (nrhs 1..16):
+ * a fault node carries two displacements, u+ on the +1 side and u- on the
+ * -1 side, with u+ - u- = s; for the mean v = (u+ + u-) / 2 equilibrium
+ * gives K v = f on the unsplit mesh with
+ *     f = sum_{e, side_e != 0} -(side_e / 2) K_e s_e
+ * (s_e: the slip at element e's nodes).  f_dev [n_nodes][3][nrhs] FP64,
+ * overwritten (asynchronous).  Away from the fault v is the displacement. */
+ebe_status ebe_split_node_forces(ebe_fault* fault, int32_t col0, int32_t nrhs, double* f_dev, void* stream);
+
+/* Green's functions (Eq. (4)): for every basis function i, the displacement
+ * at the observation points due to its unit slip:
+ *   G_dev[3 s + c][i] = v_i(stations_host[s], component c),
+ * G_dev [3 n_stations][n_basis] FP64 row-major, stations_host [n_stations]
+ * node ids (host, checked: EBE_ERR_INDEX).  Basis functions are taken in sets of 16 (the
+ * paper's case sets): per set the split-node forces, one ebe_pcg_solve with
+ * opts (NULL: defaults), and the gather of the station components.  stats:
+ * [ceil(n_basis / 16)] per-set solve statistics, or NULL.  Synchronous (the
+ * solves are); allocates two [n_nodes][3][16] FP64 vectors with the fault.
+ * Returns the worst status of the solves (EBE_NOT_CONVERGED when any set
+ * missed tol). */
+ebe_status ebe_greens_functions(ebe_fault* fault, int32_t n_stations, const int32_t* stations_host, double* G_dev,
+                                const ebe_pcg_opts* opts, ebe_pcg_stats* stats, void* stream);
+
+/* Regularised least squares of Eq. (5) over a list of weights, and the
+ * L-curve corner: for each alpha_k (alphas_host[n_alpha], positive,
+ * increasing)
+ *     a_k = argmin ||G a - d||^2 + alpha_k^2 ||L a||^2,
+ * the least-squares solution of the stacked system [G; alpha_k L] a = [d; 0]
+ * by Householder QR in FP64; rho_k = ||G a_k - d||, eta_k = ||L a_k||.  With
+ * three or more weights: the curvature of the curve (log rho, log eta) as a
+ * function of log alpha (derivatives by second-order central differences on
+ * the nonuniform grid, first-order one-sided at its two ends) and the index
+ * of its largest value (Hansen's L-curve corner; the first one if tied).
+ *   G_dev [n_obs][n_basis], d_dev [n_obs], L_dev [n_reg][n_basis] (row-major,
+ *   device); a_dev [n_alpha][n_basis]; rho_dev, eta_dev, curvature_dev
+ *   [n_alpha]; corner_dev [1] int32 (curvature and corner may be NULL with
+ *   fewer than three weights).  n_basis <= 512, n_alpha <= 1024; [G; L]
+ *   must have full column rank.  Synchronous; allocates a workspace of
+ *   n_alpha (n_obs + n_reg)(n_basis + 1) doubles. */
+ebe_status ebe_invert_lcurve(int32_t n_obs, int32_t n_basis, const double* G_dev, const double* d_dev, int32_t n_reg,
+                             const double* L_dev, int32_t n_alpha, const double* alphas_host, double* a_dev,
+                             double* rho_dev, double* eta_dev, double* curvature_dev, int32_t* corner_dev,
+                             void* stream);
 
 /* ---- product forms and the autotuner ------------------------------------ */
 

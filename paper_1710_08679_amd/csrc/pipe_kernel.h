@@ -30,9 +30,10 @@
 // another.  A patch writes every one of its nodes straight into y: the first
 // patch (in colour order) to touch a node stores its sum, the later ones add
 // theirs to what y holds (node word bit 31 set).  No staging buffer, no
-// second pass, no atomics in global memory, and every node's sum is formed
-// in a fixed order (deterministic), at the price of one launch per colour
-// and a read of y for the nodes shared between colours.
+// second pass and no atomics in global memory, at the price of one launch
+// per colour and a read of y for the nodes shared between colours.  The
+// patches' sums reach a node in colour order; inside a patch they are LDS
+// atomics as in the other forms (so not bitwise reproducible).
 #pragma once
 
 #include "patch_common.h"

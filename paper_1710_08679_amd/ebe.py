@@ -33,7 +33,8 @@ EXPORTED = (
     "ebe_batch_destroy", "ebe_status_string", "ebe_last_error", "ebe_build_info", "ebe_autotune",
     "ebe_set_product_form", "ebe_get_product_form", "ebe_level2_info", "ebe_matvec_l2", "ebe_prolong_l2",
     "ebe_restrict_l2", "ebe_matvec_noalloc", "ebe_patch_info", "ebe_set_product_variant",
-    "ebe_get_product_variant",
+    "ebe_get_product_variant", "ebe_fault_create", "ebe_fault_destroy", "ebe_split_node_forces",
+    "ebe_greens_functions", "ebe_invert_lcurve",
 )
 
 
@@ -107,6 +108,11 @@ def load():
         "ebe_set_product_form": ([_vp, _i32, _i32, _i32, _i32], _i32),
         "ebe_get_product_form": ([_vp, _i32, _i32, _i32, ctypes.POINTER(_i32)], _i32),
         "ebe_set_product_variant": ([_vp, _i32, _i32, _i32, _i32], _i32),
+        "ebe_fault_create": ([_vp, _vp, _i64, _vp, _i32, _vp, _vp, ctypes.POINTER(_vp)], _i32),
+        "ebe_fault_destroy": ([_vp], None),
+        "ebe_split_node_forces": ([_vp, _i32, _i32, _vp, _vp], _i32),
+        "ebe_greens_functions": ([_vp, _i32, _vp, _vp, ctypes.POINTER(PcgOpts), _vp, _vp], _i32),
+        "ebe_invert_lcurve": ([_i32, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
         "ebe_get_product_variant": ([_vp, _i32, _i32, _i32, ctypes.POINTER(_i32)], _i32),
         "ebe_level2_info": ([_vp, ctypes.POINTER(_i64), _vp], _i32),
         "ebe_matvec_l2": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
@@ -428,3 +434,83 @@ def batch_solve(meshes, fs, us=None, opts: PcgOpts | None = None, stream=None, *
     finally:
         lib.ebe_batch_destroy(b)
     return us, [s.as_dict() for s in st]
+
+
+class Fault:
+    """A fault with unit-slip basis functions on a mesh (``ebe_fault``):
+    split-node forces and Green's functions at observation points."""
+
+    def __init__(self, mesh: "Mesh", sides, nodes, basis, dirs):
+        lib = load()
+        sides = np.ascontiguousarray(sides, dtype=np.int8)
+        nodes = np.ascontiguousarray(nodes, dtype=np.int32)
+        basis = np.ascontiguousarray(basis, dtype=np.float64)
+        dirs = np.ascontiguousarray(dirs, dtype=np.float64)
+        if sides.shape != (mesh.n_elem,) or basis.shape[0] != nodes.size or dirs.shape != (basis.shape[1], 3):
+            raise ValueError("sides (E,), basis (n_fault_nodes, n_basis), dirs (n_basis, 3)")
+        self.mesh, self.n_basis = mesh, int(basis.shape[1])
+        h = _vp()
+        _check(lib.ebe_fault_create(mesh.handle, sides.ctypes.data, nodes.size, nodes.ctypes.data, self.n_basis,
+                                    basis.ctypes.data, dirs.ctypes.data, ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_generated(cls, mesh: "Mesh", flt) -> "Fault":
+        """From a ``meshgen.Fault``."""
+        return cls(mesh, flt.sides, flt.nodes, flt.basis, flt.dirs)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().ebe_fault_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def split_node_forces(self, col0, nrhs, out=None, stream=None):
+        """f (N, 3, nrhs) float64: split-node forces of basis functions col0 .. col0 + nrhs - 1."""
+        import torch
+        if out is None:
+            out = torch.empty((self.mesh.n_nodes, 3, nrhs), dtype=torch.float64, device="cuda")
+        _check(load().ebe_split_node_forces(self._h, int(col0), int(nrhs),
+                                            _dev(out, torch.float64, (self.mesh.n_nodes, 3, nrhs), "out"),
+                                            _stream(stream)))
+        return out
+
+    def greens_functions(self, stations, opts: PcgOpts | None = None, stream=None, **kw):
+        """(G (3 m, n_basis) float64 on the device, [per-set stats]) for the m station nodes."""
+        import torch
+        st = np.ascontiguousarray(stations, dtype=np.int32)
+        G = torch.empty((3 * st.size, self.n_basis), dtype=torch.float64, device="cuda")
+        nset = (self.n_basis + MAX_RHS - 1) // MAX_RHS
+        stats = (PcgStats * nset)()
+        if opts is None:
+            opts = default_opts(**kw)
+        _check(load().ebe_greens_functions(self._h, st.size, st.ctypes.data, _dev(G), ctypes.byref(opts), stats,
+                                           _stream(stream)))
+        return G, [x.as_dict() for x in stats]
+
+
+def invert_lcurve(G, d, L, alphas, stream=None):
+    """Eq. (5) over the weights: returns (a (n_alpha, n_basis), rho, eta, curvature, corner) on the device
+    (curvature and corner None with fewer than three weights).  G (n_obs, n_basis), d (n_obs,),
+    L (n_reg, n_basis): float64 CUDA tensors; alphas: host sequence, positive and increasing."""
+    import torch
+    al = np.ascontiguousarray(alphas, dtype=np.float64)
+    nobs, nb = G.shape
+    nreg = L.shape[0]
+    _dev(G, torch.float64, (nobs, nb), "G")
+    _dev(d, torch.float64, (nobs,), "d")
+    _dev(L, torch.float64, (nreg, nb), "L")
+    a = torch.empty((al.size, nb), dtype=torch.float64, device=G.device)
+    rho = torch.empty(al.size, dtype=torch.float64, device=G.device)
+    eta = torch.empty_like(rho)
+    curv = torch.empty_like(rho) if al.size >= 3 else None
+    corner = torch.empty(1, dtype=torch.int32, device=G.device) if al.size >= 3 else None
+    _check(load().ebe_invert_lcurve(nobs, nb, _dev(G), _dev(d), nreg, _dev(L), al.size, al.ctypes.data, _dev(a),
+                                    _dev(rho), _dev(eta), None if curv is None else _dev(curv),
+                                    None if corner is None else _dev(corner), _stream(stream)))
+    return a, rho, eta, curv, (None if corner is None else int(corner.item()))

@@ -416,6 +416,24 @@ def dipping_fault(mesh: Mesh, c: float, strike_range, dip_range, knots) -> Fault
                  basis=basis, dirs=dirs, knots=(ns, nd))
 
 
+def laplacian_regularizer(ns: int, nd: int, ndir: int = 2) -> np.ndarray:
+    """The regularisation operator of the inversion (an input of Eq. (5)):
+    per slip direction, the five-point discrete Laplacian over the (ns x nd)
+    grid of basis functions with zero slip beyond the grid; basis ordered
+    direction-major, then (strike i, dip j) with j fastest, as in Fault."""
+    n1 = ns * nd
+    L = np.zeros((ndir * n1, ndir * n1))
+    idx = np.arange(n1).reshape(ns, nd)
+    for dct in range(ndir):
+        o = dct * n1
+        L[o + idx, o + idx] = 4.0
+        L[o + idx[1:, :], o + idx[:-1, :]] = -1.0
+        L[o + idx[:-1, :], o + idx[1:, :]] = -1.0
+        L[o + idx[:, 1:], o + idx[:, :-1]] = -1.0
+        L[o + idx[:, :-1], o + idx[:, 1:]] = -1.0
+    return L
+
+
 def surface_stations(mesh: Mesh, step: int) -> np.ndarray:
     """Top-surface nodes on every `step`-th corner line in x and y (refined
     coordinates multiples of 2 step, not on the domain's side faces): the
