@@ -138,20 +138,22 @@ def solver_block(torch, ebe, meshgen, modes):
            "elements": m.n_elem, "dof": m.n_dof, "runs": []}
     sols = {}
     ref = None
-    table = {"mixed_mg3": (ebe.PREC_MG3, ebe.MODE_MIXED), "fp64_mg3": (ebe.PREC_MG3, ebe.MODE_FP64),
+    table = {"mixed_mg3": (ebe.PREC_MG3, ebe.MODE_MIXED), "mixed_mg3_fp16coarse": (ebe.PREC_MG3, ebe.MODE_MIXED),
+             "fp64_mg3": (ebe.PREC_MG3, ebe.MODE_FP64),
              "mixed_mg2": (ebe.PREC_MG2, ebe.MODE_MIXED), "fp64_mg2": (ebe.PREC_MG2, ebe.MODE_FP64),
              "fp64_pcge": (ebe.PREC_PCGE, ebe.MODE_FP64)}
     for name in modes:
         precond, mode = table[name]
+        half = int(name.endswith("fp16coarse"))
         torch.cuda.synchronize()
         tw = time.perf_counter()
-        gm.solve(fd, precond=precond, mode=mode, tol=1e-8)  # warm-up: block Jacobi, level-2 set-up, workspace
+        gm.solve(fd, precond=precond, mode=mode, tol=1e-8, coarse_half=half)  # warm-up: set-ups, workspace
         torch.cuda.synchronize()
         t_first = time.perf_counter() - tw
         times, u, st = [], None, None
         for _ in range(3):
             t0 = time.perf_counter()
-            u, st = gm.solve(fd, precond=precond, mode=mode, tol=1e-8)
+            u, st = gm.solve(fd, precond=precond, mode=mode, tol=1e-8, coarse_half=half)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
         dt = sorted(times)[1]
@@ -292,7 +294,15 @@ def batch_block(torch, ebe, meshgen, n_mesh, with_big, keep):
         fs.append(torch.from_numpy(f).cuda())
         log(f"# batch mesh {k}: grid {gr}, {m.n_elem} tets, {n} cases")
     opts = ebe.default_opts(tol=1e-8)
-    ebe.batch_solve(gms, fs, opts=opts)  # warm-up: block Jacobi, level 2, workspaces, product forms
+    # streams only (no merged meshes), then the default (small meshes merged)
+    ebe.batch_solve(gms, fs, opts=opts, merge_elems=0)  # warm-up: block Jacobi, level 2, workspaces, forms
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ebe.batch_solve(gms, fs, opts=opts, merge_elems=0)
+    torch.cuda.synchronize()
+    tu = time.perf_counter() - t0
+    info = {}
+    ebe.batch_solve(gms, fs, opts=opts, info=info)  # warm-up of the merged meshes (built here)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     us, st_b = ebe.batch_solve(gms, fs, opts=opts)
@@ -306,11 +316,14 @@ def batch_block(torch, ebe, meshgen, n_mesh, with_big, keep):
     out = {"workload": f"{n_mesh} crust meshes, log-uniform 5e4..2e6 tets, 1..16 cases each"
                        + (" + 128x128x64 (16 cases)" if with_big else "") + ", mixed MG3 to 1e-8",
            "n_mesh": len(grids), "elements_total": int(sum(g.n_elem for g in gms)), "cases_total": cases,
-           "batch_seconds": tb, "sequential_seconds": ts, "speedup": ts / tb,
+           "batch_seconds": tb, "batch_streams_only_seconds": tu, "sequential_seconds": ts, "speedup": ts / tb,
+           "merged_groups": info.get("groups"),
+           "merged_meshes": int(sum(1 for g in info.get("group_of", []) if g >= 0)),
            "solves_per_s_batch": cases / tb, "solves_per_s_sequential": cases / ts,
            "max_rel_res": max(s["max_rel_res"] for s in st_b),
            "all_converged": all(s["status"] == ebe.OK for s in st_b + st_s)}
-    log(f"# batch: {tb:.3f} s batched vs {ts:.3f} s one by one, {cases} cases")
+    log(f"# batch: {tb:.3f} s batched ({info.get('groups')} merged groups), {tu:.3f} s streams only, "
+        f"{ts:.3f} s one by one, {cases} cases")
     small = sorted(range(len(meshes)), key=lambda i: meshes[i].n_elem)[:keep]
     kept = [(i, meshes[i], fs[i].cpu().numpy(), us[i].cpu().numpy()) for i in small]
     return out, kept
@@ -413,7 +426,7 @@ def main():
     ap.add_argument("--no-solver", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-greens", action="store_true")
-    ap.add_argument("--solver-modes", default="mixed_mg3,fp64_mg3,mixed_mg2,fp64_mg2,fp64_pcge")
+    ap.add_argument("--solver-modes", default="mixed_mg3,mixed_mg3_fp16coarse,fp64_mg3,mixed_mg2,fp64_mg2,fp64_pcge")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=200000)
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle residual threads (0: min(16, cpus))")

@@ -126,7 +126,10 @@ typedef struct {
                            inner steps (and of PCGE outer steps) enqueued between two
                            convergence checks; needs a stream other than NULL (the legacy
                            default stream cannot be captured), else ignored */
-  int32_t reserved;     /* 0 */
+  int32_t coarse_half;  /* 1: (MIXED with MG2 / MG3) the linear level applies K1 assembled and
+                           stored in FP16, and level 2 its A2 in FP16 (values scaled by the largest
+                           magnitude over 2^14; FP32 arithmetic): a low-precision preconditioner
+                           experiment that halves the coarse operators' traffic; 0 (default): off */
 } ebe_pcg_opts;
 
 typedef struct {
@@ -139,6 +142,9 @@ typedef struct {
                               falls back to EBE_PREC_MG2 on a mesh whose level-2 rows are too long
                               for the level-2 set-up (more than 800 coupled aggregates) */
   int32_t graphs_captured; /* HIP graphs captured (not replayed) during this solve */
+  int32_t merged;          /* ebe_batch_solve: number of meshes solved together in the merged
+                              system that produced this result (0: solved on its own) */
+  int32_t reserved;        /* 0 */
 } ebe_pcg_stats;
 
 /* ---- mesh ------------------------------------------------------------- */
@@ -389,8 +395,20 @@ ebe_status ebe_get_product_variant(const ebe_mesh* mesh, int32_t level, ebe_dtyp
 /* ---- batches: many meshes / case sets solved together ------------------ */
 
 /* A batch runs the solves of several meshes, each with its own nrhs (1..16),
- * several at a time so that meshes too small to fill the GPU share it
- * (Section 5 solves its case sets one after another; here they overlap).
+ * so that meshes too small to fill the GPU share it (Section 5 solves its
+ * case sets one after another).  Meshes of at most merge_elems elements
+ * (default 150,000; ebe_batch_set_merge) are grouped by case count (bands
+ * 9-16, 5-8, 3-4, 1-2) into merged block-diagonal meshes of at most 1M
+ * elements, built on the first solve from the members' device copies: one
+ * solve of a merged mesh runs every product and vector pass as one launch
+ * over all its members' element patches (and replays its inner loops as
+ * captured HIP graphs).  A member's cases are scaled to unit norm in the
+ * merged system, which is solved to tol / sqrt(members), so each member's own
+ * relative residual is at most tol; after the solve each member's residual
+ * ||P(f - K u)|| / ||P f|| is recomputed with its own operator and reported in
+ * its stats (max_rel_res; merged = number of members).  Merged groups and the
+ * other meshes are solved several at a time on worker streams, largest
+ * first.
  * ebe_batch_create: meshes[n_mesh] distinct handles on one device, nrhs[n_mesh];
  *   the batch keeps the pointers (the meshes must outlive it) and creates its
  *   own worker streams (default priority).
@@ -406,6 +424,13 @@ ebe_status ebe_batch_create(ebe_mesh* const* meshes, int32_t n_mesh, const int32
 ebe_status ebe_batch_solve(ebe_batch* batch, const double* const* f_dev, double* const* u_dev,
                            const ebe_pcg_opts* opts, ebe_pcg_stats* stats, void* stream);
 void ebe_batch_destroy(ebe_batch* batch);
+/* Merge meshes of at most max_elems elements (0: merge none); takes effect at
+ * the next solve (the merged meshes are rebuilt). */
+ebe_status ebe_batch_set_merge(ebe_batch* batch, int64_t max_elems);
+/* Number of merged groups and (group_of [n_mesh] or NULL) each mesh's group,
+ * -1 for a mesh solved on its own; plans the groups if no solve has yet
+ * (synchronous). */
+ebe_status ebe_batch_info(ebe_batch* batch, int32_t* n_groups, int32_t* group_of);
 
 /* ---- diagnostics ------------------------------------------------------- */
 

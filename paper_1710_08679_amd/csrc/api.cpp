@@ -105,6 +105,30 @@ ebe_status ensure_level2(ebe_mesh* m, ebe_dtype dt, hipStream_t s) {
   return EBE_OK;
 }
 
+ebe_status ensure_half(ebe_mesh* m, int level, hipStream_t s) {
+  AsmOp& op = level == 2 ? m->a2 : m->k1;
+  if (op.ready16) return EBE_OK;
+  ebe_status st = level == 2 ? ensure_level2(m, EBE_F64, s) : ensure_assembled(m, EBE_F64, s);
+  if (st != EBE_OK) return st;
+  const int64_t n = op.slots * 9 * kSliceRows;
+  DBuf mx;
+  if ((st = op.val16.alloc(std::max<size_t>(size_t(n) * 2, 2))) != EBE_OK) return st;
+  if ((st = mx.alloc(sizeof(unsigned long long))) != EBE_OK) return st;
+  EBE_TRY_HIP(launch_absmax(op.val[0].as<double>(), n, mx.as<unsigned long long>(), s));
+  unsigned long long bits = 0;
+  EBE_TRY_HIP(hipMemcpyAsync(&bits, mx.as<void>(), sizeof(bits), hipMemcpyDeviceToHost, s));
+  EBE_TRY_HIP(hipStreamSynchronize(s));
+  double amax = 0.0;
+  std::memcpy(&amax, &bits, sizeof(amax));
+  // values scaled so the largest is 2^14: inside FP16's range with room, small
+  // entries keep FP16's 11-bit significand down to 2^-14 of the largest
+  op.half_scale = amax > 0.0 ? amax / 16384.0 : 1.0;
+  EBE_TRY_HIP(launch_to_f16(op.val[0].as<double>(), op.val16.as<void>(), n, 1.0 / op.half_scale, s));
+  EBE_TRY_HIP(hipStreamSynchronize(s));
+  op.ready16 = true;
+  return EBE_OK;
+}
+
 ebe_status prepare_products(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, hipStream_t s) {
   ebe_status st = ensure_stage(m, nrhs, dt == EBE_F64 ? 8 : 4);
   if (st == EBE_OK) st = ensure_geometry(m, dt, s);

@@ -75,7 +75,7 @@ ebe_status upload_asm(AsmOp& op, int64_t rows, const std::vector<int32_t>& soff,
   if (st == EBE_OK) st = up(op.col, scol, s);
   op.rows = rows;
   op.slots = soff.back();
-  op.ready[0] = op.ready[1] = false;
+  op.ready[0] = op.ready[1] = op.ready16 = false;
   return st;
 }
 

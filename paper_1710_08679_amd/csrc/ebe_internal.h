@@ -62,6 +62,11 @@ struct AsmOp {
   DBuf val[2];  // [slots][9][kSliceRows] block values (row-major 3x3), per dtype (F64, F32)
   int64_t rows = 0, slots = 0;
   bool ready[2] = {false, false};
+  // FP16 copy of the values divided by half_scale (the largest magnitude
+  // over 2^14), for the coarse levels of a mixed solve with coarse_half set
+  DBuf val16;
+  double half_scale = 1.0;
+  bool ready16 = false;
 };
 
 // Solver workspace; grown to the largest nrhs seen.
@@ -246,6 +251,15 @@ hipError_t launch_ebe_p1(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* 
 // y = A2 x at level 2 (its values must be prepared: ensure_level2)
 hipError_t launch_level2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in, bool bc,
                          bool add, const int* gate, hipStream_t s, double* gamma = nullptr);
+// y = A x in FP32 from the FP16 values of an assembled operator (level 1: K1,
+// level 2: A2; ensure_half first)
+hipError_t launch_asm_half(const ebe_mesh* m, int level, int nrhs, const float* x, float* y, bool mask_in, bool bc,
+                           bool add, const int* gate, hipStream_t s, double* gamma = nullptr);
+// FP16 values of an assembled operator from its FP64 values (allocates; synchronous)
+ebe_status ensure_half(ebe_mesh* m, int level, hipStream_t s);
+// out = bit pattern of max |a_i| (device, one 64-bit word); b = FP16(a * inv_scale)
+hipError_t launch_absmax(const double* a, int64_t n, unsigned long long* out, hipStream_t s);
+hipError_t launch_to_f16(const double* a, void* b, int64_t n, double inv_scale, hipStream_t s);
 hipError_t launch_ebe(const ebe_mesh* m, int order, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in,
                       bool bc, bool add, const int* gate, hipStream_t s, double* gamma = nullptr);
 // the same with the product form given (0 <= form < EBE_NUM_FORMS)

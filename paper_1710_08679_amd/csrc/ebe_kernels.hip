@@ -273,19 +273,21 @@ constexpr int asm_rows() { return 256 / (NR / asm_cpl<T, NR>()); }
 template <typename T, int NR>
 constexpr int asm_threads() { return asm_rows<T, NR>() * (NR / asm_cpl<T, NR>()); }
 
-template <typename T, int NR>
+// S: the stored value type (T, or FP16 holding the values divided by vscale,
+// which multiplies each row's sums at the end).
+template <typename T, int NR, typename S = T>
 __global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
-    const int32_t* __restrict__ soff, const int32_t* __restrict__ col, const T* __restrict__ val,
+    const int32_t* __restrict__ soff, const int32_t* __restrict__ col, const S* __restrict__ val,
     const uint8_t* __restrict__ fix, const T* __restrict__ x, T* __restrict__ y, int64_t nv, int mask_in, int bc,
     int add, double* __restrict__ gamma, double* __restrict__ gslot, unsigned* __restrict__ gcount,
-    const int* __restrict__ gate) {
+    const int* __restrict__ gate, T vscale = T(1)) {
   constexpr int W = 3 * NR;
   constexpr int CPL = asm_cpl<T, NR>();
   constexpr int LPR = NR / CPL;  // work-items per row
   constexpr int RPB = asm_rows<T, NR>();
   constexpr int VW = CPL * int(sizeof(T)) > 16 ? 16 / int(sizeof(T)) : CPL;  // values per (<= 16-byte) vector
   constexpr int NVEC = CPL / VW;
-  constexpr int S = kSliceRows;
+  constexpr int SR = kSliceRows;
   constexpr int U = sizeof(T) == 4 ? EBE_ASM_UNROLL_F32 : EBE_ASM_UNROLL_F64;  // slots per trip
   using V = VecT<T, VW>;
   __shared__ double gsum[NR];
@@ -312,8 +314,8 @@ __global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
   for (int64_t ch = stop - cq - (xcd < cr ? 1 : 0) + int64_t(blockIdx.x) / kXcds; ch < stop; ch += wx) {
     const int64_t v = ch * RPB + lr;
     if (v >= nv) continue;
-    const int64_t sl = v / S;
-    const int r = int(v - sl * S);
+    const int64_t sl = v / SR;
+    const int r = int(v - sl * SR);
     T acc[3][CPL];
 #pragma unroll
     for (int q = 0; q < 3; ++q)
@@ -327,14 +329,14 @@ __global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
     const int32_t* cp = col + r;
     int32_t wn[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) wn[u] = cp[size_t(min(kb + u, k1 - 1)) * S];
+    for (int u = 0; u < U; ++u) wn[u] = cp[size_t(min(kb + u, k1 - 1)) * SR];
     for (int32_t k = kb; k < k1; k += U) {
       int32_t w[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) w[u] = wn[u];
       if (k + U < k1) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) wn[u] = cp[size_t(min(k + U + u, k1 - 1)) * S];
+        for (int u = 0; u < U; ++u) wn[u] = cp[size_t(min(k + U + u, k1 - 1)) * SR];
       }
       T xc[U][3][CPL];
       T b[U][9];
@@ -350,9 +352,9 @@ __global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
             for (int t = 0; t < VW; ++t) xc[u][c][q * VW + t] = xv.v[t];
           }
         }
-        const T* a = val + size_t(min(k + u, k1 - 1)) * 9 * S + r;
+        const S* a = val + size_t(min(k + u, k1 - 1)) * 9 * kSliceRows + r;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) b[u][i] = a[i * S];
+        for (int i = 0; i < 9; ++i) b[u][i] = T(a[i * kSliceRows]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -369,6 +371,12 @@ __global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
           for (int t = 0; t < CPL; ++t)
             acc[q][t] += b[u][3 * q] * xc[u][0][t] + b[u][3 * q + 1] * xc[u][1][t] + b[u][3 * q + 2] * xc[u][2][t];
       }
+    }
+    if constexpr (!std::is_same<S, T>::value) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) acc[q][t] *= vscale;
     }
     const int fb = fix[v];
     if (gamma) {
@@ -450,6 +458,22 @@ hipError_t launch_asm_p(const ebe_mesh* m, const AsmOp& op, const uint8_t* fix, 
                      static_cast<const T*>(x), static_cast<T*>(y), op.rows, int(mask_in), int(bc), int(add), gamma,
                      m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64),
                      gate);
+  return hipGetLastError();
+}
+
+template <int NR>
+hipError_t launch_asm_half_p(const ebe_mesh* m, const AsmOp& op, const uint8_t* fix, const float* x, float* y,
+                             bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess || cus < 1)
+    cus = 256;
+  constexpr int RPB = asm_rows<float, NR>();
+  const int64_t grid =
+      std::max<int64_t>(1, std::min<int64_t>((op.rows + RPB - 1) / RPB, int64_t(EBE_ASM_WG_PER_CU) * cus));
+  hipLaunchKernelGGL((k_assembled<float, NR, _Float16>), dim3(unsigned(grid)), dim3(asm_threads<float, NR>()), 0, s,
+                     op.soff.as<int32_t>(), op.col.as<int32_t>(), op.val16.as<_Float16>(), fix, x, y, op.rows,
+                     int(mask_in), int(bc), int(add), gamma, m->gacc.as<double>(),
+                     reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64), gate, float(op.half_scale));
   return hipGetLastError();
 }
 
@@ -638,6 +662,22 @@ hipError_t launch_ebe_p2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* 
 hipError_t launch_ebe_p1(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool bc,
                          hipStream_t s) {
   return launch_ebe(m, 1, dt, nrhs, x, y, bc, bc, false, nullptr, s);
+}
+
+hipError_t launch_asm_half(const ebe_mesh* m, int level, int nrhs, const float* x, float* y, bool mask_in, bool bc,
+                           bool add, const int* gate, hipStream_t s, double* gamma) {
+  const AsmOp& op = level == 2 ? m->a2 : m->k1;
+  if (nrhs < 1 || nrhs > EBE_MAX_RHS || (level != 1 && level != 2) || !op.ready16 || op.rows < 1)
+    return hipErrorInvalidValue;  // values not prepared: host bug
+  const uint8_t* fix = level == 2 ? m->cfix.as<uint8_t>() : m->fix.as<uint8_t>();
+  switch (nrhs) {
+#define EBE_CASE(n) \
+  case n: return launch_asm_half_p<n>(m, op, fix, x, y, mask_in, bc, add, gate, s, gamma);
+    EBE_CASE(1) EBE_CASE(2) EBE_CASE(3) EBE_CASE(4) EBE_CASE(5) EBE_CASE(6) EBE_CASE(7) EBE_CASE(8)
+    EBE_CASE(9) EBE_CASE(10) EBE_CASE(11) EBE_CASE(12) EBE_CASE(13) EBE_CASE(14) EBE_CASE(15) EBE_CASE(16)
+#undef EBE_CASE
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_level2(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in, bool bc,

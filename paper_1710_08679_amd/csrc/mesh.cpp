@@ -353,8 +353,8 @@ ebe_status ebe_mesh_set_material(ebe_mesh* m, const double* young_dev, const dou
   EBE_TRY_HIP(launch_lame(m, s));
   m->minv_ready = false;
   m->geo_ready[0] = m->geo_ready[1] = false;
-  m->k1.ready[0] = m->k1.ready[1] = false;
-  m->a2.ready[0] = m->a2.ready[1] = false;
+  m->k1.ready[0] = m->k1.ready[1] = m->k1.ready16 = false;
+  m->a2.ready[0] = m->a2.ready[1] = m->a2.ready16 = false;
   return EBE_OK;
 }
 

@@ -377,6 +377,22 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ a,
     b[i] = float(a[i]);
 }
 
+// largest |a_i| (non-negative doubles order as their bit patterns)
+__global__ __launch_bounds__(kBlock) void k_absmax(const double* __restrict__ a, int64_t n,
+                                                   unsigned long long* __restrict__ out) {
+  double mx = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    mx = fmax(mx, fabs(a[i]));
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(mx)));
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_f16(const double* __restrict__ a, _Float16* __restrict__ b, int64_t n,
+                                                   double inv_scale) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    b[i] = _Float16(float(a[i] * inv_scale));
+}
+
 __global__ __launch_bounds__(kBlock) void k_check_material(const double* __restrict__ E,
                                                            const double* __restrict__ nu,
                                                            int* __restrict__ bad, int64_t n) {
@@ -450,6 +466,23 @@ hipError_t launch_assemble_a2(const ebe_mesh* m, bool assemble, bool f32, hipStr
   if (g > 65536) g = 65536;
   hipLaunchKernelGGL(k_to_f32, dim3(unsigned(g)), dim3(kBlock), 0, s, m->a2.val[0].as<double>(),
                      m->a2.val[1].as<float>(), nval);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const double* a, int64_t n, unsigned long long* out, hipStream_t s) {
+  hipError_t e = launch_fill_zero(out, sizeof(unsigned long long), s);
+  if (e != hipSuccess || n == 0) return e;
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_absmax, dim3(unsigned(g)), dim3(kBlock), 0, s, a, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f16(const double* a, void* b, int64_t n, double inv_scale, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_to_f16, dim3(unsigned(g)), dim3(kBlock), 0, s, a, static_cast<_Float16*>(b), n, inv_scale);
   return hipGetLastError();
 }
 

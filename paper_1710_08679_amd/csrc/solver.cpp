@@ -142,24 +142,30 @@ uintptr_t addr(const void* p) { return reinterpret_cast<uintptr_t>(p); }
 // The level's operator: EBE products on levels 0 and 1, the assembled A2 on level 2.
 template <typename T>
 hipError_t level_product(const ebe_mesh* m, int level, int nr, const T* x, T* y, const int* gate, hipStream_t s,
-                         double* gamma = nullptr) {
+                         double* gamma = nullptr, bool half = false) {
   // all solver vectors are kept zero on fixed DOFs, so inputs need no masking
+  if constexpr (sizeof(T) == 4) {
+    if (half && level >= 1) return launch_asm_half(m, level, nr, x, y, false, true, false, gate, s, gamma);
+  }
   if (level == 2) return launch_level2(m, dtype_of<T>(), nr, x, y, false, true, false, gate, s, gamma);
   return launch_ebe(m, level == 0 ? 2 : 1, dtype_of<T>(), nr, x, y, false, true, false, gate, s, gamma);
 }
 
 template <typename T>
 ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int nr, double eps, int nmax,
-                       bool graphs, SolverState& st, hipStream_t s) {
+                       bool graphs, bool half, SolverState& st, hipStream_t s) {
   InnerScalars* din = &st.sc->inner[level];
-  EBE_K(level_product<T>(m, level, nr, u, q, &st.sc->outer_active, s));
+  half = half && sizeof(T) == 4 && level >= 1;
+  EBE_K(level_product<T>(m, level, nr, u, q, &st.sc->outer_active, s, nullptr, half));
   EBE_K(sk_inner_init<T>(m, level, r, q, e, nr, eps, nmax, st, s));
   int enq = 0;
   int chunk = level == 0 ? 3 : (level == 1 ? 4 : 8);
   while (enq < nmax - 1) {
     const int k = std::min(chunk, nmax - 1 - enq);
     const void* data = level == 2 ? m->a2.val[sizeof(T) == 8 ? 0 : 1].as<void>() : m->pl[level].stage.as<void>();
-    const uintptr_t form = level == 2 ? uintptr_t(EBE_FORM_ASSEMBLED) : product_key(m, level == 0 ? 2 : 1, dtype_of<T>(), nr);
+    const uintptr_t form = half ? uintptr_t(64)  // the FP16 assembled operator
+                                : (level == 2 ? uintptr_t(EBE_FORM_ASSEMBLED)
+                                              : product_key(m, level == 0 ? 2 : 1, dtype_of<T>(), nr));
     ebe_status rs = enqueue_steps(
         m,
         {1, uintptr_t(level), uintptr_t(k), uintptr_t(nr), sizeof(T), uintptr_t(form), addr(e), addr(p), addr(q),
@@ -169,7 +175,7 @@ ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int
         graphs, s, [&]() -> ebe_status {
           for (int c = 0; c < k; ++c) {
             EBE_K(sk_inner_p<T>(m, level, e, p, q, nr, st, s));
-            EBE_K(level_product<T>(m, level, nr, p, q, &din->active, s, din->gamma));
+            EBE_K(level_product<T>(m, level, nr, p, q, &din->active, s, din->gamma, half));
             EBE_K(sk_inner_update<T>(m, level, e, u, q, p, nr, eps, nmax, st, s));
           }
           return EBE_OK;
@@ -208,16 +214,18 @@ ebe_status mg_precondition(ebe_mesh* m, int nr, const ebe_pcg_opts& o, const Buf
     EBE_K(launch_restrict_p2(m, dt, nr, r1, r2, s));           // r2 <= P2^T r1
     EBE_K(launch_restrict_p2(m, dt, nr, u1, u2, s));           // u2 <= P2^T u1
     ebe_status r2s = inner_solve<T>(m, 2, r2, u2, static_cast<T*>(b.e2), static_cast<T*>(b.p2),
-                                    static_cast<T*>(b.q2), nr, o.inner_eps[2], o.inner_max[2], o.graphs != 0, st, s);
+                                    static_cast<T*>(b.q2), nr, o.inner_eps[2], o.inner_max[2], o.graphs != 0,
+                                    o.coarse_half != 0, st, s);
     if (r2s != EBE_OK) return r2s;
     EBE_K(launch_prolong_p2(m, dt, nr, u2, u1, s));            // u1 <= P2 u2
   }
   ebe_status rs = inner_solve<T>(m, 1, r1, u1, static_cast<T*>(b.e1), static_cast<T*>(b.p1),
-                                 static_cast<T*>(b.q1), nr, o.inner_eps[1], o.inner_max[1], o.graphs != 0, st, s);
+                                 static_cast<T*>(b.q1), nr, o.inner_eps[1], o.inner_max[1], o.graphs != 0,
+                                 o.coarse_half != 0, st, s);
   if (rs != EBE_OK) return rs;
   EBE_K(launch_prolong(m, dt, nr, u1, ub, true, s));           // u_bar <= P1 u1
   rs = inner_solve<T>(m, 0, rb, ub, static_cast<T*>(b.e0), static_cast<T*>(b.p0), static_cast<T*>(b.q0), nr,
-                      o.inner_eps[0], o.inner_max[0], o.graphs != 0, st, s);
+                      o.inner_eps[0], o.inner_max[0], o.graphs != 0, false, st, s);
   if (rs != EBE_OK) return rs;
   EBE_K(sk_outer_z_cast<T>(m, ub, b.r, b.q, nr, st, s));  // z = u_bar: (z,q), (z,r), beta
   EBE_K(sk_outer_p_cast<T>(m, ub, b.p, nr, st, s));       // p <= z + beta p
@@ -229,7 +237,8 @@ ebe_status check_opts(const ebe_pcg_opts& o) {
       (o.mode != EBE_MODE_FP64 && o.mode != EBE_MODE_MIXED) || !(o.tol > 0.0) || o.max_outer < 1 ||
       o.check_every < 1 || o.inner_max[0] < 1 || o.inner_max[1] < 1 || o.inner_max[2] < 1 ||
       !(o.inner_eps[0] >= 0.0) || !(o.inner_eps[1] >= 0.0) || !(o.inner_eps[2] >= 0.0) ||
-      (o.coarse_guess != 0 && o.coarse_guess != 1) || (o.graphs != 0 && o.graphs != 1)) {
+      (o.coarse_guess != 0 && o.coarse_guess != 1) || (o.graphs != 0 && o.graphs != 1) ||
+      (o.coarse_half != 0 && o.coarse_half != 1)) {
     set_error("ebe_pcg_solve: invalid options");
     return EBE_ERR_ARG;
   }
@@ -322,6 +331,9 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   for (int t = 0; t < (mg ? 3 : 1); ++t)
     if ((st_ = prepare_products(m, tunes[t].level, tunes[t].dt, nr, s)) != EBE_OK) return st_;
   if (o.precond == EBE_PREC_MG3 && (st_ = ensure_level2(m, inner_dt, s)) != EBE_OK) return st_;
+  if (o.coarse_half && o.mode != EBE_MODE_MIXED) o.coarse_half = 0;  // FP16 coarse operators feed FP32 loops only
+  if (mg && o.coarse_half && (st_ = ensure_half(m, 1, s)) != EBE_OK) return st_;
+  if (o.precond == EBE_PREC_MG3 && o.coarse_half && (st_ = ensure_half(m, 2, s)) != EBE_OK) return st_;
 
   EBE_K(launch_fill_zero(st.sc, sizeof(SolverScalars), s));
   EBE_K(launch_fill_zero(st.counter, 64, s));

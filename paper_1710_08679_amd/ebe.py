@@ -34,7 +34,7 @@ EXPORTED = (
     "ebe_set_product_form", "ebe_get_product_form", "ebe_level2_info", "ebe_matvec_l2", "ebe_prolong_l2",
     "ebe_restrict_l2", "ebe_matvec_noalloc", "ebe_patch_info", "ebe_set_product_variant",
     "ebe_get_product_variant", "ebe_fault_create", "ebe_fault_destroy", "ebe_split_node_forces",
-    "ebe_greens_functions", "ebe_invert_lcurve",
+    "ebe_greens_functions", "ebe_invert_lcurve", "ebe_batch_set_merge", "ebe_batch_info",
 )
 
 
@@ -43,20 +43,21 @@ class PcgOpts(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("inner_eps", ctypes.c_double * 3), ("inner_max", ctypes.c_int32 * 3),
                 ("use_x0", ctypes.c_int32), ("coarse_guess", ctypes.c_int32), ("graphs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("coarse_half", ctypes.c_int32)]
 
 
 class PcgStats(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("inner_iters", ctypes.c_int64 * 3), ("max_rel_res", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("precond_used", ctypes.c_int32),
-                ("graphs_captured", ctypes.c_int32)]
+                ("graphs_captured", ctypes.c_int32), ("merged", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"outer_iters": self.outer_iters, "status": self.status,
                 "inner_iters": [int(v) for v in self.inner_iters],
                 "max_rel_res": self.max_rel_res, "seconds": self.seconds,
-                "precond_used": self.precond_used, "graphs_captured": self.graphs_captured}
+                "precond_used": self.precond_used, "graphs_captured": self.graphs_captured,
+                "merged": self.merged}
 
 
 class EbeError(RuntimeError):
@@ -101,6 +102,8 @@ def load():
         "ebe_batch_solve": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(PcgOpts),
                              ctypes.POINTER(PcgStats), _vp], _i32),
         "ebe_batch_destroy": ([_vp], None),
+        "ebe_batch_set_merge": ([_vp, _i64], _i32),
+        "ebe_batch_info": ([_vp, ctypes.POINTER(_i32), _vp], _i32),
         "ebe_status_string": ([_i32], ctypes.c_char_p),
         "ebe_last_error": ([], ctypes.c_char_p),
         "ebe_build_info": ([], ctypes.c_char_p),
@@ -408,8 +411,11 @@ class Mesh:
         return u, st.as_dict()
 
 
-def batch_solve(meshes, fs, us=None, opts: PcgOpts | None = None, stream=None, **kw):
-    """Solve several meshes (each with its own nrhs) as one batch; returns (us, [stats])."""
+def batch_solve(meshes, fs, us=None, opts: PcgOpts | None = None, stream=None, merge_elems=None, info=None,
+                **kw):
+    """Solve several meshes (each with its own nrhs) as one batch; returns (us, [stats]).
+    merge_elems: merge meshes up to this many elements (None: the library default, 0: none);
+    info: a dict that receives the merged groups ({"groups": g, "group_of": [...]})."""
     import torch
     lib = load()
     n = len(meshes)
@@ -425,6 +431,13 @@ def batch_solve(meshes, fs, us=None, opts: PcgOpts | None = None, stream=None, *
     b = _vp()
     _check(lib.ebe_batch_create(hs, n, nr, ctypes.byref(b)))
     try:
+        if merge_elems is not None:
+            _check(lib.ebe_batch_set_merge(b, int(merge_elems)))
+        if info is not None:
+            ng = _i32()
+            gof = np.empty(n, dtype=np.int32)
+            _check(lib.ebe_batch_info(b, ctypes.byref(ng), gof.ctypes.data))
+            info["groups"], info["group_of"] = int(ng.value), gof.tolist()
         fp = (_vp * n)(*[f.data_ptr() for f in fs])
         up = (_vp * n)(*[u.data_ptr() for u in us])
         st = (PcgStats * n)()

@@ -59,7 +59,7 @@ def test_struct_layouts_match_header(tmp_path):
     """The binding's ctypes structures match the C header, field by field:
     a C program built from include/ebe.h prints sizes and offsets."""
     assert ctypes.sizeof(ebe.PcgOpts) == 80
-    assert ctypes.sizeof(ebe.PcgStats) == 56
+    assert ctypes.sizeof(ebe.PcgStats) == 64
     fields = {"ebe_pcg_opts": ebe.PcgOpts, "ebe_pcg_stats": ebe.PcgStats}
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "ebe.h"', "int main(void) {"]
     for cname, py in fields.items():

@@ -251,6 +251,22 @@ def test_nonfinite_input_is_reported(crust):
     assert ei.value.status == ebe.ERR_NONFINITE
 
 
+@pytest.mark.parametrize("precond", [ebe.PREC_MG2, ebe.PREC_MG3])
+def test_crust_mixed_with_fp16_coarse_operators(crust, precond):
+    """Low-precision preconditioner experiment: the linear level's K1 and the
+    level-2 A2 stored in FP16 (FP32 arithmetic).  The FP64 outer loop still
+    reaches the tolerance and the direct solution; the iteration counts of
+    both settings are printed for comparison."""
+    m, gm, f, K, ud = crust
+    u0, st0 = gm.solve(dev(f), precond=precond, mode=ebe.MODE_MIXED, tol=1e-8)
+    u, st = gm.solve(dev(f), precond=precond, mode=ebe.MODE_MIXED, tol=1e-8, coarse_half=1)
+    print(f"[fp16 coarse precond={precond}] FP32 coarse {st0['outer_iters']} {st0['inner_iters']}, "
+          f"FP16 coarse {st['outer_iters']} {st['inner_iters']}", flush=True)
+    assert st["status"] == ebe.OK and st["max_rel_res"] <= 1e-8
+    assert rel_err(u.cpu().numpy(), ud) <= 1e-6
+    assert st["outer_iters"] <= 2 * st0["outer_iters"]
+
+
 def test_batch_of_uneven_meshes(gpu_lib):
     ms, gms, fs, refs = [], [], [], []
     for k, (g, n) in enumerate([((4, 4, 2), 3), ((6, 6, 3), 1), ((5, 5, 3), 16)]):
@@ -291,6 +307,38 @@ def test_batch_with_more_meshes_than_lanes_and_an_error(gpu_lib):
         ebe.batch_solve(gms, bad, opts=opts)
     assert ei.value.status == ebe.ERR_NONFINITE
     assert "mesh 4" in str(ei.value)
+
+
+def test_batch_merges_small_meshes(gpu_lib):
+    """Meshes with 9-16 cases are solved as one merged block-diagonal system
+    (one launch per step over all their patches); a mesh with 2 cases alone.
+    Each result matches the oracle's direct solve, each member's reported
+    residual is its own (recomputed with its operator), and merging off
+    gives the same solutions."""
+    grids = [(3, 3, 2), (4, 3, 2), (4, 4, 2), (5, 4, 3), (3, 5, 2)]
+    nrhs = [12, 9, 16, 10, 2]
+    gms, fs, refs = [], [], []
+    for k, (g, n) in enumerate(zip(grids, nrhs)):
+        m = meshgen.crust_mesh(*g)
+        f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(5, 40 + k), nrhs=n)
+        f[:, :, -1] *= 1e3 ** (k % 3)  # cases of very different size share the merged system
+        K = fem.assemble(m.xyz, m.conn, m.young, m.poisson)
+        gms.append(ebe.Mesh.from_generated(m))
+        fs.append(dev(f))
+        refs.append(solve.sparse_solve(K, f, m.fixed))
+    info = {}
+    us, sts = ebe.batch_solve(gms, fs, tol=1e-9, info=info)
+    print(f"[merged batch] {info}, merged {[s['merged'] for s in sts]}", flush=True)
+    assert info["groups"] == 1 and info["group_of"] == [0, 0, 0, 0, -1]
+    assert [s["merged"] for s in sts] == [4, 4, 4, 4, 0]
+    for u, r, st in zip(us, refs, sts):
+        assert st["status"] == ebe.OK and st["max_rel_res"] <= 1e-9
+        assert rel_err(u.cpu().numpy(), r) <= 1e-6
+    info0 = {}
+    us0, sts0 = ebe.batch_solve(gms, fs, tol=1e-9, merge_elems=0, info=info0)
+    assert info0["groups"] == 0 and all(s["merged"] == 0 for s in sts0)
+    for u, u0 in zip(us, us0):
+        assert float((u - u0).norm() / u0.norm()) <= 1e-6
 
 
 # ---------------------------------------------------------------------------
