@@ -294,20 +294,21 @@ def batch_block(torch, ebe, meshgen, n_mesh, with_big, keep):
         fs.append(torch.from_numpy(f).cuda())
         log(f"# batch mesh {k}: grid {gr}, {m.n_elem} tets, {n} cases")
     opts = ebe.default_opts(tol=1e-8)
-    # streams only (no merged meshes), then the default (small meshes merged)
-    ebe.batch_solve(gms, fs, opts=opts, merge_elems=0)  # warm-up: block Jacobi, level 2, workspaces, forms
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ebe.batch_solve(gms, fs, opts=opts, merge_elems=0)
-    torch.cuda.synchronize()
-    tu = time.perf_counter() - t0
-    info = {}
-    ebe.batch_solve(gms, fs, opts=opts, info=info)  # warm-up of the merged meshes (built here)
+    # the default batch (concurrent solves on worker streams), then meshes of
+    # up to 150k elements merged into block-diagonal systems
+    ebe.batch_solve(gms, fs, opts=opts)  # warm-up: block Jacobi, level 2, workspaces, product forms
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     us, st_b = ebe.batch_solve(gms, fs, opts=opts)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    info = {}
+    ebe.batch_solve(gms, fs, opts=opts, merge_elems=150000, info=info)  # warm-up: the merged meshes are built
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st_m = ebe.batch_solve(gms, fs, opts=opts, merge_elems=150000)
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - t0
     t0 = time.perf_counter()
     st_s = [gm.solve(f, opts=opts)[1] for gm, f in zip(gms, fs)]
     torch.cuda.synchronize()
@@ -316,13 +317,14 @@ def batch_block(torch, ebe, meshgen, n_mesh, with_big, keep):
     out = {"workload": f"{n_mesh} crust meshes, log-uniform 5e4..2e6 tets, 1..16 cases each"
                        + (" + 128x128x64 (16 cases)" if with_big else "") + ", mixed MG3 to 1e-8",
            "n_mesh": len(grids), "elements_total": int(sum(g.n_elem for g in gms)), "cases_total": cases,
-           "batch_seconds": tb, "batch_streams_only_seconds": tu, "sequential_seconds": ts, "speedup": ts / tb,
-           "merged_groups": info.get("groups"),
+           "batch_seconds": tb, "sequential_seconds": ts, "speedup": ts / tb,
+           "merged_150k_seconds": tm, "merged_groups": info.get("groups"),
            "merged_meshes": int(sum(1 for g in info.get("group_of", []) if g >= 0)),
+           "merged_max_rel_res": max(s["max_rel_res"] for s in st_m),
            "solves_per_s_batch": cases / tb, "solves_per_s_sequential": cases / ts,
            "max_rel_res": max(s["max_rel_res"] for s in st_b),
            "all_converged": all(s["status"] == ebe.OK for s in st_b + st_s)}
-    log(f"# batch: {tb:.3f} s batched ({info.get('groups')} merged groups), {tu:.3f} s streams only, "
+    log(f"# batch: {tb:.3f} s batched, {tm:.3f} s with small meshes merged ({info.get('groups')} groups), "
         f"{ts:.3f} s one by one, {cases} cases")
     small = sorted(range(len(meshes)), key=lambda i: meshes[i].n_elem)[:keep]
     kept = [(i, meshes[i], fs[i].cpu().numpy(), us[i].cpu().numpy()) for i in small]

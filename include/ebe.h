@@ -364,8 +364,8 @@ ebe_status ebe_invert_lcurve(int32_t n_obs, int32_t n_basis, const double* G_dev
 
 /* Time every product form of y = K x (level 0: quadratic mesh, level 1:
  * linear mesh) for (dtype, nrhs) on this mesh, and for PIPELINED and
- * COLOURED both kernel variants (element geometry kept in LDS, or read by
- * each work-item), and keep the fastest for every later product with these
+ * COLOURED every kernel variant (ebe_set_product_variant), and keep the
+ * fastest for every later product with these
  * parameters (Section 4 tunes its kernels' parameters by hand; here the
  * search is measured on the mesh); ms_out[EBE_NUM_FORMS] (or NULL) receives
  * the times in milliseconds, indexed by form (the faster variant), -1 for a
@@ -396,8 +396,8 @@ ebe_status ebe_get_product_variant(const ebe_mesh* mesh, int32_t level, ebe_dtyp
 
 /* A batch runs the solves of several meshes, each with its own nrhs (1..16),
  * so that meshes too small to fill the GPU share it (Section 5 solves its
- * case sets one after another).  Meshes of at most merge_elems elements
- * (default 150,000; ebe_batch_set_merge) are grouped by case count (bands
+ * case sets one after another).  With ebe_batch_set_merge(batch, max_elems)
+ * (default 0: off), meshes of at most max_elems elements are grouped by case count (bands
  * 9-16, 5-8, 3-4, 1-2) into merged block-diagonal meshes of at most 1M
  * elements, built on the first solve from the members' device copies: one
  * solve of a merged mesh runs every product and vector pass as one launch
@@ -424,8 +424,11 @@ ebe_status ebe_batch_create(ebe_mesh* const* meshes, int32_t n_mesh, const int32
 ebe_status ebe_batch_solve(ebe_batch* batch, const double* const* f_dev, double* const* u_dev,
                            const ebe_pcg_opts* opts, ebe_pcg_stats* stats, void* stream);
 void ebe_batch_destroy(ebe_batch* batch);
-/* Merge meshes of at most max_elems elements (0: merge none); takes effect at
- * the next solve (the merged meshes are rebuilt). */
+/* Merge meshes of at most max_elems elements (0, the default: merge none);
+ * takes effect at the next solve (the merged meshes are rebuilt).  On the
+ * serving set of 32 meshes of 5e4..2e6 elements plus one of 6.3M, merged
+ * solves measured slower than concurrent separate ones (3.0 s at 150,000
+ * against 2.8 s), so merging is an option, not the default. */
 ebe_status ebe_batch_set_merge(ebe_batch* batch, int64_t max_elems);
 /* Number of merged groups and (group_of [n_mesh] or NULL) each mesh's group,
  * -1 for a mesh solved on its own; plans the groups if no solve has yet

@@ -44,7 +44,14 @@ using namespace ebe;
 
 namespace {
 constexpr int kLanes = 4;                          // concurrent jobs: one per hardware queue a process gets by default
-constexpr int64_t kDefaultMergeElems = 150000;     // meshes up to this size are merged
+// merging is off unless asked for (ebe_batch_set_merge): on the 32 + 1 mesh
+// serving set it measured slower than concurrent solves alone (3.03 s with
+// meshes <= 150k elements merged, 4.70 s with meshes <= 600k merged into
+// groups of <= 4M, against 2.77 s): every member iterates until the hardest
+// one converges, to a tolerance sqrt(members) tighter, on cases padded to
+// the group's largest count, and large merged jobs balance worse over the
+// worker streams
+constexpr int64_t kDefaultMergeElems = 0;
 constexpr int64_t kGroupElems = 1000000;           // elements of one merged mesh, at most
 
 struct Group {

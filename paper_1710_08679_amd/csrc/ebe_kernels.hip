@@ -486,12 +486,12 @@ hipError_t ebe_dispatch_p(int order, int form, const ebe_mesh* m, const void* x,
     return launch_asm_p<T, NR>(m, m->k1, m->fix.as<uint8_t>(), x, y, mask_in, bc, add, gate, s, gamma);
   if (form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED) {
     const bool colour = form == EBE_FORM_COLOURED;
-    const bool geo_lds = m->fvar[order == 2 ? 0 : 1][sizeof(T) == 8 ? 0 : 1][NR] == 0;
+    const int var = m->fvar[order == 2 ? 0 : 1][sizeof(T) == 8 ? 0 : 1][NR];
     if (order == 2)
-      return geo_lds ? launch_pipe<T, NR, 2, true>(m, x, y, mask_in, bc, add, gate, s, gamma, colour)
-                     : launch_pipe<T, NR, 2, false>(m, x, y, mask_in, bc, add, gate, s, gamma, colour);
-    return geo_lds ? launch_pipe<T, NR, 1, true>(m, x, y, mask_in, bc, add, gate, s, gamma, colour)
-                   : launch_pipe<T, NR, 1, false>(m, x, y, mask_in, bc, add, gate, s, gamma, colour);
+      return var != 1 ? launch_pipe<T, NR, 2, true, 1>(m, x, y, mask_in, bc, add, gate, s, gamma, colour)
+                      : launch_pipe<T, NR, 2, false, 1>(m, x, y, mask_in, bc, add, gate, s, gamma, colour);
+    return var != 1 ? launch_pipe<T, NR, 1, true, 1>(m, x, y, mask_in, bc, add, gate, s, gamma, colour)
+                    : launch_pipe<T, NR, 1, false, 1>(m, x, y, mask_in, bc, add, gate, s, gamma, colour);
   }
   // stream the staged partials past the caches when they cannot stay in the
   // last-level cache until the shared-node pass reads them back

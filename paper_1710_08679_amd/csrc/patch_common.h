@@ -252,9 +252,10 @@ __global__ __launch_bounds__(256) void k_reduce_shared(const int32_t* __restrict
 
 // Pipelined (and, on the quadratic mesh, coloured) forms of the EBE product
 // (pipe_kernel.h; instantiated in ebe_pipe_{f32,f64}_{lds,row}.hip).
-// colour: the coloured form (order 2 only); GEO: element geometry kept in LDS
-// (else read per work-item).  The caller checks form_usable() first.
-template <typename T, int NR, int ORDER, bool GEO>
+// colour: the coloured form (order 2 only); GEO: element geometry kept in
+// LDS (else read per work-item); NP: passes over the cases (instantiated: 1).
+// The caller checks form_usable() first.
+template <typename T, int NR, int ORDER, bool GEO, int NP>
 hipError_t launch_pipe(const ebe_mesh* m, const void* x, void* y, bool mask_in, bool bc, bool add, const int* gate,
                        hipStream_t s, double* gamma, bool colour);
 

@@ -41,38 +41,40 @@
 namespace ebe {
 namespace {
 
-#ifndef EBE_PIPE_THREADS_F32
-#define EBE_PIPE_THREADS_F32 0  // 0: as the other forms (threads_for)
-#endif
-#ifndef EBE_PIPE_WAVES_F32
-#define EBE_PIPE_WAVES_F32 0  // 0: as many wavefronts per SIMD as LDS allows, at most 4
-#endif
-#ifndef EBE_PIPE_WAVES_F64
-#define EBE_PIPE_WAVES_F64 0  // 0: as many wavefronts per SIMD as LDS allows, at most 2
-#endif
-
+// Cases per pass and work-items per workgroup.  NP = 1 (the instantiated
+// kernels): all n cases in one pass, the workgroup size of the other forms.
+// NP = 2: the cases in two passes of n / 2, so the FP64 accumulator holds
+// half the cases (32 KB per workgroup at n = 16: five workgroups per CU
+// instead of two), in workgroups of two element rounds per pass (48
+// elements x 8 cases on 192 work-items, no wavefront idle at the barrier
+// that ends the element phase); measured slower on the 64^3 cube (FP32
+// n = 16: 0.92 ms coloured, 1.16 ms pipelined, against 0.69 and 0.78 in one
+// pass), so not instantiated.
 template <typename T>
-constexpr int pipe_threads(int nr, int order) {
-  return (sizeof(T) == 4 && order == 2 && EBE_PIPE_THREADS_F32 > 0) ? EBE_PIPE_THREADS_F32
-                                                                    : threads_for(nr, order, int(sizeof(T)), false);
+constexpr int pipe_threads(int nr, int order, int np) {
+  if (np == 2) {
+    const int items = (order == 2 ? kPatchElems : kLinPatchElems) * (nr / 2);
+    return (items / 2 + 63) / 64 * 64;
+  }
+  return threads_for(nr, order, int(sizeof(T)), false);
 }
 
 template <typename T>
-constexpr int pipe_lds_bytes(int nr, int order, bool geo_lds) {
+constexpr int pipe_lds_bytes(int nr, int order, bool geo_lds, int np) {
   const int maxn = order == 2 ? kPatchNodes : kLinPatchCorners;
   const int pe = order == 2 ? kPatchElems : kLinPatchElems;
   const int nloc = order == 2 ? 10 : 4;
-  return maxn * 3 * nr * 8 + pe * 2 * nloc * 4 + (geo_lds ? pe * 14 * int(sizeof(T)) : 0) + 8 * maxn + 8 * nr + 16;
+  return maxn * 3 * (nr / np) * 8 + pe * 2 * nloc * 4 + (geo_lds ? pe * 14 * int(sizeof(T)) : 0) + 8 * maxn +
+         8 * nr + 16;
 }
 
 template <typename T>
-constexpr int pipe_waves_per_simd(int nr, int order, bool geo_lds) {
-  const int lds = (pipe_lds_bytes<T>(nr, order, geo_lds) + 511) / 512 * 512;
+constexpr int pipe_waves_per_simd(int nr, int order, bool geo_lds, int np) {
+  const int lds = (pipe_lds_bytes<T>(nr, order, geo_lds, np) + 511) / 512 * 512;
   const int wg = 163840 / lds;
-  const int w = (wg > 0 ? wg : 1) * (pipe_threads<T>(nr, order) / 64) / 4;
+  // waves per SIMD when the resident workgroups' wavefronts spread over the 4 SIMDs
+  const int w = ((wg > 0 ? wg : 1) * (pipe_threads<T>(nr, order, np) / 64) + 3) / 4;
   const int most = (sizeof(T) == 8 && order == 2) ? 2 : 4;
-  if (sizeof(T) == 4 && order == 2 && EBE_PIPE_WAVES_F32 > 0) return EBE_PIPE_WAVES_F32;
-  if (sizeof(T) == 8 && order == 2 && EBE_PIPE_WAVES_F64 > 0) return EBE_PIPE_WAVES_F64;
   return w > most ? most : (w < 1 ? 1 : w);
 }
 
@@ -80,35 +82,39 @@ constexpr int pipe_waves_per_simd(int nr, int order, bool geo_lds) {
 // from q = K p).  MASK: zero the fixed DOFs of x while reading it.  COLOUR:
 // the coloured form; plist then lists this launch's patches (one colour).
 // GEO: element geometry prefetched with the patch metadata and kept in LDS
-// (else each work-item of the element phase reads its element's row); which
-// is faster depends on the dtype and n, so the tuner measures both.
-template <typename T, int NR, int ORDER, bool MASK, bool GAMMA, bool COLOUR, bool GEO>
-__global__ __launch_bounds__(pipe_threads<T>(NR, ORDER))
-__attribute__((amdgpu_waves_per_eu(pipe_waves_per_simd<T>(NR, ORDER, GEO)))) void k_ebe_pipe(
+// (else each work-item of the element phase reads its element's row).  NP:
+// passes over the cases (above).  Which variant is faster depends on the
+// dtype and n, so the tuner measures them.
+template <typename T, int NR, int ORDER, bool MASK, bool GAMMA, bool COLOUR, bool GEO, int NP>
+__global__ __launch_bounds__(pipe_threads<T>(NR, ORDER, NP))
+__attribute__((amdgpu_waves_per_eu(pipe_waves_per_simd<T>(NR, ORDER, GEO, NP)))) void k_ebe_pipe(
     const T* __restrict__ gcache, const uint32_t* __restrict__ ptab, const int32_t* __restrict__ pelem,
     const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
     const int32_t* __restrict__ plist, const T* __restrict__ x, T* __restrict__ y, T* __restrict__ stage,
     int stream, int npatch, int bc, int add, double* __restrict__ gamma, double* __restrict__ gslot,
     unsigned* __restrict__ gcount, const int* __restrict__ gate) {
+  static_assert(NP == 1 || NR % NP == 0, "passes split the cases evenly");
   constexpr int NLOC = ORDER == 2 ? 10 : 4;
-  constexpr int W = 3 * NR;
+  constexpr int W = 3 * NR;                         // values of a node row in x, y and the staging buffer
+  constexpr int CW = NR / NP;                       // cases per pass
+  constexpr int WC = 3 * CW;                        // values of a node row of F (one pass)
   constexpr uint32_t RB = uint32_t(W * sizeof(T));  // bytes of a node row in x and y
-  constexpr uint32_t FB = uint32_t(W * 8);          // bytes of a node row in F
-  constexpr int TPB = pipe_threads<T>(NR, ORDER);
+  constexpr uint32_t FB = uint32_t(WC * 8);         // bytes of a node row in F
+  constexpr int TPB = pipe_threads<T>(NR, ORDER, NP);
   constexpr int MAXN = ORDER == 2 ? kPatchNodes : kLinPatchCorners;
   constexpr int PE = ORDER == 2 ? kPatchElems : kLinPatchElems;
   constexpr int KW = (MAXN + TPB - 1) / TPB;           // node entries per work-item
   constexpr int KE = (PE + TPB - 1) / TPB;             // elements per work-item (node tables)
-  constexpr int GW = 64 / NR > 1 ? 64 / NR : 1;        // elements per wave in the element phase
-  constexpr int KI = ((PE + GW - 1) / GW * GW * NR + TPB - 1) / TPB;  // element-phase items per work-item
-  constexpr int VEC = pass_vec(NR, NR, int(sizeof(T)));
-  constexpr int NV = W / VEC;
+  constexpr int GW = 64 / CW > 1 ? 64 / CW : 1;        // elements per wave in the element phase
+  constexpr int KI = ((PE + GW - 1) / GW * GW * CW + TPB - 1) / TPB;  // element-phase items per work-item
+  constexpr int VEC = pass_vec(NR, CW, int(sizeof(T)));
+  constexpr int NV = WC / VEC;                          // vectors of a node row in one pass
   constexpr int EPK = TPB / NV;
   constexpr int KIT = (MAXN + EPK - 1) / EPK;
   constexpr int GV = 16 / int(sizeof(T));  // values per 16-byte piece of a geometry row
   using V = VecT<T, VEC>;
   using GR = VecT<T, GV>;
-  __shared__ double F[MAXN * W];
+  __shared__ double F[MAXN * WC];
   __shared__ uint32_t etab[PE][2 * NLOC];  // per element: NLOC x-row byte offsets, then NLOC F-row byte offsets
   constexpr bool kGeoLds = GEO;
   __shared__ T geo[kGeoLds ? PE : 1][14];   // per element: G (12), lambda V s, mu V s
@@ -125,7 +131,11 @@ __attribute__((amdgpu_waves_per_eu(pipe_waves_per_simd<T>(NR, ORDER, GEO)))) voi
   const int start = xcd * q + (xcd < rr ? xcd : rr), stop = start + q + (xcd < rr ? 1 : 0);
   int p = start + int(blockIdx.x) / kXcds;
   if (GAMMA && tid < NR) gsum[tid] = 0.0;
-  const int sv = tid % NV, sent = tid < EPK * NV ? tid / NV : MAXN, sq = sv * VEC, sc = sq / NR, scc = sq - sc * NR;
+  // F starts at zero; every write-back zeroes what it read, so it stays zero between passes
+  for (int i = tid; i < MAXN * WC; i += TPB) F[i] = 0.0;
+  // this work-item's vector of a pass's node row (write-back): value sq of the
+  // row, component sc, cases scc .. scc + VEC - 1 of the pass
+  const int sv = tid % NV, sent = tid < EPK * NV ? tid / NV : MAXN, sq = sv * VEC, sc = sq / CW, scc = sq - sc * CW;
 
   // prefetched state of the next patch
   int e0 = 0, ne = 0, o0 = 0, nn = 0;
@@ -184,8 +194,13 @@ __attribute__((amdgpu_waves_per_eu(pipe_waves_per_simd<T>(NR, ORDER, GEO)))) voi
     fetch_meta(p);
     fetch_late();
   }
-  double en_acc = 0.0;
-  constexpr bool kLaneCase = (64 % NR) == 0 && (TPB % NR) == 0;
+  // (x, K x): a work-item keeps one case of each pass when the pass width
+  // divides 64, so it sums in registers (one sum per pass) and the lanes of a
+  // case are combined across the wavefront at the end
+  constexpr bool kLaneCase = (64 % CW) == 0 && (TPB % CW) == 0;
+  double en_acc[NP];
+#pragma unroll
+  for (int ps_ = 0; ps_ < NP; ++ps_) en_acc[ps_] = 0.0;
 #pragma unroll 1
   for (; p < stop; p += wx) {
     // A. commit this patch
@@ -220,129 +235,132 @@ __attribute__((amdgpu_waves_per_eu(pipe_waves_per_simd<T>(NR, ORDER, GEO)))) voi
         }
       }
     }
-#pragma unroll
-    for (int k = 0; k < KIT; ++k) {
-      const int ent = sent + k * EPK;
-      if (ent < nn) {
-#pragma unroll
-        for (int t = 0; t < VEC; ++t) F[ent * W + sq + t] = 0.0;
-      }
-    }
     const int ce0 = e0, cne = ne, cnn = nn;
     __syncthreads();
     // B. the next patch's metadata
     const int pn = p + wx;
     if (pn < stop) fetch_meta(pn);
-    // C. element phase of this patch
-    const int nj = spread_count<NR>(cne);
+    const int nj = spread_count<CW>(cne);
     const char* xb = reinterpret_cast<const char*>(x);
     char* fbase = reinterpret_cast<char*>(F);
 #pragma unroll
-    for (int k = 0; k < KI; ++k) {
-      const int w = tid + k * TPB;
-      const int j = w / NR, r = w - j * NR;
-      const int el = spread_element<NR>(j, cne);
-      if (w >= nj * NR || el >= cne) continue;
-      T Gm[4][3], clam, cmu;
-      if constexpr (kGeoLds) {
+    for (int pass = 0; pass < NP; ++pass) {
+      const int c0 = pass * CW;
+      // C. element phase of this pass
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
+      for (int k = 0; k < KI; ++k) {
+        const int w = tid + k * TPB;
+        const int j = w / CW, r = w - j * CW;
+        const int el = spread_element<CW>(j, cne);
+        if (w >= nj * CW || el >= cne) continue;
+        T Gm[4][3], clam, cmu;
+        if constexpr (kGeoLds) {
 #pragma unroll
-          for (int d = 0; d < 3; ++d) Gm[kk][d] = geo[el][3 * kk + d];
-        clam = geo[el][12];
-        cmu = geo[el][13];
-      } else {  // geometry row: G (12 values), volume, lambda, mu, as formed by the geometry kernel
-        T g[16];
-        const GR* row = reinterpret_cast<const GR*>(gcache + (int64_t(ce0) + el) * 16);
+          for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-        for (int v = 0; v < 16 / GV; ++v) {
-          const GR gv = row[v];
+            for (int d = 0; d < 3; ++d) Gm[kk][d] = geo[el][3 * kk + d];
+          clam = geo[el][12];
+          cmu = geo[el][13];
+        } else {  // geometry row: G (12 values), volume, lambda, mu, as formed by the geometry kernel
+          T g[16];
+          const GR* row = reinterpret_cast<const GR*>(gcache + (int64_t(ce0) + el) * 16);
 #pragma unroll
-          for (int t = 0; t < GV; ++t) g[v * GV + t] = gv.v[t];
+          for (int v = 0; v < 16 / GV; ++v) {
+            const GR gv = row[v];
+#pragma unroll
+            for (int t = 0; t < GV; ++t) g[v * GV + t] = gv.v[t];
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Gm[kk][d] = g[3 * kk + d];
+          const T sv0 = ORDER == 2 ? g[12] * T(0.05) : g[12];  // V / 20 (quadratic) or V (linear)
+          clam = g[13] * sv0;
+          cmu = g[14] * sv0;
         }
+        uint32_t xo[NLOC], fo[NLOC];
+        {
+          const uint32_t rx = uint32_t(c0 + r) * uint32_t(sizeof(T)), rf = uint32_t(r) * 8u;
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-          for (int d = 0; d < 3; ++d) Gm[kk][d] = g[3 * kk + d];
-        const T sv0 = ORDER == 2 ? g[12] * T(0.05) : g[12];  // V / 20 (quadratic) or V (linear)
-        clam = g[13] * sv0;
-        cmu = g[14] * sv0;
-      }
-      uint32_t xo[NLOC], fo[NLOC];
-      {
-        const uint32_t rx = uint32_t(r) * uint32_t(sizeof(T)), rf = uint32_t(r) * 8u;
-#pragma unroll
-        for (int a = 0; a < NLOC; ++a) {
-          xo[a] = etab[el][a] + rx;
-          fo[a] = etab[el][NLOC + a] + rf;
+          for (int a = 0; a < NLOC; ++a) {
+            xo[a] = etab[el][a] + rx;
+            fo[a] = etab[el][NLOC + a] + rf;
+          }
         }
-      }
-      T en = T(0);
-      auto u = [&](int a, int c) -> T {
-        const T v = *reinterpret_cast<const T*>(xb + size_t(xo[a]) + size_t(c) * NR * sizeof(T));
-        if constexpr (MASK) {
-          const int32_t wd = words[(fo[a] - uint32_t(r) * 8u) / FB];
-          return ((wd >> (kIdxBits + c)) & 1) ? T(0) : v;
-        } else {
-          return v;
-        }
-      };
-      auto emit = [&](int a, const T f[3]) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          atomicAdd(reinterpret_cast<double*>(fbase + fo[a]) + c * NR, double(f[c]));
-      };
-      if constexpr (ORDER == 2) p2_apply<T>(Gm, clam, cmu, u, emit, GAMMA, en);
-      else p1_apply<T>(Gm, clam, cmu, u, emit, GAMMA, en);
-      if constexpr (GAMMA) {
-        if constexpr (kLaneCase) en_acc += double(en);
-        else atomicAdd(&gsum[r], double(en));
-      }
-    }
-    __syncthreads();
-    // D. the next patch's element node words (in flight during E)
-    if (pn < stop) fetch_late();
-    // E. write back this patch
-#pragma unroll
-    for (int k = 0; k < KIT; ++k) {
-      const int ent = sent + k * EPK;
-      if (ent < cnn) {
-        const int32_t wd = words[ent];
-        const int col = sc * NR + scc;
-        V v;
-#pragma unroll
-        for (int t = 0; t < VEC; ++t) v.v[t] = T(F[ent * W + sq + t]);
-        const bool fixed = bc && ((wd >> (kIdxBits + sc)) & 1);
-        if (!COLOUR && wd < 0) {  // shared node: partial sum to its staging slot
-          T* sp = stage + size_t(slots[ent]) * W + col;
-          if (stream) store_stream<T, VEC>(sp, v);
-          else *reinterpret_cast<V*>(sp) = v;
-        } else {
-          V* yp = reinterpret_cast<V*>(y + size_t(wd & kIdxMask) * W + col);
-          if (add || (COLOUR && wd < 0)) {  // y += (the caller, or an earlier colour, wrote y)
-            if (!fixed) {  // (a fixed DOF keeps what y holds: the caller's value, or the first colour's zero)
-              V o = *yp;
-#pragma unroll
-              for (int t = 0; t < VEC; ++t) o.v[t] += v.v[t];
-              *yp = o;
-            }
+        T en = T(0);
+        auto u = [&](int a, int c) -> T {
+          const T v = *reinterpret_cast<const T*>(xb + size_t(xo[a]) + size_t(c) * NR * sizeof(T));
+          if constexpr (MASK) {
+            const int32_t wd = words[(fo[a] - uint32_t(r) * 8u) / FB];
+            return ((wd >> (kIdxBits + c)) & 1) ? T(0) : v;
           } else {
-            if (fixed) {
+            return v;
+          }
+        };
+        auto emit = [&](int a, const T f[3]) {
 #pragma unroll
-              for (int t = 0; t < VEC; ++t) v.v[t] = T(0);
+          for (int c = 0; c < 3; ++c)
+            atomicAdd(reinterpret_cast<double*>(fbase + fo[a]) + c * CW, double(f[c]));
+        };
+        if constexpr (ORDER == 2) p2_apply<T>(Gm, clam, cmu, u, emit, GAMMA, en);
+        else p1_apply<T>(Gm, clam, cmu, u, emit, GAMMA, en);
+        if constexpr (GAMMA) {
+          if constexpr (kLaneCase) en_acc[pass] += double(en);
+          else atomicAdd(&gsum[c0 + r], double(en));
+        }
+      }
+      __syncthreads();
+      // D. the next patch's element node words (in flight during the last write-back)
+      if (pass == NP - 1 && pn < stop) fetch_late();
+      // E. write back this pass, zeroing F behind it
+#pragma unroll
+      for (int k = 0; k < KIT; ++k) {
+        const int ent = sent + k * EPK;
+        if (ent < cnn) {
+          const int32_t wd = words[ent];
+          const int col = sc * NR + c0 + scc;
+          V v;
+#pragma unroll
+          for (int t = 0; t < VEC; ++t) {
+            v.v[t] = T(F[ent * WC + sq + t]);
+            F[ent * WC + sq + t] = 0.0;
+          }
+          const bool fixed = bc && ((wd >> (kIdxBits + sc)) & 1);
+          if (!COLOUR && wd < 0) {  // shared node: partial sum to its staging slot
+            T* sp = stage + size_t(slots[ent]) * W + col;
+            if (stream) store_stream<T, VEC>(sp, v);
+            else *reinterpret_cast<V*>(sp) = v;
+          } else {
+            V* yp = reinterpret_cast<V*>(y + size_t(wd & kIdxMask) * W + col);
+            if (add || (COLOUR && wd < 0)) {  // y += (the caller, or an earlier colour, wrote y)
+              if (!fixed) {  // (a fixed DOF keeps what y holds: the caller's value, or the first colour's zero)
+                V o = *yp;
+#pragma unroll
+                for (int t = 0; t < VEC; ++t) o.v[t] += v.v[t];
+                *yp = o;
+              }
+            } else {
+              if (fixed) {
+#pragma unroll
+                for (int t = 0; t < VEC; ++t) v.v[t] = T(0);
+              }
+              *yp = v;
             }
-            *yp = v;
           }
         }
       }
+      __syncthreads();  // F (next pass), or words, slots, node tables and geometry (next patch)
     }
-    __syncthreads();  // words, slots, node tables and F are refilled by the next patch
   }
   if constexpr (GAMMA) {
     if constexpr (kLaneCase) {
 #pragma unroll
-      for (int off = 32; off >= NR; off >>= 1) en_acc += __shfl_xor(en_acc, off, 64);
-      if ((tid & 63) < NR) atomicAdd(&gsum[tid & 63], en_acc);
+      for (int pass = 0; pass < NP; ++pass) {
+        double v = en_acc[pass];
+#pragma unroll
+        for (int off = 32; off >= CW; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((tid & 63) < CW) atomicAdd(&gsum[pass * CW + (tid & 63)], v);
+      }
     }
     __syncthreads();
     fold_gamma<NR, TPB>(gsum, gamma, gslot, gcount);
@@ -351,14 +369,14 @@ __attribute__((amdgpu_waves_per_eu(pipe_waves_per_simd<T>(NR, ORDER, GEO)))) voi
 
 // as many persistent workgroups as fit on the device at once (measured
 // occupancy x CUs), at most one per patch
-template <typename T, int NR, int ORDER, bool MASK, bool GAMMA, bool COLOUR, bool GEO>
+template <typename T, int NR, int ORDER, bool MASK, bool GAMMA, bool COLOUR, bool GEO, int NP>
 hipError_t launch_pipe_k(const ebe_mesh* m, const PatchLevel& L, const int32_t* plist, int64_t npatch, const void* x,
                          void* y, bool stream, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
-  constexpr int TPB = pipe_threads<T>(NR, ORDER);
+  constexpr int TPB = pipe_threads<T>(NR, ORDER, NP);
   static const int per_cu = [] {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ebe_pipe<T, NR, ORDER, MASK, GAMMA, COLOUR, GEO>, TPB, 0) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ebe_pipe<T, NR, ORDER, MASK, GAMMA, COLOUR, GEO, NP>, TPB,
+                                                     0) != hipSuccess ||
         n < 1)
       n = 1;
     return n;
@@ -368,7 +386,7 @@ hipError_t launch_pipe_k(const ebe_mesh* m, const PatchLevel& L, const int32_t* 
     cus = 256;
   const int64_t grid = std::min<int64_t>(npatch, int64_t(per_cu) * cus);
   if (grid < 1) return hipSuccess;
-  hipLaunchKernelGGL((k_ebe_pipe<T, NR, ORDER, MASK, GAMMA, COLOUR, GEO>), dim3(unsigned(grid)), dim3(TPB), 0, s,
+  hipLaunchKernelGGL((k_ebe_pipe<T, NR, ORDER, MASK, GAMMA, COLOUR, GEO, NP>), dim3(unsigned(grid)), dim3(TPB), 0, s,
                      m->geo[sizeof(T) == 8 ? 0 : 1].as<T>(), L.ptab.as<uint32_t>(), L.pelem.as<int32_t>(),
                      L.poff.as<int32_t>(), COLOUR ? L.cword.as<int32_t>() : L.pnode.as<int32_t>(),
                      L.pslot.as<int32_t>(), plist, static_cast<const T*>(x), static_cast<T*>(y),
@@ -377,24 +395,24 @@ hipError_t launch_pipe_k(const ebe_mesh* m, const PatchLevel& L, const int32_t* 
   return hipGetLastError();
 }
 
-template <typename T, int NR, int ORDER, bool COLOUR, bool GEO>
+template <typename T, int NR, int ORDER, bool COLOUR, bool GEO, int NP>
 hipError_t launch_pipe_c(const ebe_mesh* m, const PatchLevel& L, const int32_t* plist, int64_t npatch, const void* x,
                          void* y, bool stream, bool mask_in, bool bc, bool add, const int* gate, hipStream_t s,
                          double* gamma) {
   if (mask_in && gamma) return hipErrorInvalidValue;  // no caller needs both
   if (mask_in)
-    return launch_pipe_k<T, NR, ORDER, true, false, COLOUR, GEO>(m, L, plist, npatch, x, y, stream, bc, add, gate, s,
-                                                            nullptr);
+    return launch_pipe_k<T, NR, ORDER, true, false, COLOUR, GEO, NP>(m, L, plist, npatch, x, y, stream, bc, add,
+                                                                    gate, s, nullptr);
   if (gamma)
-    return launch_pipe_k<T, NR, ORDER, false, true, COLOUR, GEO>(m, L, plist, npatch, x, y, stream, bc, add, gate, s,
-                                                            gamma);
-  return launch_pipe_k<T, NR, ORDER, false, false, COLOUR, GEO>(m, L, plist, npatch, x, y, stream, bc, add, gate, s,
-                                                           nullptr);
+    return launch_pipe_k<T, NR, ORDER, false, true, COLOUR, GEO, NP>(m, L, plist, npatch, x, y, stream, bc, add,
+                                                                    gate, s, gamma);
+  return launch_pipe_k<T, NR, ORDER, false, false, COLOUR, GEO, NP>(m, L, plist, npatch, x, y, stream, bc, add, gate,
+                                                                   s, nullptr);
 }
 
 }  // namespace
 
-template <typename T, int NR, int ORDER, bool GEO>
+template <typename T, int NR, int ORDER, bool GEO, int NP>
 hipError_t launch_pipe(const ebe_mesh* m, const void* x, void* y, bool mask_in, bool bc, bool add, const int* gate,
                        hipStream_t s, double* gamma, bool colour) {
   const PatchLevel& L = m->pl[ORDER == 2 ? 0 : 1];
@@ -402,8 +420,8 @@ hipError_t launch_pipe(const ebe_mesh* m, const void* x, void* y, bool mask_in, 
     if (colour) {
       const int32_t* cp = L.cperm.as<int32_t>();
       for (size_t c = 0; c + 1 < L.coff.size(); ++c) {
-        const hipError_t e = launch_pipe_c<T, NR, ORDER, true, GEO>(m, L, cp + L.coff[c], L.coff[c + 1] - L.coff[c], x, y,
-                                                               false, mask_in, bc, add, gate, s, gamma);
+        const hipError_t e = launch_pipe_c<T, NR, ORDER, true, GEO, NP>(
+            m, L, cp + L.coff[c], L.coff[c + 1] - L.coff[c], x, y, false, mask_in, bc, add, gate, s, gamma);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
@@ -413,8 +431,8 @@ hipError_t launch_pipe(const ebe_mesh* m, const void* x, void* y, bool mask_in, 
   // stream the staged partials past the caches when they cannot stay in the
   // last-level cache until the shared-node pass reads them back
   const bool st = int64_t(L.nslots) * 3 * NR * int64_t(sizeof(T)) > kStreamStageBytes;
-  hipError_t e = launch_pipe_c<T, NR, ORDER, false, GEO>(m, L, nullptr, L.npatch, x, y, st, mask_in, bc, add, gate, s,
-                                                    gamma);
+  hipError_t e = launch_pipe_c<T, NR, ORDER, false, GEO, NP>(m, L, nullptr, L.npatch, x, y, st, mask_in, bc, add, gate,
+                                                             s, gamma);
   if (e != hipSuccess || L.nshared == 0) return e;
   const int64_t work = L.nshared * (3 * NR / reduce_width<T, NR>());
   hipLaunchKernelGGL((k_reduce_shared<T, NR>), dim3(unsigned((work + 255) / 256)), dim3(256), 0, s,

@@ -411,3 +411,4 @@ def test_coloured_form_on_unordered_patches(shuffled, dtype, variant):
         for _ in range(3):
             y = gm.matvec(x, apply_bc=True).cpu().numpy().astype(np.float64)
             assert_close_bound(y, fem.matvec_bc(K, xr, m.fixed), abs(K), xr, dtype, kap, "coloured P K P x")
+

@@ -327,7 +327,7 @@ def test_batch_merges_small_meshes(gpu_lib):
         fs.append(dev(f))
         refs.append(solve.sparse_solve(K, f, m.fixed))
     info = {}
-    us, sts = ebe.batch_solve(gms, fs, tol=1e-9, info=info)
+    us, sts = ebe.batch_solve(gms, fs, tol=1e-9, info=info, merge_elems=150000)
     print(f"[merged batch] {info}, merged {[s['merged'] for s in sts]}", flush=True)
     assert info["groups"] == 1 and info["group_of"] == [0, 0, 0, 0, -1]
     assert [s["merged"] for s in sts] == [4, 4, 4, 4, 0]
