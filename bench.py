@@ -57,7 +57,7 @@ def product_bytes(N, Nv, E, n, p):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("ebe_kernels.hip", "p2_element.h", "patches.cpp", "ebe_internal.h"):
+    for f in ("ebe_kernels.hip", "pipe_kernel.h", "patch_common.h", "p2_element.h", "patches.cpp", "ebe_internal.h"):
         with open(os.path.join(ROOT, "paper_1710_08679_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -536,7 +536,11 @@ def main():
             "frac": F / t / 1e12 / VALU_PEAK_TFLOPS["f32"], "traffic": traffic,
             "frac_of_plain_fma_peak": F / t / 1e12 / PLAIN_FMA_PEAK_TFLOPS,
             "ops_model": f"E*({OPS_PER_ELEM_RHS}n+{OPS_PER_ELEM}) VALU ops per product, FMA = 2 flops",
-            "kernel": f"EBE product FP32 n=16, {form} form (ebe_matvec)", "ms_per_launch": ms_events,
+            "kernel": f"EBE product FP32 n=16, {form} form (ebe_matvec: "
+                      + ("one k_ebe_pipe launch per patch colour" if form == "coloured" else
+                         "patch kernel + shared-node pass") + ")",
+            "launches_per_product": gm.patch_info(0)["colours"] if form == "coloured" else 2,
+            "ms_per_launch": ms_events,
             "algorithmic_flops": F, "algorithmic_bytes": B,
             "hbm": {"achieved": B / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": B / t / 1e9 / HBM_PEAK_GBS}}
     if traffic is not None:
