@@ -54,7 +54,8 @@ def morton3(i, j, k) -> np.ndarray:
 
 @dataclass
 class Mesh:
-    """A mesh of straight-sided 10-node tetrahedra plus per-element material."""
+    """A mesh of 10-node tetrahedra plus per-element material (straight-sided
+    as built; ``quadratic_map`` and ``curve_edges`` curve them)."""
     xyz: np.ndarray            # (N, 3) float64 node coordinates
     conn: np.ndarray           # (E, 10) int32 connectivity, VTK local order
     n_vertices: int            # nodes [0, n_vertices) are corners
@@ -289,6 +290,34 @@ def shuffled(mesh: Mesh, rng: np.random.Generator) -> Mesh:
     return Mesh(xyz=xyz, conn=newid[mesh.conn[pe]].astype(np.int32), n_vertices=nv, young=mesh.young[pe].copy(),
                 poisson=mesh.poisson[pe].copy(), fixed=fixed, grid=mesh.grid, lengths=mesh.lengths,
                 refined=refined)
+
+
+def _with_xyz(mesh: Mesh, xyz: np.ndarray) -> Mesh:
+    return Mesh(xyz=xyz, conn=mesh.conn.copy(), n_vertices=mesh.n_vertices, young=mesh.young.copy(),
+                poisson=mesh.poisson.copy(), fixed=mesh.fixed.copy(), grid=mesh.grid, lengths=mesh.lengths,
+                refined=None if mesh.refined is None else mesh.refined.copy())
+
+
+def quadratic_map(mesh: Mesh, c: float) -> Mesh:
+    """The mesh with every node (corners and edge nodes) moved by the global
+    map x -> (x + c x^2, y, z).  Edge nodes leave their edge midpoints, so
+    the elements become curved; a quadratic element reproduces the mapped
+    geometry exactly (its interpolation of a quadratic map is the map)."""
+    xyz = mesh.xyz.copy()
+    xyz[:, 0] = xyz[:, 0] + c * xyz[:, 0] ** 2
+    return _with_xyz(mesh, xyz)
+
+
+def curve_edges(mesh: Mesh, rng: np.random.Generator, amp: float = 0.05) -> Mesh:
+    """The mesh with each edge node moved off its edge midpoint by a seeded
+    random vector of length at most amp times that edge's length (corners
+    stay): curved tetrahedra of a general shape."""
+    ends = mesh.edge_endpoints()
+    ln = np.linalg.norm(mesh.xyz[ends[:, 1]] - mesh.xyz[ends[:, 0]], axis=1)
+    d = rng.uniform(-1.0, 1.0, size=(ends.shape[0], 3)) / np.sqrt(3.0)
+    xyz = mesh.xyz.copy()
+    xyz[mesh.n_vertices:] += amp * ln[:, None] * d
+    return _with_xyz(mesh, xyz)
 
 
 def hub_mesh(arms: int) -> Mesh:
