@@ -167,6 +167,25 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
                            const double* young, const double* poisson,
                            const uint8_t* dof_fixed, void* stream, ebe_mesh** out);
 
+/* Create a mesh of curved (isoparametric) 10-node tetrahedra: the same
+ * arguments and checks as ebe_mesh_create, except that edge nodes may lie
+ * anywhere; instead the Jacobian of each element's quadratic map
+ * x(L) = sum_a N_a(L) x_a must be positive (det J > 1e-14 * longest corner
+ * edge^3) at the four quadrature points and at the ten nodes, else
+ * EBE_ERR_INVERTED.  K_e = sum_q w_q B_q^T D B_q det J_q with the symmetric
+ * 4-point rule (Section 2, Eq. (2): the isoparametric element with its
+ * Jacobian evaluated per point; for straight elements this equals the
+ * straight-sided operator to rounding).  Products on the quadratic level use
+ * the gather form of the patch kernel with the element geometry formed at
+ * every product from the ten node coordinates; the linear level (corners)
+ * and level 2 are as for straight meshes.  Not supported on such a mesh
+ * (EBE_ERR_ARG): ebe_adjoint_grad, ebe_fault_create; batches solve it on its
+ * own (never merged). */
+ebe_status ebe_mesh_create_curved(const double* xyz, int64_t n_nodes, int64_t n_vertices,
+                                  const int32_t* conn10, int64_t n_elem,
+                                  const double* young, const double* poisson,
+                                  const uint8_t* dof_fixed, void* stream, ebe_mesh** out);
+
 /* Replace the per-element moduli from device arrays [n_elem] (asynchronous
  * apart from a range check that synchronises the stream). */
 ebe_status ebe_mesh_set_material(ebe_mesh* mesh, const double* young_dev,

@@ -312,6 +312,10 @@ ebe_status ebe_block_jacobi(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nr
 ebe_status ebe_adjoint_grad(ebe_mesh* m, ebe_dtype dt, int32_t nrhs, const void* u, const void* lam, void* g,
                             void* stream) {
   ebe_status st = check_common("ebe_adjoint_grad", m, dt, nrhs, u, g);
+  if (st == EBE_OK && m->curved) {
+    set_error("ebe_adjoint_grad: not supported on a mesh of curved elements");
+    return EBE_ERR_ARG;
+  }
   if (st != EBE_OK) return st;
   if (!lam || lam == g || !aligned16(lam)) {
     set_error("ebe_adjoint_grad: lam is NULL, aliases g or is not 16-byte aligned");

@@ -168,7 +168,9 @@ ebe_status plan(ebe_batch* b, hipStream_t s) {
   const int32_t n = int32_t(b->meshes.size());
   std::vector<int32_t> small[4];
   for (int32_t i = 0; i < n; ++i) {
-    if (b->merge_elems > 0 && b->meshes[i]->n_elem <= b->merge_elems) small[band_of(b->nrhs[i])].push_back(i);
+    // curved meshes are solved on their own (the merged mesh is built straight-sided)
+    if (b->merge_elems > 0 && b->meshes[i]->n_elem <= b->merge_elems && !b->meshes[i]->curved)
+      small[band_of(b->nrhs[i])].push_back(i);
     else b->solo.push_back(i);
   }
   for (auto& band : small) {

@@ -170,9 +170,12 @@ static_assert(kPatchNodes <= 128 && kLinPatchCorners <= 128, "patch-local ids mu
 struct ebe_mesh {
   int64_t n_nodes = 0, n_vertices = 0, n_elem = 0;
   bool has_bc = false;
+  // isoparametric (curved) quadratic elements: the quadratic level uses the
+  // curved element kernel (gather form), xv holds every node
+  bool curved = false;
   int device = 0;
   ebe::DBuf conn;       // int32 [E][10], packed (see kIdxBits)
-  ebe::DBuf xv;         // double4 [Nv] corner coordinates (w unused)
+  ebe::DBuf xv;         // double4 [Nv] corner coordinates (curved: [N], corners first; w unused)
   ebe::DBuf lame64;     // double2 [E] (lambda, mu)
   ebe::DBuf lame32;     // float2  [E]
   ebe::DBuf young;      // double [E]

@@ -39,13 +39,16 @@
 namespace ebe {
 namespace {
 
-// STAGE: the staged form (else the gather form).  MASK: zero the fixed
+// STAGE: the staged form (else the gather form).  CURVED: isoparametric
+// quadratic elements (quadratic level, gather form): phase 1 forms each
+// element's four quadrature-point gradients and weights from its ten node
+// coordinates (xv then holds every node), phase 2 applies p2c_apply.  MASK: zero the fixed
 // DOFs of x while reading it (y = P K P x); callers whose x is already zero
 // there (the solver) skip it, and the kernel then has no masking code.  bc: zero the fixed DOFs of y.  add: y += K x
 // instead of y = K x.  gamma (optional): gamma[r] += (x_r, K x_r) formed
 // element by element as sum_e x_eᵀ K_e x_e, which is what CG needs from
 // q = K p without a separate inner-product pass.
-template <typename T, int NR, int ORDER, bool STAGE, bool MASK>
+template <typename T, int NR, int ORDER, bool STAGE, bool MASK, bool CURVED>
 __global__ __launch_bounds__(threads_for(NR, ORDER, int(sizeof(T)), STAGE))
 __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) void k_ebe_patch(
     const int32_t* __restrict__ conn, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
@@ -72,7 +75,10 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
   using V = VecT<T, VEC>;
   __shared__ double F[MAXN * WC];
   __shared__ __align__(16) T X[STAGE ? MAXN * WC : 1];
-  __shared__ T geo[PE][14];
+  static_assert(!CURVED || (ORDER == 2 && !STAGE), "curved elements: quadratic level, gather form");
+  // element data: straight, G (12), lambda V s, mu V s; curved, per
+  // quadrature point q at 12 q: grad L_1..L_3 (9), lambda det J / 24, mu det J / 24
+  __shared__ __align__(16) T geo[PE][CURVED ? 48 : 14];
   __shared__ int32_t words[MAXN];
   __shared__ int32_t slots[MAXN];
   __shared__ double gsum[NR];
@@ -86,7 +92,32 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
     slots[i] = pslot[o0 + i];
   }
   if (tid < NR) gsum[tid] = 0.0;
-  for (int el = tid; el < ne; el += TPB) {
+  if constexpr (CURVED) {
+    for (int w = tid; w < 4 * ne; w += TPB) {
+      const int el = w >> 2, q = w & 3;
+      const int64_t e = int64_t(e0) + el;
+      const double4 x0 = xv[conn[e * 10] & kIdxMask];
+      double d[10][3];
+#pragma unroll
+      for (int a = 0; a < 10; ++a) {
+        const double4 xa = xv[conn[e * 10 + a] & kIdxMask];
+        d[a][0] = xa.x - x0.x;
+        d[a][1] = xa.y - x0.y;
+        d[a][2] = xa.z - x0.z;
+      }
+      double G[3][3];
+      const double wdet = curved_point(d, q, G) * (1.0 / 24.0);
+      T* g = &geo[el][12 * q];
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) g[3 * j + dd] = T(G[j][dd]);
+      const auto lm = lame[e];
+      g[9] = T(double(lm.x) * wdet);
+      g[10] = T(double(lm.y) * wdet);
+    }
+  }
+  for (int el = tid; el < (CURVED ? 0 : ne); el += TPB) {
     const int64_t e = int64_t(e0) + el;
     if (gcache) {  // the mesh's geometry cache: one row per element, formed exactly as below
       const T* g = gcache + e * 16;
@@ -163,12 +194,6 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
         if constexpr (!STAGE) gw[a] = words[lid[a]];
         lid[a] = lid[a] * WC + r;
       }
-      T G[4][3];
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) G[k][d] = geo[el][3 * k + d];
-      const T cl = geo[el][12], cm = geo[el][13];
       T en = T(0);
       auto u = [&](int a, int c) -> T {
         if constexpr (STAGE) {
@@ -182,8 +207,19 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
 #pragma unroll
         for (int c = 0; c < 3; ++c) atomicAdd(F + lid[a] + c * CW, double(f[c]));
       };
-      if constexpr (ORDER == 2) p2_apply<T>(G, cl, cm, u, emit, gamma != nullptr, en);
-      else p1_apply<T>(G, cl, cm, u, emit, gamma != nullptr, en);
+      if constexpr (CURVED) {
+        const T* gr = geo[el];
+        p2c_apply<T>([&](int q, int i) { return gr[12 * q + i]; }, u, emit, gamma != nullptr, en);
+      } else {
+        T G[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) G[k][d] = geo[el][3 * k + d];
+        const T cl = geo[el][12], cm = geo[el][13];
+        if constexpr (ORDER == 2) p2_apply<T>(G, cl, cm, u, emit, gamma != nullptr, en);
+        else p1_apply<T>(G, cl, cm, u, emit, gamma != nullptr, en);
+      }
       if (gamma) {
         if constexpr (kLaneCase) en_acc += double(en);
         else atomicAdd(&gsum[c0 + r], double(en));
@@ -422,26 +458,27 @@ __global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
   }
 }
 
-template <typename T, int NR, int ORDER, bool STAGE, bool MASK>
+template <typename T, int NR, int ORDER, bool STAGE, bool MASK, bool CURVED = false>
 void launch_patch_m(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool stream, bool bc,
                     bool add, const int* gate, hipStream_t s, double* gamma) {
   using P = typename Pair<T>::type;
   const P* lame = (sizeof(T) == 8) ? reinterpret_cast<const P*>(m->lame64.as<void>())
                                    : reinterpret_cast<const P*>(m->lame32.as<void>());
-  hipLaunchKernelGGL((k_ebe_patch<T, NR, ORDER, STAGE, MASK>), dim3(unsigned(L.npatch)),
+  hipLaunchKernelGGL((k_ebe_patch<T, NR, ORDER, STAGE, MASK, CURVED>), dim3(unsigned(L.npatch)),
                      dim3(threads_for(NR, ORDER, int(sizeof(T)), STAGE)), 0, s, m->conn.as<int32_t>(),
                      ORDER == 2 ? m->lconn.as<uint8_t>() : m->lconn1.as<uint8_t>(), L.pelem.as<int32_t>(),
                      L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(), m->xv.as<double4>(), lame,
                      static_cast<const T*>(x), static_cast<T*>(y), stage, int(stream), int(bc), int(add), gamma,
                      m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64),
-                     gate, m->geo_ready[sizeof(T) == 8 ? 0 : 1] ? m->geo[sizeof(T) == 8 ? 0 : 1].as<T>() : nullptr);
+                     gate,
+                     !CURVED && m->geo_ready[sizeof(T) == 8 ? 0 : 1] ? m->geo[sizeof(T) == 8 ? 0 : 1].as<T>() : nullptr);
 }
 
-template <typename T, int NR, int ORDER, bool STAGE>
+template <typename T, int NR, int ORDER, bool STAGE, bool CURVED = false>
 void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool stream,
                   bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
-  if (mask_in) launch_patch_m<T, NR, ORDER, STAGE, true>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
-  else launch_patch_m<T, NR, ORDER, STAGE, false>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
+  if (mask_in) launch_patch_m<T, NR, ORDER, STAGE, true, CURVED>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
+  else launch_patch_m<T, NR, ORDER, STAGE, false, CURVED>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
 }
 // y = A x for an assembled operator whose row fix bits are `fix`
 template <typename T, int NR>
@@ -496,7 +533,9 @@ hipError_t ebe_dispatch_p(int order, int form, const ebe_mesh* m, const void* x,
   // stream the staged partials past the caches when they cannot stay in the
   // last-level cache until the shared-node pass reads them back
   const bool st = int64_t(L.nslots) * 3 * NR * int64_t(sizeof(T)) > kStreamStageBytes;
-  if (order == 2) {
+  if (order == 2 && m->curved) {  // gather form only (form_usable)
+    launch_patch<T, NR, 2, false, true>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
+  } else if (order == 2) {
     if (form == EBE_FORM_STAGED) launch_patch<T, NR, 2, true>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
     else launch_patch<T, NR, 2, false>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
   } else {
@@ -542,8 +581,13 @@ template <typename T, int NR>
 hipError_t launch_noalloc_p(const ebe_mesh* m, const void* x, void* y, bool bc, void* stage, hipStream_t s) {
   const PatchLevel& L = m->pl[0];
   T* st = static_cast<T*>(stage);
-  if (bc) launch_patch_m<T, NR, 2, false, true>(m, L, x, y, st, false, bc, false, nullptr, s, nullptr);
-  else launch_patch_m<T, NR, 2, false, false>(m, L, x, y, st, false, bc, false, nullptr, s, nullptr);
+  if (m->curved) {
+    if (bc) launch_patch_m<T, NR, 2, false, true, true>(m, L, x, y, st, false, bc, false, nullptr, s, nullptr);
+    else launch_patch_m<T, NR, 2, false, false, true>(m, L, x, y, st, false, bc, false, nullptr, s, nullptr);
+  } else {
+    if (bc) launch_patch_m<T, NR, 2, false, true>(m, L, x, y, st, false, bc, false, nullptr, s, nullptr);
+    else launch_patch_m<T, NR, 2, false, false>(m, L, x, y, st, false, bc, false, nullptr, s, nullptr);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || L.nshared == 0) return e;
   const int64_t work = L.nshared * (3 * NR / reduce_width<T, NR>());
@@ -617,6 +661,7 @@ bool form_available(int order, int form) {
 
 bool form_usable(const ebe_mesh* m, int order, int form, ebe_dtype dt, int nrhs) {
   if (!form_available(order, form)) return false;
+  if (order == 2 && m->curved) return form == EBE_FORM_GATHER;  // the curved element kernel
   if (form != EBE_FORM_PIPELINED && form != EBE_FORM_COLOURED) return true;
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   // node tables hold 32-bit byte offsets of node rows

@@ -29,6 +29,10 @@ ebe_status ebe_fault_create(ebe_mesh* m, const int8_t* sides, int64_t n_fault_no
     set_error("ebe_fault_create: null argument, no fault node or no basis function");
     return EBE_ERR_ARG;
   }
+  if (m->curved) {
+    set_error("ebe_fault_create: not supported on a mesh of curved elements");
+    return EBE_ERR_ARG;
+  }
   const int64_t N = m->n_nodes, E = m->n_elem;
   std::vector<int32_t> row(N, -1);
   for (int64_t i = 0; i < n_fault_nodes; ++i) {

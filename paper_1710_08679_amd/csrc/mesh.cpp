@@ -2,10 +2,13 @@
 // end-points, corner -> edge-node adjacency, packed connectivity) and upload.
 //
 // The handle holds exactly what an EBE product needs to rebuild every element
-// matrix on the fly (Section 2, EBE method): connectivity (Q_i), corner
-// coordinates and per-element material.  Edge-node coordinates are only used
-// here, to check that elements are straight-sided (then K_i depends only on
-// the four corners).
+// matrix on the fly (Section 2, EBE method): connectivity (Q_i), coordinates
+// and per-element material.  A mesh from ebe_mesh_create must be
+// straight-sided (checked here), so its K_i depends only on the four corners
+// and only corner coordinates are kept; one from ebe_mesh_create_curved keeps
+// every node's coordinates for the isoparametric element kernel, after
+// checking that each element's Jacobian is positive at its quadrature points
+// and nodes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +20,7 @@
 #include <vector>
 
 #include "ebe_internal.h"
+#include "p2_element.h"
 
 namespace ebe {
 
@@ -98,22 +102,21 @@ const char* ebe_build_info(void) {
   return "gfx950; HIP; FP32 packed ops disabled; unsafe FP atomics (coarse-grained memory)";
 }
 
-ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertices,
-                           const int32_t* conn10, int64_t n_elem, const double* young,
-                           const double* poisson, const uint8_t* dof_fixed, void* stream,
-                           ebe_mesh** out) {
+static ebe_status create_mesh(const char* fn, bool curved, const double* xyz, int64_t n_nodes,
+                              int64_t n_vertices, const int32_t* conn10, int64_t n_elem, const double* young,
+                              const double* poisson, const uint8_t* dof_fixed, void* stream, ebe_mesh** out) {
   if (!out) {
-    set_error("ebe_mesh_create: out is NULL");
+    set_error("%s: out is NULL", fn);
     return EBE_ERR_ARG;
   }
   *out = nullptr;
   if (!xyz || !conn10 || !young || !poisson) {
-    set_error("ebe_mesh_create: null input pointer");
+    set_error("%s: null input pointer", fn);
     return EBE_ERR_ARG;
   }
   if (n_nodes <= 0 || n_vertices <= 0 || n_elem <= 0 || n_vertices > n_nodes ||
       n_nodes >= (int64_t(1) << kIdxBits)) {
-    set_error("ebe_mesh_create: bad sizes n_nodes=%lld n_vertices=%lld n_elem=%lld",
+    set_error("%s: bad sizes n_nodes=%lld n_vertices=%lld n_elem=%lld", fn,
               (long long)n_nodes, (long long)n_vertices, (long long)n_elem);
     return EBE_ERR_ARG;
   }
@@ -122,12 +125,12 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
 
   for (int64_t i = 0; i < 3 * N; ++i)
     if (!std::isfinite(xyz[i])) {
-      set_error("ebe_mesh_create: non-finite coordinate at node %lld", (long long)(i / 3));
+      set_error("%s: non-finite coordinate at node %lld", fn, (long long)(i / 3));
       return EBE_ERR_NONFINITE;
     }
   for (int64_t e = 0; e < E; ++e)
     if (!material_ok(young[e], poisson[e])) {
-      set_error("ebe_mesh_create: element %lld has E=%g nu=%g", (long long)e, young[e], poisson[e]);
+      set_error("%s: element %lld has E=%g nu=%g", fn, (long long)e, young[e], poisson[e]);
       return EBE_ERR_MATERIAL;
     }
 
@@ -137,12 +140,12 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
     const int32_t* c = conn10 + 10 * e;
     for (int a = 0; a < 10; ++a) {
       if (c[a] < 0 || c[a] >= N) {
-        set_error("ebe_mesh_create: element %lld node %d index %d out of [0,%lld)", (long long)e, a,
+        set_error("%s: element %lld node %d index %d out of [0,%lld)", fn, (long long)e, a,
                   c[a], (long long)N);
         return EBE_ERR_INDEX;
       }
       if ((a < 4) != (c[a] < Nv)) {
-        set_error("ebe_mesh_create: element %lld local node %d (id %d) breaks vertex-first numbering",
+        set_error("%s: element %lld local node %d (id %d) breaks vertex-first numbering", fn,
                   (long long)e, a, c[a]);
         return EBE_ERR_NUMBERING;
       }
@@ -151,7 +154,7 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
   }
   for (int64_t i = 0; i < N; ++i)
     if (!seen[i]) {
-      set_error("ebe_mesh_create: node %lld is not used by any element", (long long)i);
+      set_error("%s: node %lld is not used by any element", fn, (long long)i);
       return EBE_ERR_INDEX;
     }
   seen.clear();
@@ -177,8 +180,33 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
       hmax = std::max(hmax, std::sqrt(l2));
     }
     if (!(det > 1e-14 * hmax * hmax * hmax)) {
-      set_error("ebe_mesh_create: element %lld has det=%g (inverted or degenerate)", (long long)e, det);
+      set_error("%s: element %lld has det=%g (inverted or degenerate)", fn, (long long)e, det);
       return EBE_ERR_INVERTED;
+    }
+    if (curved) {
+      // the Jacobian of the quadratic map must be positive at the four
+      // quadrature points and at the ten nodes
+      double dl[10][3];
+      for (int a = 0; a < 10; ++a)
+        for (int j = 0; j < 3; ++j) dl[a][j] = xyz[3 * c[a] + j] - x0[j];
+      for (int pt = 0; pt < 14; ++pt) {
+        double L[4] = {0.0, 0.0, 0.0, 0.0};
+        if (pt < 4) {
+          for (int k = 0; k < 4; ++k) L[k] = quad_l(pt, k);
+        } else if (pt < 8) {
+          L[pt - 4] = 1.0;
+        } else {
+          L[kEdge[pt - 8][0]] = L[kEdge[pt - 8][1]] = 0.5;
+        }
+        double cj[3][3];
+        curved_jacobian(dl, L, cj);
+        const double dj = det_columns(cj);
+        if (!(dj > 1e-14 * hmax * hmax * hmax)) {
+          set_error("%s: element %lld has det J = %g at %s %d (inverted or degenerate)", fn, (long long)e, dj,
+                    pt < 4 ? "quadrature point" : "node", pt < 4 ? pt : pt - 4);
+          return EBE_ERR_INVERTED;
+        }
+      }
     }
     for (int k = 0; k < 6; ++k) {
       int32_t p = c[kEdge[k][0]], q = c[kEdge[k][1]];
@@ -188,8 +216,8 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
         double mid = 0.5 * (xyz[3 * p + j] + xyz[3 * q + j]);
         dev = std::max(dev, std::fabs(xm[j] - mid));
       }
-      if (dev > 1e-10 * hmax) {
-        set_error("ebe_mesh_create: element %lld edge %d node is %g off the midpoint", (long long)e, k, dev);
+      if (!curved && dev > 1e-10 * hmax) {
+        set_error("%s: element %lld edge %d node is %g off the midpoint", fn, (long long)e, k, dev);
         return EBE_ERR_CURVED;
       }
       if (p > q) std::swap(p, q);
@@ -198,7 +226,7 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
         en[0] = p;
         en[1] = q;
       } else if (en[0] != p || en[1] != q) {
-        set_error("ebe_mesh_create: edge node %d has end points (%d,%d) and (%d,%d)", c[4 + k], en[0],
+        set_error("%s: edge node %d has end points (%d,%d) and (%d,%d)", fn, c[4 + k], en[0],
                   en[1], p, q);
         return EBE_ERR_INDEX;
       }
@@ -222,7 +250,7 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
 
   // corner -> incident elements (CSR, by element), for the row-wise K1 assembly
   if (4 * E >= (int64_t(1) << 31)) {
-    set_error("ebe_mesh_create: too many elements for 32-bit corner incidence lists");
+    set_error("%s: too many elements for 32-bit corner incidence lists", fn);
     return EBE_ERR_ARG;
   }
   std::vector<int32_t> veoff(Nv + 1, 0), vel(size_t(4 * E));
@@ -262,7 +290,7 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
     std::sort(bcol.begin() + b0, bcol.end());
     bcol.erase(std::unique(bcol.begin() + b0, bcol.end()), bcol.end());
     if (bcol.size() >= size_t(1) << 31) {
-      set_error("ebe_mesh_create: corner graph too large for 32-bit block indices");
+      set_error("%s: corner graph too large for 32-bit block indices", fn);
       return EBE_ERR_ARG;
     }
     bptr[v + 1] = int32_t(bcol.size());
@@ -277,8 +305,10 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
   std::vector<int32_t> packed(10 * E);
   for (int64_t k = 0; k < 10 * E; ++k) packed[k] = conn10[k] | (int32_t(fix[conn10[k]]) << kIdxBits);
 
-  std::vector<double> xv(4 * Nv);
-  for (int64_t v = 0; v < Nv; ++v) {
+  // corner coordinates (curved meshes: every node's, corners first)
+  const int64_t Nx = curved ? N : Nv;
+  std::vector<double> xv(4 * Nx);
+  for (int64_t v = 0; v < Nx; ++v) {
     xv[4 * v + 0] = xyz[3 * v + 0];
     xv[4 * v + 1] = xyz[3 * v + 1];
     xv[4 * v + 2] = xyz[3 * v + 2];
@@ -287,13 +317,14 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
 
   ebe_mesh* m = new (std::nothrow) ebe_mesh();
   if (!m) {
-    set_error("ebe_mesh_create: host allocation failed");
+    set_error("%s: host allocation failed", fn);
     return EBE_ERR_OOM;
   }
   m->n_nodes = N;
   m->n_vertices = Nv;
   m->n_elem = E;
   m->has_bc = any_bc;
+  m->curved = curved;
   (void)hipGetDevice(&m->device);
   ebe_status st = EBE_OK;
   if (st == EBE_OK) st = upload(m->conn, packed.data(), packed.size(), s);
@@ -317,7 +348,7 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
     if (he == hipSuccess) he = launch_fill_zero(m->gacc.as<void>(), kGammaBytes, s);
     if (he == hipSuccess) he = hipStreamSynchronize(s);
     if (he != hipSuccess) {
-      set_error("ebe_mesh_create: upload failed: %s", hipGetErrorString(he));
+      set_error("%s: upload failed: %s", fn, hipGetErrorString(he));
       st = EBE_ERR_HIP;
     }
   }
@@ -327,6 +358,20 @@ ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertice
   }
   *out = m;
   return EBE_OK;
+}
+
+ebe_status ebe_mesh_create(const double* xyz, int64_t n_nodes, int64_t n_vertices, const int32_t* conn10,
+                           int64_t n_elem, const double* young, const double* poisson, const uint8_t* dof_fixed,
+                           void* stream, ebe_mesh** out) {
+  return create_mesh("ebe_mesh_create", false, xyz, n_nodes, n_vertices, conn10, n_elem, young, poisson, dof_fixed,
+                     stream, out);
+}
+
+ebe_status ebe_mesh_create_curved(const double* xyz, int64_t n_nodes, int64_t n_vertices, const int32_t* conn10,
+                                  int64_t n_elem, const double* young, const double* poisson,
+                                  const uint8_t* dof_fixed, void* stream, ebe_mesh** out) {
+  return create_mesh("ebe_mesh_create_curved", true, xyz, n_nodes, n_vertices, conn10, n_elem, young, poisson,
+                     dof_fixed, stream, out);
 }
 
 ebe_status ebe_mesh_set_material(ebe_mesh* m, const double* young_dev, const double* poisson_dev,

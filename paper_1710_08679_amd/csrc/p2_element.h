@@ -1,6 +1,7 @@
-// Element operators of straight-sided tetrahedra, applied without forming
-// the element matrix (Section 2, EBE method: K_i is rebuilt from the corner
-// coordinates and the material at every product).
+// Element operators of tetrahedra, applied without forming the element
+// matrix (Section 2, EBE method: K_i is rebuilt from the node coordinates and
+// the material at every product): straight-sided elements in closed form
+// (p2_apply, p1_apply), curved isoparametric ones by quadrature (p2c_apply).
 //
 // Quadratic (10-node) element.  With barycentric coordinates L_k and their
 // constant gradients G_k, the displacement gradient of a quadratic field is
@@ -280,6 +281,179 @@ EBE_HD void p1_forces(const T G[4][3], T cl, T cm, const T u[4][3], T f[4][3]) {
         f[a][2] = fa[2];
       },
       false, unused);
+}
+
+// ---------------------------------------------------------------------------
+// Curved (isoparametric) 10-node tetrahedra: edge nodes anywhere, the element
+// map x(L) = sum_a N_a(L) x_a quadratic, its Jacobian varying inside the
+// element.  K_e = sum_q w_q B_q^T D B_q det J_q with the symmetric 4-point
+// rule (exact for straight elements, where this equals p2_apply to
+// rounding): point q has barycentric coordinate kQa at corner q and kQb at
+// the other three, weight 1/24 (a quarter of the reference volume 1/6);
+// kQa = (5 + 3 sqrt 5) / 20, kQb = (5 - sqrt 5) / 20.
+//
+// Derivatives are taken with the four barycentric coordinates as independent
+// variables: dN_i/dL_k = (4 L_i - 1) delta_ik for corner i, and for the edge
+// node between corners k and m dN_km/dL_k = 4 L_m.  With G_k = grad L_k
+// (G_0 = -(G_1 + G_2 + G_3)), grad N_a = sum_k (dN_a/dL_k) G_k, so a field
+// sum_a v_a N_a has the gradient sum_k V_k (x) G_k with
+//     V_k = sum_a v_a dN_a/dL_k = (4 L_k - 1) v_k + 4 sum_{m != k} L_m v_km.
+// Applied to the coordinates this gives the Jacobian's columns
+// dx/dL_j - dx/dL_0 = X_j - X_0 (j = 1..3), whose inverse's rows are
+// G_1..G_3; applied to a displacement it gives grad u.
+// ---------------------------------------------------------------------------
+constexpr double kQa = (5.0 + 3.0 * 2.23606797749978969641) / 20.0;
+constexpr double kQb = (5.0 - 2.23606797749978969641) / 20.0;
+
+// barycentric coordinate of corner k at quadrature point q
+EBE_HD constexpr double quad_l(int q, int k) { return q == k ? kQa : kQb; }
+
+// Columns c[j] = X_{j+1} - X_0 of the Jacobian at barycentric point L, from
+// the node coordinates relative to corner 0 (d[0] = 0).
+EBE_HD void curved_jacobian(const double d[10][3], const double L[4], double c[3][3]) {
+  double X[4][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) X[k][i] = (4.0 * L[k] - 1.0) * d[k][i];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int k = edge_end(e, 0), m = edge_end(e, 1);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      X[k][i] += 4.0 * L[m] * d[4 + e][i];
+      X[m][i] += 4.0 * L[k] * d[4 + e][i];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) c[j][i] = X[j + 1][i] - X[0][i];
+}
+
+// det of the Jacobian with columns c
+EBE_HD double det_columns(const double c[3][3]) {
+  return c[0][0] * (c[1][1] * c[2][2] - c[1][2] * c[2][1]) + c[0][1] * (c[1][2] * c[2][0] - c[1][0] * c[2][2]) +
+         c[0][2] * (c[1][0] * c[2][1] - c[1][1] * c[2][0]);
+}
+
+// Gradients G[j] = grad L_{j+1} (j = 0..2) at quadrature point q and det J
+// there, in FP64, from node coordinates relative to corner 0.
+EBE_HD double curved_point(const double d[10][3], int q, double G[3][3]) {
+  const double L[4] = {quad_l(q, 0), quad_l(q, 1), quad_l(q, 2), quad_l(q, 3)};
+  double c[3][3];
+  curved_jacobian(d, L, c);
+  // rows of the inverse: (c1 x c2, c2 x c0, c0 x c1) / det
+  const double det = det_columns(c);
+  const double inv = 1.0 / det;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double* a = c[(j + 1) % 3];
+    const double* b = c[(j + 2) % 3];
+    G[j][0] = (a[1] * b[2] - a[2] * b[1]) * inv;
+    G[j][1] = (a[2] * b[0] - a[0] * b[2]) * inv;
+    G[j][2] = (a[0] * b[1] - a[1] * b[0]) * inv;
+  }
+  return det;
+}
+
+// f = K_e u for a curved 10-node tetrahedron.  geo(q, i) returns the point
+// data of quadrature point q: i = 3 j + d (j, d < 3) component d of
+// grad L_{j+1}; i = 9: lambda det J_q / 24; i = 10: mu det J_q / 24 (read
+// where used, so they need not stay in registers).  u(a, c) is called once
+// per node and component, emit(a, f) once per node after all four points.
+// with_energy: energy = u_eᵀ K_e u_e = sum_q S_q : e_q (the scaled stress
+// against the engineering strain).
+template <typename T, class Geo, class U, class Emit>
+EBE_HD void p2c_apply(Geo&& geo, U&& u, Emit&& emit, bool with_energy, T& energy) {
+  T uc[4][3], ue[6][3], sm[4][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uc[k][c] = u(k, c);
+      sm[k][c] = T(0);
+    }
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int k = edge_end(e, 0), m = edge_end(e, 1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      ue[e][c] = u(4 + e, c);
+      sm[k][c] += ue[e][c];  // sum over the edge nodes at corner k
+      sm[m][c] += ue[e][c];
+    }
+  }
+  const T a4 = T(4.0 * kQa - 1.0), b4 = T(4.0 * kQb - 1.0), bb = T(4.0 * kQb), ab = T(4.0 * (kQa - kQb));
+  T S[4][6];
+  T en = T(0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    // V_k = (4 L_k - 1) u_k + 4 kQb sum_{m != k} u_km + 4 (kQa - kQb) u_kq
+    T V[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        V[k][c] = (k == q ? a4 : b4) * uc[k][c] + bb * sm[k][c];
+        if (k != q) V[k][c] += ab * ue[edge_node(k, q) - 4][c];
+      }
+    // grad u: H[c][d] = sum_j (V_j - V_0)[c] G_j[d]
+    T Gp[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int dd = 0; dd < 3; ++dd) Gp[j][dd] = geo(q, 3 * j + dd);
+    T H[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int dd = 0; dd < 3; ++dd) {
+        T h = (V[1][c] - V[0][c]) * Gp[0][dd];
+        h += (V[2][c] - V[0][c]) * Gp[1][dd];
+        h += (V[3][c] - V[0][c]) * Gp[2][dd];
+        H[c][dd] = h;
+      }
+    const T e6[6] = {H[0][0], H[1][1], H[2][2], H[1][2] + H[2][1], H[2][0] + H[0][2], H[0][1] + H[1][0]};
+    stress(e6, geo(q, 9), geo(q, 10), S[q]);
+    if (with_energy) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) en += S[q][c] * e6[c];
+    }
+  }
+  if (with_energy) energy = en;
+  // f_a = sum_q S_q grad N_a(q) = sum_q sum_k (dN_a/dL_k)(q) t_kq, t_kq = S_q G_k(q)
+  T f[10][3];
+#pragma unroll
+  for (int a = 0; a < 10; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) f[a][c] = T(0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T t[4][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T g[3] = {geo(q, 3 * j), geo(q, 3 * j + 1), geo(q, 3 * j + 2)};
+      sym_mv(S[q], g, t[j + 1]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t[0][c] = -((t[1][c] + t[2][c]) + t[3][c]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const T ck = T(4.0 * quad_l(q, k) - 1.0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) f[k][c] += ck * t[k][c];
+    }
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int k = edge_end(e, 0), m = edge_end(e, 1);
+      const T lm = T(4.0 * quad_l(q, m)), lk = T(4.0 * quad_l(q, k));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) f[4 + e][c] += lm * t[k][c] + lk * t[m][c];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 10; ++a) emit(a, f[a]);
 }
 
 }  // namespace ebe

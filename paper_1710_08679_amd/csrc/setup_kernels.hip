@@ -85,6 +85,64 @@ __global__ __launch_bounds__(kBlock) void k_diag_blocks(const int32_t* __restric
   }
 }
 
+// Quadratic-level blocks of curved elements: M_a = sum_q (det J_q / 24)
+// g_aq g_aqᵀ with g_aq = grad N_a at quadrature point q (p2_element.h: the
+// barycentric derivatives of N_a against the point's gradients grad L_k).
+__global__ __launch_bounds__(kBlock) void k_diag_blocks_curved(const int32_t* __restrict__ conn,
+                                                               const double4* __restrict__ xv,
+                                                               const double2* __restrict__ lame,
+                                                               double* __restrict__ blk, int64_t nelem) {
+  const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= nelem) return;
+  int32_t cw[10];
+  double d[10][3];
+#pragma unroll
+  for (int a = 0; a < 10; ++a) cw[a] = conn[e * 10 + a] & kIdxMask;
+  const double4 x0 = xv[cw[0]];
+#pragma unroll
+  for (int a = 0; a < 10; ++a) {
+    const double4 xa = xv[cw[a]];
+    d[a][0] = xa.x - x0.x;
+    d[a][1] = xa.y - x0.y;
+    d[a][2] = xa.z - x0.z;
+  }
+  double M[10][6];
+#pragma unroll
+  for (int a = 0; a < 10; ++a)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) M[a][c] = 0.0;
+#pragma unroll 1
+  for (int q = 0; q < 4; ++q) {
+    double G[3][3], Gk[4][3];
+    const double w = curved_point(d, q, G) * (1.0 / 24.0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Gk[1][c] = G[0][c];
+      Gk[2][c] = G[1][c];
+      Gk[3][c] = G[2][c];
+      Gk[0][c] = -((G[0][c] + G[1][c]) + G[2][c]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double ck = 4.0 * quad_l(q, k) - 1.0;
+      const double g[3] = {ck * Gk[k][0], ck * Gk[k][1], ck * Gk[k][2]};
+      outer_sym(g, g, w, M[k]);
+    }
+#pragma unroll
+    for (int ed = 0; ed < 6; ++ed) {
+      const int k = edge_end(ed, 0), m = edge_end(ed, 1);
+      const double lm = 4.0 * quad_l(q, m), lk = 4.0 * quad_l(q, k);
+      double g[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g[c] = lm * Gk[k][c] + lk * Gk[m][c];
+      outer_sym(g, g, w, M[4 + ed]);
+    }
+  }
+  const double2 lm = lame[e];
+#pragma unroll
+  for (int a = 0; a < 10; ++a) add_block(blk + size_t(cw[a]) * 6, M[a], lm.x, lm.y);
+}
+
 // fixed DOFs -> identity rows/columns, then invert (symmetric 3x3, FP64)
 __global__ __launch_bounds__(kBlock) void k_invert_blocks(const double* __restrict__ blk,
                                                           const uint8_t* __restrict__ fix,
@@ -423,7 +481,10 @@ hipError_t launch_diag_blocks(const ebe_mesh* m, int level, double* blk6, hipStr
   const int64_t n = level == 0 ? m->n_nodes : m->n_vertices;
   hipError_t e = launch_fill_zero(blk6, size_t(n) * 6 * sizeof(double), s);
   if (e != hipSuccess) return e;
-  if (level == 0)
+  if (level == 0 && m->curved)
+    hipLaunchKernelGGL(k_diag_blocks_curved, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s,
+                       m->conn.as<int32_t>(), m->xv.as<double4>(), m->lame64.as<double2>(), blk6, m->n_elem);
+  else if (level == 0)
     hipLaunchKernelGGL(k_diag_blocks<0>, dim3(grid_for(m->n_elem)), dim3(kBlock), 0, s,
                        m->conn.as<int32_t>(), m->xv.as<double4>(), m->lame64.as<double2>(), blk6, m->n_elem);
   else

@@ -35,6 +35,7 @@ EXPORTED = (
     "ebe_restrict_l2", "ebe_matvec_noalloc", "ebe_patch_info", "ebe_set_product_variant",
     "ebe_get_product_variant", "ebe_fault_create", "ebe_fault_destroy", "ebe_split_node_forces",
     "ebe_greens_functions", "ebe_invert_lcurve", "ebe_batch_set_merge", "ebe_batch_info",
+    "ebe_mesh_create_curved",
 )
 
 
@@ -82,6 +83,7 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "ebe_mesh_create": ([_vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)], _i32),
+        "ebe_mesh_create_curved": ([_vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)], _i32),
         "ebe_mesh_set_material": ([_vp, _vp, _vp, _vp], _i32),
         "ebe_mesh_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _i32),
         "ebe_mesh_destroy": ([_vp], None),
@@ -195,7 +197,9 @@ def default_opts(**kw) -> PcgOpts:
 class Mesh:
     """A device-resident mesh handle (``ebe_mesh``)."""
 
-    def __init__(self, xyz, conn, n_vertices, young, poisson, fixed=None, stream=None):
+    def __init__(self, xyz, conn, n_vertices, young, poisson, fixed=None, stream=None, curved=False):
+        """curved: create with ``ebe_mesh_create_curved`` (isoparametric elements,
+        edge nodes anywhere) instead of ``ebe_mesh_create`` (straight-sided)."""
         lib = load()
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         conn = np.ascontiguousarray(conn, dtype=np.int32)
@@ -210,17 +214,18 @@ class Mesh:
         if fx is not None and fx.shape != (self.n_nodes, 3):
             raise ValueError("fixed must be (N, 3)")
         h = _vp()
-        _check(lib.ebe_mesh_create(xyz.ctypes.data, self.n_nodes, self.n_vertices, conn.ctypes.data, self.n_elem,
-                                   young.ctypes.data, poisson.ctypes.data,
-                                   None if fx is None else fx.ctypes.data,
-                                   _vp(None) if stream is None else _stream(stream), ctypes.byref(h)))
+        create = lib.ebe_mesh_create_curved if curved else lib.ebe_mesh_create
+        _check(create(xyz.ctypes.data, self.n_nodes, self.n_vertices, conn.ctypes.data, self.n_elem,
+                      young.ctypes.data, poisson.ctypes.data, None if fx is None else fx.ctypes.data,
+                      _vp(None) if stream is None else _stream(stream), ctypes.byref(h)))
+        self.curved = bool(curved)
         self._h = h
 
     @classmethod
-    def from_generated(cls, m, stream=None) -> "Mesh":
-        """Upload a ``meshgen.Mesh``."""
+    def from_generated(cls, m, stream=None, curved=False) -> "Mesh":
+        """Upload a ``meshgen.Mesh`` (curved: as isoparametric elements)."""
         fixed = m.fixed if m.fixed.any() else None
-        return cls(m.xyz, m.conn, m.n_vertices, m.young, m.poisson, fixed, stream)
+        return cls(m.xyz, m.conn, m.n_vertices, m.young, m.poisson, fixed, stream, curved=curved)
 
     @property
     def handle(self):

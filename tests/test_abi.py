@@ -93,7 +93,9 @@ def create(m, **over):
     E = over.get("E", m.young)
     nu = over.get("nu", m.poisson)
     with pytest.raises(ebe.EbeError) as ei:
-        ebe.Mesh(xyz, conn, nv, E, nu)
+        ebe.Mesh(xyz, conn, nv, E, nu, curved=over.get("curved", False))
+    if "message" in over:
+        over["message"].append(str(ei.value))
     return ei.value.status
 
 
@@ -124,6 +126,28 @@ def test_validation_rejects_bad_meshes(lib):
     c = m.conn.copy()
     c[c == m.n_nodes - 1] = m.conn[0, 9]  # node n-1 unused (and an edge node reused inconsistently)
     assert create(m, conn=c) in (ebe.ERR_INDEX, ebe.ERR_CURVED)
+
+
+def test_curved_mesh_validation(lib):
+    """ebe_mesh_create_curved accepts edge nodes off their midpoints but checks
+    the Jacobian of each element's quadratic map at its quadrature points and
+    nodes; the other checks are those of ebe_mesh_create."""
+    m = meshgen.kuhn_mesh(2, 2, 2)
+    c0, c1 = m.conn[0, 0], m.conn[0, 1]
+    x = m.xyz.copy()
+    # the edge node of edge (0, 1) past the quarter point toward corner 0:
+    # the map folds over, det J < 0 at corner 0
+    x[m.conn[0, 4]] = m.xyz[c0] + 0.1 * (m.xyz[c1] - m.xyz[c0])
+    msg = []
+    assert create(m, xyz=x, curved=True, message=msg) == ebe.ERR_INVERTED
+    assert "det J" in msg[0] and "ebe_mesh_create_curved" in msg[0]
+    assert create(m, xyz=x) == ebe.ERR_CURVED
+    c = m.conn.copy()
+    c[0, 1], c[0, 2] = m.conn[0, 2], m.conn[0, 1]
+    assert create(m, conn=c, curved=True) == ebe.ERR_INVERTED
+    E = m.young.copy()
+    E[2] = 0.0
+    assert create(m, E=E, curved=True) == ebe.ERR_MATERIAL
 
 
 def test_null_arguments_are_rejected(lib):
