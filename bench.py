@@ -236,6 +236,54 @@ def greens_block(torch, ebe, meshgen, knots=(8, 4), step=4):
 FORM_NAMES = {0: "gather", 1: "staged", 2: "pipelined", 3: "assembled", 4: "coloured"}
 
 
+def curved_block(torch, ebe, meshgen, g, reps, warmup, straight):
+    """Products on curved (isoparametric) elements: the matvec cube with every
+    node moved by x -> (x + 0.25 x^2, y, z), so edge nodes leave their edge
+    midpoints, through ebe_mesh_create_curved (the curved gather kernel).
+    Per (dtype, n): median time against the straight mesh's, and an
+    oracle-free check at full size (K applied to a linear field vanishes at
+    interior nodes: a uniform stress is in equilibrium, exactly under this
+    map)."""
+    import numpy as np
+    m = meshgen.quadratic_map(meshgen.matvec_mesh(g), 0.25)
+    gm = ebe.Mesh.from_generated(m, curved=True)
+    N = m.n_nodes
+    out = {"workload": f"unit cube {g}^3 hexes x 6 tets mapped by x -> x + 0.25 x^2 (curved edges)",
+           "elements": m.n_elem, "runs": []}
+    for name, dt, n in (("f32", torch.float32, 16), ("f64", torch.float64, 16), ("f32", torch.float32, 4)):
+        gm.autotune(0, dt, n)
+        sets = 3
+        xs = [torch.randn((N, 3, n), dtype=torch.float64, device="cuda").to(dt) for _ in range(sets)]
+        ys = [torch.empty((N, 3, n), dtype=dt, device="cuda") for _ in range(sets)]
+        warm = stats_ms(time_each(lambda i: gm.matvec(xs[i % sets], out=ys[i % sets]), reps, warmup, torch))
+        ref = next((v["ms"] for v in straight if v["dtype"] == name and v["nrhs"] == n), None)
+        rec = {"dtype": name, "nrhs": n, "ms": warm["median"], "warm_ms": warm,
+               "gdof_rhs_per_s": 3 * N * n / (warm["median"] * 1e-3) / 1e9,
+               "straight_ms": ref, "vs_straight": None if ref is None else warm["median"] / ref}
+        out["runs"].append(rec)
+        log(f"# curved {name} n={n}: {warm['median']:.3f} ms ({rec['gdof_rhs_per_s']:.1f} GDOF*RHS/s)"
+            + ("" if ref is None else f", {rec['vs_straight']:.2f}x the straight mesh's {ref:.3f} ms"))
+        del xs, ys
+        torch.cuda.empty_cache()
+    A = torch.from_numpy(meshgen.rng_for(2, 6).standard_normal((3, 3, 4))).cuda()
+    xyz = torch.from_numpy(m.xyz).cuda()
+    y = gm.matvec(torch.einsum("nd,cdr->ncr", xyz, A).contiguous()).abs().amax(dim=(1, 2)).cpu().numpy()
+    # interior nodes whose elements all have one material (the layers' moduli
+    # differ, and a uniform strain is in equilibrium only inside a layer)
+    lo = np.full(N, np.inf)
+    hi = np.full(N, -np.inf)
+    ew = np.repeat(m.young, 10)
+    np.minimum.at(lo, m.conn.ravel(), ew)
+    np.maximum.at(hi, m.conn.ravel(), ew)
+    inner = np.all((m.refined > 0) & (m.refined < 2 * g), axis=1) & (lo == hi)
+    out["linear_field_check"] = {"interior_max_over_max": float(y[inner].max() / y.max()),
+                                 "interior_nodes": int(inner.sum()),
+                                 "what": "max |K u| at interior nodes inside one layer / max |K u|, u = A x linear "
+                                         "(FP64, 4 cases)"}
+    log(f"# curved linear-field check: {out['linear_field_check']}")
+    return out
+
+
 def adjoint_block(torch, ebe, meshgen, steps, warmup):
     """The adjoint workload: 64x64x32 hexes x 6 = 786,432 tets, lognormal moduli,
     4 cases: the element-gradient kernel g_e = -sum_c lam_c,e^T (K_e/E_e) u_c,e
@@ -428,6 +476,7 @@ def main():
     ap.add_argument("--no-solver", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-greens", action="store_true")
+    ap.add_argument("--no-curved", action="store_true")
     ap.add_argument("--solver-modes", default="mixed_mg3,mixed_mg3_fp16coarse,fp64_mg3,mixed_mg2,fp64_mg2,fp64_pcge")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=200000)
@@ -558,6 +607,9 @@ def main():
             "roofline": roof, "variants": variants}
     del flush_buf
     torch.cuda.empty_cache()
+    if not args.no_curved:
+        line["curved"] = curved_block(torch, ebe, meshgen, g, args.reps, args.warmup, variants)
+        torch.cuda.empty_cache()
     solved = None
     if not args.no_solver:
         line["solver"], solved = solver_block(torch, ebe, meshgen, args.solver_modes.split(","))

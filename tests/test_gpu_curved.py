@@ -186,3 +186,26 @@ def test_curved_mesh_refusals(curved):
     ms = gm.autotune(0, torch.float32, 4)
     assert ms[ebe.FORM_GATHER] > 0 and all(ms[f] < 0 for f in (ebe.FORM_STAGED, ebe.FORM_PIPELINED,
                                                                  ebe.FORM_COLOURED))
+
+
+def test_full_size_curved_matvec_sampled(gpu_lib):
+    """The 64^3 x 6 cube mapped by x -> x + 0.25 x^2 (bench.py's curved
+    workload), FP32 with 16 cases: every node of the first and last element
+    ranges and a random sample, against the oracle's element products around
+    them."""
+    from tests.helpers import restricted_matvec
+    m = meshgen.quadratic_map(meshgen.matvec_mesh(64), 0.25)
+    gm = ebe.Mesh.from_generated(m, curved=True)
+    rng = meshgen.rng_for(86, 0)
+    x = meshgen.random_vectors(rng, m.n_nodes, 16).astype(np.float32).astype(np.float64)
+    y = gm.matvec(to_dev(x, np.float32)).cpu().numpy().astype(np.float64)
+    nodes = np.unique(np.concatenate([m.conn[:96].ravel(), m.conn[-96:].ravel(),
+                                      rng.choice(m.n_nodes, 256, replace=False)]))
+    ref, absKx = restricted_matvec(m, x, nodes)
+    touched = np.nonzero(np.isin(m.conn, nodes).any(axis=1))[0]
+    sub = meshgen.Mesh(xyz=m.xyz, conn=m.conn[touched], n_vertices=m.n_vertices, young=m.young[touched],
+                       poisson=m.poisson[touched], fixed=m.fixed)
+    tol = C_TOL[np.float32] * kappa_points(sub) * unit_roundoff(np.float32) * absKx + 1e-300
+    worst = float(np.max(np.abs(y[nodes] - ref) / tol))
+    print(f"[curved 64^3 f32 n=16] {nodes.size} nodes, worst err / bound {worst:.3g}", flush=True)
+    assert worst <= 1.0
