@@ -91,10 +91,38 @@ def test_a2_product_matches_oracle(lv2, dtype, nrhs):
 
 
 def test_level2_blocks_match_oracle(lv2):
-    m, gm, agg, na, P2, A2, cfx, (absP, absA) = lv2
+    """Diagonal blocks of A2 elementwise within the rounding bound of their
+    sums: an entry of A2 = P2^T K1p P2 is a sum of k products, each factor
+    itself a rounded sum (K1 of element blocks, P2 = T - omega D1^-1 K1p T
+    with the inverted 3x3 blocks D1^-1), so |error| <= (k + 16 kappa_D) u
+    times the same sums of absolute terms, with the element blocks' absolute
+    values in place of |K1| (cancellation inside K1 is not free), k the
+    largest term count of a diagonal-block entry and kappa_D the largest
+    condition number of the blocks D1."""
+    m, gm, agg, na, P2, A2, cfx, _ = lv2
     got = gm.diag_blocks(2).cpu().numpy()
     ref = fem.diag_blocks(A2, na)
-    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    nv = m.n_vertices
+    Ke = np.abs(fem.element_stiffness_p1(m.xyz[m.conn[:, :4]], m.young, m.poisson))
+    dm = (3 * m.conn[:, :4, None].astype(np.int64) + np.arange(3)).reshape(m.n_elem, 12)
+    absK1 = sp.coo_matrix((Ke.ravel(), (np.repeat(dm, 12, axis=1).ravel(), np.tile(dm, (1, 12)).ravel())),
+                          shape=(3 * nv, 3 * nv)).tocsr()
+    absK1p = amg.projected(absK1, m.fixed)
+    K1 = fem.assemble(m.xyz, m.conn, m.young, m.poisson, order=1, n_nodes=nv)
+    Dblk = fem.diag_blocks(amg.projected(K1, m.fixed), nv)
+    Dinv = solve.block_jacobi_inverse(K1, m.fixed[:nv], nv)
+    free = ~m.fixed[:nv].astype(bool)
+    kap = max(np.linalg.cond(Dblk[v][np.ix_(free[v], free[v])]) for v in range(nv) if free[v].any())
+    T = amg.prolongation_p2(agg, na, m.fixed)
+    absP = (abs(T) + amg.OMEGA * (sp.block_diag(list(np.abs(Dinv))).tocsr() @ (absK1p @ abs(T)))).tocsr()
+    bound = fem.diag_blocks((absP.T @ absK1p @ absP).tocsr(), na)
+    pat = lambda a: (abs(a) > 0).astype(np.float64)  # noqa: E731
+    k = fem.diag_blocks((pat(absP).T @ pat(absK1p) @ pat(absP)).tocsr(), na).max()
+    u = np.finfo(np.float64).eps / 2
+    tol = (k + 16 * kap) * u * bound + 1e-300
+    worst = float(np.max(np.abs(got - ref) / tol))
+    print(f"[level-2 blocks] k={k:.0f} kappa_D={kap:.3g}, worst err / bound {worst:.3g}", flush=True)
+    assert worst <= 1.0
     Minv = solve.block_jacobi_inverse(A2, cfx, na)
     x = meshgen.rng_for(95, 0).standard_normal((na, 3, 4))
     x[cfx] = 0.0
