@@ -233,7 +233,7 @@ def greens_block(torch, ebe, meshgen, knots=(8, 4), step=4):
     return out
 
 
-FORM_NAMES = {0: "gather", 1: "staged", 2: "pipelined", 3: "assembled", 4: "coloured"}
+FORM_NAMES = {0: "gather", 1: "staged", 2: "pipelined", 3: "assembled", 4: "coloured", 5: "deterministic"}
 
 
 def curved_block(torch, ebe, meshgen, g, reps, warmup, straight):

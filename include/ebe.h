@@ -89,6 +89,13 @@ typedef int32_t ebe_dtype;
  * staging buffer and no second pass; the patches' sums reach a node in a
  * fixed (colour) order, while inside a patch the sums are LDS atomics, as
  * in the other forms, so results agree to rounding, not bit for bit.
+ * DETERMINISTIC (quadratic level only) is GATHER without atomics: each
+ * element-case stores its nodal forces in slots of its own in LDS, and each
+ * patch node adds the slots of the elements that touch it in a fixed order
+ * (in FP64), so y = K x is the same bit for bit on every run (the (x, K x)
+ * sums the solver takes from its products are not).  It needs the geometry
+ * cache (filled by the entry points) and takes the cases in passes of at
+ * most 8 (FP32) or 4 (FP64).
  * PIPELINED and COLOURED need a mesh below 2^25 nodes whose vectors at this
  * (dtype, nrhs) are below 4 GiB; elsewhere GATHER runs in their place.
  * AUTO: the mesh's tuned choice, else a fixed default. */
@@ -99,7 +106,8 @@ typedef enum {
   EBE_FORM_PIPELINED = 2,
   EBE_FORM_ASSEMBLED = 3,
   EBE_FORM_COLOURED = 4,
-  EBE_NUM_FORMS = 5
+  EBE_FORM_DETERMINISTIC = 5,
+  EBE_NUM_FORMS = 6
 } ebe_form;
 
 typedef struct ebe_mesh ebe_mesh;   /* opaque; owns device copies of the mesh and workspace */
@@ -395,8 +403,9 @@ ebe_status ebe_invert_lcurve(int32_t n_obs, int32_t n_basis, const double* G_dev
 ebe_status ebe_autotune(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, void* stream,
                         double* ms_out);
 
-/* Force (EBE_FORM_GATHER / _STAGED / _PIPELINED, _COLOURED for level 0,
- * _ASSEMBLED for level 1) or reset (EBE_FORM_AUTO) the form used
+/* Force (EBE_FORM_GATHER / _STAGED / _PIPELINED, _COLOURED and
+ * _DETERMINISTIC for level 0, _ASSEMBLED for level 1) or reset
+ * (EBE_FORM_AUTO) the form used
  * for (level, dtype, nrhs), and read the form that would be used. */
 ebe_status ebe_set_product_form(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, int32_t form);
 ebe_status ebe_get_product_form(const ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs,

@@ -34,7 +34,7 @@ SOURCES = [
     "mesh.cpp", "patches.cpp", "assembled.cpp", "api.cpp", "solver.cpp", "batch.cpp", "autotune.cpp",
     "ebe_kernels.hip", "ebe_pipe_f32_lds.hip", "ebe_pipe_f32_row.hip", "ebe_pipe_f64_lds.hip",
     "ebe_pipe_f64_row.hip", "setup_kernels.hip", "ebe_vec.hip", "ebe_adjoint.hip", "solver_kernels.hip",
-    "greens.cpp", "greens_kernels.hip", "batch_kernels.hip",
+    "greens.cpp", "greens_kernels.hip", "batch_kernels.hip", "ebe_det.hip",
 ]
 
 

@@ -159,6 +159,12 @@ struct PatchLevel {
   DBuf cperm;
   DBuf cword;
   std::vector<int64_t> coff;
+  // node-centric incidence lists of the quadratic patches (deterministic
+  // form): pinc [E][10] element slots (element - patch's first) * 10 + a,
+  // grouped by patch entry in element order; pistart [entries] the start of
+  // an entry's list relative to its patch's first slot
+  DBuf pinc;
+  DBuf pistart;
 };
 // element node words: 25 bits of node id, 7 bits of patch-local id
 constexpr int kPtabLocalShift = 25;
@@ -343,6 +349,12 @@ ebe_status build_level2(ebe_mesh* m, const std::vector<int32_t>& bptr, const std
 ebe_status ensure_level2(ebe_mesh* m, ebe_dtype dt, hipStream_t s);
 // grow the staging buffers for products with up to nrhs cases of the given element size
 ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes);
+
+// ---- deterministic product form (ebe_det.hip) -------------------------------
+// y = K x (quadratic level) with no atomics in the sums; needs the geometry
+// cache of dtype dt and the staging buffer (prepare_products)
+hipError_t launch_det(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in, bool bc,
+                      bool add, const int* gate, hipStream_t s, double* gamma);
 
 // ---- allocation-free product (ebe_kernels.hip) ------------------------------
 // Size of the fixed device array that stages shared-node partial sums for

@@ -656,12 +656,13 @@ ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes) {
 
 bool form_available(int order, int form) {
   return form >= 0 && form < EBE_NUM_FORMS && (form != EBE_FORM_ASSEMBLED || order == 1) &&
-         (form != EBE_FORM_COLOURED || order == 2);
+         ((form != EBE_FORM_COLOURED && form != EBE_FORM_DETERMINISTIC) || order == 2);
 }
 
 bool form_usable(const ebe_mesh* m, int order, int form, ebe_dtype dt, int nrhs) {
   if (!form_available(order, form)) return false;
   if (order == 2 && m->curved) return form == EBE_FORM_GATHER;  // the curved element kernel
+  if (form == EBE_FORM_DETERMINISTIC) return m->pl[0].pinc.bytes() > 0;
   if (form != EBE_FORM_PIPELINED && form != EBE_FORM_COLOURED) return true;
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   // node tables hold 32-bit byte offsets of node rows
@@ -685,9 +686,11 @@ hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt,
   const bool staged = form != EBE_FORM_COLOURED && form != EBE_FORM_ASSEMBLED;
   if ((staged && L.stage.bytes() < need) || L.npatch < 1 || nrhs < 1 || nrhs > EBE_MAX_RHS ||
       !form_usable(m, order, form, dt, nrhs) ||
-      ((form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED) && !m->geo_ready[k]) ||
+      ((form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED || form == EBE_FORM_DETERMINISTIC) &&
+       !m->geo_ready[k]) ||
       (form == EBE_FORM_ASSEMBLED && !m->k1.ready[k]))
     return hipErrorInvalidValue;  // staging, geometry or assembled values not prepared, or bad form: host bug
+  if (form == EBE_FORM_DETERMINISTIC) return launch_det(m, dt, nrhs, x, y, mask_in, bc, add, gate, s, gamma);
   return dt == EBE_F64 ? ebe_dispatch<double>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma)
                        : ebe_dispatch<float>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma);
 }

@@ -214,6 +214,30 @@ ebe_status build_patches(ebe_mesh* m, const int32_t* conn10, const uint8_t* fix,
     if ((st = up(m->pl[0].cperm, cperm, s)) != EBE_OK) return st;
     if ((st = up(m->pl[0].cword, cword, s)) != EBE_OK) return st;
   }
+  {
+    // incidence lists of the quadratic patches: for each patch entry, the
+    // element slots that touch it, in element order (deterministic form)
+    const std::vector<int32_t>& pe = pelem[0];
+    const LevelTables& t0 = t[0];
+    std::vector<uint16_t> pinc(size_t(E) * 10);
+    std::vector<int32_t> pistart(t0.pnode.size());
+    std::vector<int32_t> cnt;
+    for (size_t p = 0; p + 1 < pe.size(); ++p) {
+      const int32_t e0 = pe[p], ne = pe[p + 1] - e0, o0 = t0.poff[p], nn = t0.poff[p + 1] - o0;
+      cnt.assign(size_t(nn) + 1, 0);
+      for (int32_t el = 0; el < ne; ++el)
+        for (int a = 0; a < 10; ++a) cnt[lconn[(size_t(e0) + el) * 16 + a] + 1]++;
+      for (int32_t i = 0; i < nn; ++i) cnt[i + 1] += cnt[i];
+      for (int32_t i = 0; i < nn; ++i) pistart[size_t(o0) + i] = cnt[i];
+      for (int32_t el = 0; el < ne; ++el)
+        for (int a = 0; a < 10; ++a) {
+          const int lid = lconn[(size_t(e0) + el) * 16 + a];
+          pinc[size_t(e0) * 10 + cnt[lid]++] = uint16_t(el * 10 + a);
+        }
+    }
+    if ((st = up(m->pl[0].pinc, pinc, s)) != EBE_OK) return st;
+    if ((st = up(m->pl[0].pistart, pistart, s)) != EBE_OK) return st;
+  }
   for (int l = 0; l < 2; ++l) {
     PatchLevel& L = m->pl[l];
     if ((st = up(L.pelem, pelem[l], s)) != EBE_OK) return st;

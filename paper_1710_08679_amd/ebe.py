@@ -23,7 +23,8 @@ PREC_PCGE, PREC_MG2, PREC_MG3 = 0, 1, 2
 MODE_FP64, MODE_MIXED = 0, 1
 MAX_RHS = 16
 FORM_AUTO, FORM_GATHER, FORM_STAGED, FORM_PIPELINED, FORM_ASSEMBLED, FORM_COLOURED = -1, 0, 1, 2, 3, 4
-NUM_FORMS = 5
+FORM_DETERMINISTIC = 5
+NUM_FORMS = 6
 
 EXPORTED = (
     "ebe_mesh_create", "ebe_mesh_set_material", "ebe_mesh_info", "ebe_mesh_destroy", "ebe_matvec",

@@ -173,7 +173,7 @@ def test_curved_mesh_refusals(curved):
         gm.adjoint_grad(u, u)
     assert ei.value.status == ebe.ERR_ARG and "curved" in str(ei.value)
     try:  # a form the curved kernel does not come in is kept as a preference; the gather form runs
-        for form in (ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_COLOURED):
+        for form in (ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_COLOURED, ebe.FORM_DETERMINISTIC):
             gm.set_form(0, torch.float32, 4, form)
             assert gm.form(0, torch.float32, 4) == ebe.FORM_GATHER
     finally:
@@ -185,7 +185,7 @@ def test_curved_mesh_refusals(curved):
     assert ei.value.status == ebe.ERR_ARG and "curved" in str(ei.value)
     ms = gm.autotune(0, torch.float32, 4)
     assert ms[ebe.FORM_GATHER] > 0 and all(ms[f] < 0 for f in (ebe.FORM_STAGED, ebe.FORM_PIPELINED,
-                                                                 ebe.FORM_COLOURED))
+                                                                 ebe.FORM_COLOURED, ebe.FORM_DETERMINISTIC))
 
 
 def test_full_size_curved_matvec_sampled(gpu_lib):

@@ -31,7 +31,8 @@ def small(gpu_lib):
     return m, ebe.Mesh.from_generated(m), oracle_K(m), oracle_K(m, order=1), kappa_max(m)
 
 
-FORMS = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_COLOURED]  # quadratic level
+FORMS = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_COLOURED,
+         ebe.FORM_DETERMINISTIC]  # quadratic level
 FORMS1 = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_ASSEMBLED]  # linear level
 # the pipelined and coloured kernels in their second variant (geometry read per work-item)
 FORMS_V = FORMS + [(ebe.FORM_PIPELINED, 1), (ebe.FORM_COLOURED, 1)]
@@ -129,8 +130,11 @@ def test_autotune_keeps_the_faster_form(small):
         print(f"[autotune level {level} n={nrhs}] ms by form: {ts}", flush=True)
         have = [t for t in ts if t >= 0]
         assert len(ts) == ebe.NUM_FORMS and min(have) > 0
-        assert len(have) == 4
-        assert ts[ebe.FORM_ASSEMBLED if level == 0 else ebe.FORM_COLOURED] == -1
+        assert len(have) == (5 if level == 0 else 4)
+        if level == 0:
+            assert ts[ebe.FORM_ASSEMBLED] == -1
+        else:
+            assert ts[ebe.FORM_COLOURED] == -1 and ts[ebe.FORM_DETERMINISTIC] == -1
         assert gm.form(level, torch.float32, nrhs) == ts.index(min(have))
         gm.set_form(level, torch.float32, nrhs, ebe.FORM_AUTO)
     with pytest.raises(ebe.EbeError):
@@ -139,6 +143,8 @@ def test_autotune_keeps_the_faster_form(small):
         gm.set_form(0, torch.float32, 4, ebe.FORM_ASSEMBLED)
     with pytest.raises(ebe.EbeError):
         gm.set_form(1, torch.float32, 4, ebe.FORM_COLOURED)
+    with pytest.raises(ebe.EbeError):
+        gm.set_form(1, torch.float32, 4, ebe.FORM_DETERMINISTIC)
     with pytest.raises(ebe.EbeError):
         gm.autotune(2, torch.float32, 4)
 
@@ -278,6 +284,26 @@ def test_full_size_matvec_sampled_nodes(big, dtype, nrhs, form):
     tol = tol_factor(dtype, kap) * bnd
     err = np.abs(y[nodes] - ref)
     assert np.all(err <= tol), float(np.max(err / tol))
+
+
+@pytest.mark.parametrize("dtype,nrhs", [(np.float32, 16), (np.float64, 7), (np.float32, 1)])
+def test_deterministic_form_is_bitwise_reproducible(big, dtype, nrhs):
+    """The deterministic form on the 64^3 workload: repeated products, with
+    products of the other forms launched in between (other schedules, other
+    cache contents), give the same bits; and they match the oracle on
+    sampled nodes (the parity tests above cover it on every mesh)."""
+    m, gm, kap = big
+    x = to_dev(meshgen.random_vectors(meshgen.rng_for(2, 40 + nrhs), m.n_nodes, nrhs), dtype)
+    outs = []
+    for rep in range(4):
+        with forced_form(gm, 0, dtype, nrhs, ebe.FORM_DETERMINISTIC):
+            outs.append(gm.matvec(x, apply_bc=rep % 2 == 0))
+        with forced_form(gm, 0, dtype, nrhs, FORMS[rep % 4]):
+            gm.matvec(x)
+    assert torch.equal(outs[0], outs[2]) and torch.equal(outs[1], outs[3])
+    with forced_form(gm, 0, dtype, nrhs, ebe.FORM_COLOURED):
+        other = [gm.matvec(x) for _ in range(2)]
+    print(f"[deterministic n={nrhs}] coloured form repeats equal: {torch.equal(other[0], other[1])}", flush=True)
 
 
 def test_full_size_matvec_invariants(big):

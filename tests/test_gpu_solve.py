@@ -60,7 +60,7 @@ def crust(gpu_lib):
 
 
 @pytest.mark.parametrize("form", [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_ASSEMBLED,
-                                  ebe.FORM_COLOURED])
+                                  ebe.FORM_COLOURED, ebe.FORM_DETERMINISTIC])
 def test_crust_mixed_mg2_in_each_product_form(crust, form):
     """Every product of the solve (outer FP64, inner FP32 on both levels,
     each also forming (p, K p)) in one given form (the assembled form exists
@@ -70,7 +70,8 @@ def test_crust_mixed_mg2_in_each_product_form(crust, form):
     keys = [(0, torch.float64), (0, torch.float32), (1, torch.float32)]
     try:
         for level, dt in keys:
-            only = (form == ebe.FORM_ASSEMBLED and level == 0) or (form == ebe.FORM_COLOURED and level == 1)
+            only = (form == ebe.FORM_ASSEMBLED and level == 0) or (
+                form in (ebe.FORM_COLOURED, ebe.FORM_DETERMINISTIC) and level == 1)
             gm.set_form(level, dt, 16, ebe.FORM_GATHER if only else form)
         u, st = gm.solve(dev(f), precond=ebe.PREC_MG2, mode=ebe.MODE_MIXED, tol=1e-8)
     finally:
