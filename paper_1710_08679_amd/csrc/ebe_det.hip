@@ -6,13 +6,14 @@
 // Per patch and pass of cases:
 //   1. one work-item per (element, case) streams the element's nodal values
 //      from x through K_e (p2_apply) and stores each nodal force into its own
-//      slot of an element-local LDS buffer EB[element][local node][case][c]
+//      slot of an element-local LDS buffer EB[element][local node][c][case]
 //      (no two work-items write one slot);
-//   2. after a barrier, one work-item per (patch node, component, case) adds
-//      the slots of the node's incidence list (the (element, local node)
-//      pairs that touch it, in element order, built on the host) in FP64, in
-//      that fixed order, and writes the sum once: exclusive nodes straight
-//      into y, shared nodes into their staging slot;
+//   2. after a barrier, one work-item per (patch node, component, VEC
+//      consecutive cases) adds the slots of the node's incidence list (the
+//      (element, local node) pairs that touch it, in element order, built on
+//      the host) in FP64, in that fixed order, and writes the sums once, as
+//      one vector: exclusive nodes straight into y, shared nodes into their
+//      staging slot;
 // and the node-centric pass adds a shared node's staged partials in patch
 // order, as for the gather form.  The element buffer holds PE x 30 x CW
 // values of the dtype, so the cases go in passes of CW (at most 8 in FP32,
@@ -70,10 +71,13 @@ __attribute__((amdgpu_waves_per_eu(det_waves_per_simd<T>(NR)))) void k_ebe_det(
   constexpr int NPASS = (NR + CW - 1) / CW;
   constexpr int W = 3 * NR;
   constexpr int SL = 3 * CW;  // values of one (element, local node) slot row
+  constexpr int VEC = pass_vec(NR, CW, int(sizeof(T)));  // cases per node-sum work-item (one vector)
+  constexpr int NVR = CW / VEC;                           // vectors per component row
+  using V = VecT<T, VEC>;
   constexpr int TPB = det_threads(NR, int(sizeof(T)));
   constexpr int PE = kPatchElems;
   constexpr int MAXN = kPatchNodes;
-  __shared__ T EB[PE * 10 * SL];
+  __shared__ __align__(16) T EB[PE * 10 * SL];
   __shared__ T geo[PE][14];
   __shared__ int32_t words[MAXN];
   __shared__ int32_t slots[MAXN];
@@ -133,10 +137,10 @@ __attribute__((amdgpu_waves_per_eu(det_waves_per_simd<T>(NR)))) void k_ebe_det(
         const T v = x[size_t(uint32_t(gw[a]) & uint32_t(kIdxMask)) * W + c * NR + c0 + r];
         return (MASK && ((gw[a] >> (kIdxBits + c)) & 1)) ? T(0) : v;
       };
-      T* eb = EB + (el * 10) * SL + 3 * r;
+      T* eb = EB + (el * 10) * SL + r;
       auto emit = [&](int a, const T f[3]) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) eb[a * SL + c] = f[c];
+        for (int c = 0; c < 3; ++c) eb[a * SL + c * CW] = f[c];
       };
       p2_apply<T>(G, cl, cm, u, emit, gamma != nullptr, en);
       if (gamma) {
@@ -152,28 +156,48 @@ __attribute__((amdgpu_waves_per_eu(det_waves_per_simd<T>(NR)))) void k_ebe_det(
       }
     }
     __syncthreads();
-    // node sums in incidence order; items (entry, component, case), case fastest
-    for (int w = tid; w < nn * SL; w += TPB) {
-      const int ent = w / SL;
-      const int rem = w - ent * SL;
-      const int c = rem / CW, r = rem - c * CW;
-      if (r >= cw) continue;
-      double s = 0.0;
+    // node sums in incidence order; items (entry, component, vector of
+    // cases), cases fastest.  Vectors never straddle the pass's last case
+    // (VEC divides both n and the pass width).
+    for (int w = tid; w < nn * 3 * NVR; w += TPB) {
+      const int ent = w / (3 * NVR);
+      const int rem = w - ent * (3 * NVR);
+      const int c = rem / NVR, r0 = (rem - c * NVR) * VEC;
+      if (r0 >= cw) continue;
+      double s[VEC];
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) s[t] = 0.0;
       const int k1 = ioff[ent + 1];
-      for (int k = ioff[ent]; k < k1; ++k) s += double(EB[int(inc[k]) * SL + 3 * r + c]);
+      for (int k = ioff[ent]; k < k1; ++k) {
+        const V v = *reinterpret_cast<const V*>(EB + int(inc[k]) * SL + c * CW + r0);
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) s[t] += double(v.v[t]);
+      }
+      V out;
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) out.v[t] = T(s[t]);
       const int32_t wd = words[ent];
-      const int col = c * NR + c0 + r;
-      if (wd < 0) {  // shared node: partial sum to its staging slot
+      const int col = c * NR + c0 + r0;
+      if (wd < 0) {  // shared node: partial sums to its staging slot
         T* sp = stage + size_t(slots[ent]) * W + col;
-        if (stream) __builtin_nontemporal_store(T(s), sp);
-        else *sp = T(s);
+        if (stream) store_stream<T, VEC>(sp, out);
+        else *reinterpret_cast<V*>(sp) = out;
       } else {
-        T* yp = y + size_t(wd & kIdxMask) * W + col;
+        V* yp = reinterpret_cast<V*>(y + size_t(wd & kIdxMask) * W + col);
         const bool fixed = bc && ((wd >> (kIdxBits + c)) & 1);
         if (add) {
-          if (!fixed) *yp += T(s);
+          if (!fixed) {
+            V o = *yp;
+#pragma unroll
+            for (int t = 0; t < VEC; ++t) o.v[t] += out.v[t];
+            *yp = o;
+          }
         } else {
-          *yp = fixed ? T(0) : T(s);
+          if (fixed) {
+#pragma unroll
+            for (int t = 0; t < VEC; ++t) out.v[t] = T(0);
+          }
+          *yp = out;
         }
       }
     }
