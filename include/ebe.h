@@ -390,8 +390,8 @@ ebe_status ebe_invert_lcurve(int32_t n_obs, int32_t n_basis, const double* G_dev
 /* ---- product forms and the autotuner ------------------------------------ */
 
 /* Time every product form of y = K x (level 0: quadratic mesh, level 1:
- * linear mesh) for (dtype, nrhs) on this mesh, and for PIPELINED and
- * COLOURED every kernel variant (ebe_set_product_variant), and keep the
+ * linear mesh) for (dtype, nrhs) on this mesh, and for GATHER, STAGED,
+ * PIPELINED and COLOURED every kernel variant (ebe_set_product_variant), and keep the
  * fastest for every later product with these
  * parameters (Section 4 tunes its kernels' parameters by hand; here the
  * search is measured on the mesh); ms_out[EBE_NUM_FORMS] (or NULL) receives
@@ -411,10 +411,13 @@ ebe_status ebe_set_product_form(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, 
 ebe_status ebe_get_product_form(const ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs,
                                 int32_t* form);
 
-/* Kernel variant of the PIPELINED and COLOURED forms for (level, dtype,
- * nrhs): 0 = element geometry prefetched with the patch metadata and kept
+/* Kernel variant of a form for (level, dtype, nrhs).  PIPELINED and
+ * COLOURED: 0 = element geometry prefetched with the patch metadata and kept
  * in LDS (the default), 1 = read from the geometry cache by each work-item
- * of the element phase.  Same result up to rounding; ebe_autotune sets it,
+ * of the element phase.  GATHER and STAGED: 0 = element geometry read from
+ * the mesh's geometry cache (the default), 1 = formed at every product from
+ * the four corner coordinates (fewer bytes where few cases share an
+ * element).  Same result up to rounding; ebe_autotune sets it,
  * ebe_set_product_form resets it to 0; other forms ignore it. */
 ebe_status ebe_set_product_variant(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, int32_t variant);
 ebe_status ebe_get_product_variant(const ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs,

@@ -45,9 +45,15 @@ ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const vo
   for (int f = 0; f < EBE_NUM_FORMS; ++f) best[f] = DBL_MAX;
   for (int form = 0; form < EBE_NUM_FORMS && e == hipSuccess; ++form) {
     if (!form_usable(m, order, form, dt, nrhs)) continue;
-    // the pipelined and coloured kernels come in two variants (element
-    // geometry kept in LDS, or read per work-item): measure both
-    const int nvar = (form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED) ? 2 : 1;
+    // the patch kernels come in two variants: pipelined and coloured with
+    // the element geometry kept in LDS or read per work-item, gather and
+    // staged with the geometry read from the cache or formed from the corner
+    // coordinates: measure both
+    const bool curved = order == 2 && m->curved;
+    const int nvar = (form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED ||
+                      ((form == EBE_FORM_GATHER || form == EBE_FORM_STAGED) && !curved))
+                         ? 2
+                         : 1;
     for (int var = 0; var < nvar && e == hipSuccess; ++var) {
       m->fvar[lv][k][nrhs] = int8_t(var);
       e = launch_ebe_form(m, order, form, dt, nrhs, x, y, false, m->has_bc, false, nullptr, s);  // warm-up

@@ -458,9 +458,11 @@ __global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
   }
 }
 
+// cache: read the element geometry from the mesh's cache (when it is filled),
+// else form it from the corner coordinates in the kernel
 template <typename T, int NR, int ORDER, bool STAGE, bool MASK, bool CURVED = false>
 void launch_patch_m(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool stream, bool bc,
-                    bool add, const int* gate, hipStream_t s, double* gamma) {
+                    bool add, const int* gate, hipStream_t s, double* gamma, bool cache = true) {
   using P = typename Pair<T>::type;
   const P* lame = (sizeof(T) == 8) ? reinterpret_cast<const P*>(m->lame64.as<void>())
                                    : reinterpret_cast<const P*>(m->lame32.as<void>());
@@ -471,14 +473,17 @@ void launch_patch_m(const ebe_mesh* m, const PatchLevel& L, const void* x, void*
                      static_cast<const T*>(x), static_cast<T*>(y), stage, int(stream), int(bc), int(add), gamma,
                      m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64),
                      gate,
-                     !CURVED && m->geo_ready[sizeof(T) == 8 ? 0 : 1] ? m->geo[sizeof(T) == 8 ? 0 : 1].as<T>() : nullptr);
+                     !CURVED && cache && m->geo_ready[sizeof(T) == 8 ? 0 : 1] ? m->geo[sizeof(T) == 8 ? 0 : 1].as<T>()
+                                                                              : nullptr);
 }
 
 template <typename T, int NR, int ORDER, bool STAGE, bool CURVED = false>
 void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y, T* stage, bool stream,
-                  bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
-  if (mask_in) launch_patch_m<T, NR, ORDER, STAGE, true, CURVED>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
-  else launch_patch_m<T, NR, ORDER, STAGE, false, CURVED>(m, L, x, y, stage, stream, bc, add, gate, s, gamma);
+                  bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma, bool cache = true) {
+  if (mask_in)
+    launch_patch_m<T, NR, ORDER, STAGE, true, CURVED>(m, L, x, y, stage, stream, bc, add, gate, s, gamma, cache);
+  else
+    launch_patch_m<T, NR, ORDER, STAGE, false, CURVED>(m, L, x, y, stage, stream, bc, add, gate, s, gamma, cache);
 }
 // y = A x for an assembled operator whose row fix bits are `fix`
 template <typename T, int NR>
@@ -533,14 +538,21 @@ hipError_t ebe_dispatch_p(int order, int form, const ebe_mesh* m, const void* x,
   // stream the staged partials past the caches when they cannot stay in the
   // last-level cache until the shared-node pass reads them back
   const bool st = int64_t(L.nslots) * 3 * NR * int64_t(sizeof(T)) > kStreamStageBytes;
+  // variant 1: element geometry formed from the corner coordinates (less
+  // memory traffic than the cache rows where few cases share an element)
+  const bool cache = m->fvar[order == 2 ? 0 : 1][sizeof(T) == 8 ? 0 : 1][NR] != 1;
   if (order == 2 && m->curved) {  // gather form only (form_usable)
     launch_patch<T, NR, 2, false, true>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
   } else if (order == 2) {
-    if (form == EBE_FORM_STAGED) launch_patch<T, NR, 2, true>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
-    else launch_patch<T, NR, 2, false>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
+    if (form == EBE_FORM_STAGED)
+      launch_patch<T, NR, 2, true>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma, cache);
+    else
+      launch_patch<T, NR, 2, false>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma, cache);
   } else {
-    if (form == EBE_FORM_STAGED) launch_patch<T, NR, 1, true>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
-    else launch_patch<T, NR, 1, false>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma);
+    if (form == EBE_FORM_STAGED)
+      launch_patch<T, NR, 1, true>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma, cache);
+    else
+      launch_patch<T, NR, 1, false>(m, L, x, y, stage, st, mask_in, bc, add, gate, s, gamma, cache);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || L.nshared == 0) return e;

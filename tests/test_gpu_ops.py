@@ -34,9 +34,10 @@ def small(gpu_lib):
 FORMS = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_COLOURED,
          ebe.FORM_DETERMINISTIC]  # quadratic level
 FORMS1 = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_ASSEMBLED]  # linear level
-# the pipelined and coloured kernels in their second variant (geometry read per work-item)
-FORMS_V = FORMS + [(ebe.FORM_PIPELINED, 1), (ebe.FORM_COLOURED, 1)]
-FORMS1_V = FORMS1 + [(ebe.FORM_PIPELINED, 1)]
+# second variants: pipelined and coloured kernels with the geometry read per
+# work-item, gather and staged kernels with the geometry formed from the corners
+FORMS_V = FORMS + [(ebe.FORM_PIPELINED, 1), (ebe.FORM_COLOURED, 1), (ebe.FORM_GATHER, 1), (ebe.FORM_STAGED, 1)]
+FORMS1_V = FORMS1 + [(ebe.FORM_PIPELINED, 1), (ebe.FORM_GATHER, 1)]
 
 
 class forced_form:
@@ -259,7 +260,7 @@ def big(gpu_lib):
     return m, ebe.Mesh.from_generated(m), kappa_max(m)
 
 
-@pytest.mark.parametrize("form", FORMS + ["tuned"])
+@pytest.mark.parametrize("form", FORMS + [(ebe.FORM_GATHER, 1), "tuned"])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nrhs", [1, 16])
 def test_full_size_matvec_sampled_nodes(big, dtype, nrhs, form):
