@@ -93,7 +93,8 @@ typedef int32_t ebe_dtype;
  * element-case stores its nodal forces in slots of its own in LDS, and each
  * patch node adds the slots of the elements that touch it in a fixed order
  * (in FP64), so y = K x is the same bit for bit on every run (the (x, K x)
- * sums the solver takes from its products are not).  It needs the geometry
+ * sums the solver takes from its products are not); its variant 1 runs the
+ * patches colour by colour, as COLOURED does.  It needs the geometry
  * cache (filled by the entry points) and takes the cases in passes of at
  * most 8 (FP32) or 4 (FP64).
  * PIPELINED and COLOURED need a mesh below 2^25 nodes whose vectors at this
@@ -417,7 +418,10 @@ ebe_status ebe_get_product_form(const ebe_mesh* mesh, int32_t level, ebe_dtype d
  * of the element phase.  GATHER and STAGED: 0 = element geometry read from
  * the mesh's geometry cache (the default), 1 = formed at every product from
  * the four corner coordinates (fewer bytes where few cases share an
- * element).  Same result up to rounding; ebe_autotune sets it,
+ * element).  DETERMINISTIC: 0 = shared nodes' partial sums staged and
+ * added by a second pass, 1 = patches colour by colour with their sums added
+ * straight into y (the colour order is fixed, so still bit-reproducible).
+ * Same result up to rounding; ebe_autotune sets it,
  * ebe_set_product_form resets it to 0; other forms ignore it. */
 ebe_status ebe_set_product_variant(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, int32_t variant);
 ebe_status ebe_get_product_variant(const ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs,

@@ -48,10 +48,12 @@ ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const vo
     // the patch kernels come in two variants: pipelined and coloured with
     // the element geometry kept in LDS or read per work-item, gather and
     // staged with the geometry read from the cache or formed from the corner
-    // coordinates: measure both
+    // coordinates, deterministic with staging or colour by colour: measure
+    // both
     const bool curved = order == 2 && m->curved;
     const int nvar = (form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED ||
-                      ((form == EBE_FORM_GATHER || form == EBE_FORM_STAGED) && !curved))
+                      ((form == EBE_FORM_GATHER || form == EBE_FORM_STAGED) && !curved) ||
+                      (form == EBE_FORM_DETERMINISTIC && m->pl[0].coff.size() > 1))
                          ? 2
                          : 1;
     for (int var = 0; var < nvar && e == hipSuccess; ++var) {

@@ -15,7 +15,12 @@
 //      one vector: exclusive nodes straight into y, shared nodes into their
 //      staging slot;
 // and the node-centric pass adds a shared node's staged partials in patch
-// order, as for the gather form.  The element buffer holds PE x 30 x CW
+// order, as for the gather form.  Coloured variant: the patches run colour by
+// colour (no two patches of a colour share a node), one launch per colour,
+// and each patch writes its node sums straight into y, storing where it is
+// the first in colour order to touch the node and adding otherwise: no
+// staging and no second pass, and the additions reach a node in the fixed
+// colour order.  The element buffer holds PE x 30 x CW
 // values of the dtype, so the cases go in passes of CW (at most 8 in FP32,
 // 4 in FP64: 48 KB).  The (x, K x) sums of the solver's products are still
 // folded with device atomics (not part of y).
@@ -58,15 +63,17 @@ constexpr int det_waves_per_simd(int nr) {
 // MASK, bc, add, gamma as in the gather form.  gcache: the mesh's geometry
 // cache (required).  pistart: per patch entry, the start of its incidence
 // list relative to the patch's first element slot; pinc: element slots
-// (element - e0) * 10 + a grouped by patch entry.
-template <typename T, int NR, bool MASK>
+// (element - e0) * 10 + a grouped by patch entry.  COLOUR: the workgroups
+// run the patches plist[0..gridDim.x) of one colour, pnode holds the
+// coloured node words (bit 31: an earlier colour wrote the node).
+template <typename T, int NR, bool MASK, bool COLOUR>
 __global__ __launch_bounds__(det_threads(NR, int(sizeof(T))))
 __attribute__((amdgpu_waves_per_eu(det_waves_per_simd<T>(NR)))) void k_ebe_det(
     const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem, const int32_t* __restrict__ poff,
     const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot, const int32_t* __restrict__ pistart,
     const uint16_t* __restrict__ pinc, const T* __restrict__ gcache, const T* __restrict__ x, T* __restrict__ y,
     T* __restrict__ stage, int stream, int bc, int add, double* __restrict__ gamma, double* __restrict__ gslot,
-    unsigned* __restrict__ gcount, const int* __restrict__ gate) {
+    unsigned* __restrict__ gcount, const int* __restrict__ gate, const int32_t* __restrict__ plist) {
   constexpr int CW = det_cases(NR, int(sizeof(T)));
   constexpr int NPASS = (NR + CW - 1) / CW;
   constexpr int W = 3 * NR;
@@ -86,7 +93,7 @@ __attribute__((amdgpu_waves_per_eu(det_waves_per_simd<T>(NR)))) void k_ebe_det(
   __shared__ double gsum[NR];
   if (gate && *gate == 0) return;
   const int tid = threadIdx.x;
-  const int p = xcd_patch(blockIdx.x, gridDim.x);
+  const int p = COLOUR ? plist[xcd_patch(blockIdx.x, gridDim.x)] : xcd_patch(blockIdx.x, gridDim.x);
   const int e0 = pelem[p], ne = pelem[p + 1] - e0;
   const int o0 = poff[p], nn = poff[p + 1] - o0;
   for (int i = tid; i < nn; i += TPB) {
@@ -178,15 +185,15 @@ __attribute__((amdgpu_waves_per_eu(det_waves_per_simd<T>(NR)))) void k_ebe_det(
       for (int t = 0; t < VEC; ++t) out.v[t] = T(s[t]);
       const int32_t wd = words[ent];
       const int col = c * NR + c0 + r0;
-      if (wd < 0) {  // shared node: partial sums to its staging slot
+      if (!COLOUR && wd < 0) {  // shared node: partial sums to its staging slot
         T* sp = stage + size_t(slots[ent]) * W + col;
         if (stream) store_stream<T, VEC>(sp, out);
         else *reinterpret_cast<V*>(sp) = out;
       } else {
         V* yp = reinterpret_cast<V*>(y + size_t(wd & kIdxMask) * W + col);
         const bool fixed = bc && ((wd >> (kIdxBits + c)) & 1);
-        if (add) {
-          if (!fixed) {
+        if (add || (COLOUR && wd < 0)) {  // y += (the caller, or an earlier colour, wrote y)
+          if (!fixed) {  // (a fixed DOF keeps the caller's value or the first colour's zero)
             V o = *yp;
 #pragma unroll
             for (int t = 0; t < VEC; ++t) o.v[t] += out.v[t];
@@ -206,48 +213,63 @@ __attribute__((amdgpu_waves_per_eu(det_waves_per_simd<T>(NR)))) void k_ebe_det(
   if (gamma) fold_gamma<NR, TPB>(gsum, gamma, gslot, gcount);
 }
 
-template <typename T, int NR>
-hipError_t launch_det_p(const ebe_mesh* m, const void* x, void* y, bool mask_in, bool bc, bool add,
-                        const int* gate, hipStream_t s, double* gamma) {
+template <typename T, int NR, bool MASK, bool COLOUR>
+hipError_t launch_det_k(const ebe_mesh* m, const int32_t* plist, int64_t npatch, const void* x, void* y, bool st,
+                        bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[0];
   const int k = sizeof(T) == 8 ? 0 : 1;
-  const T* gc = m->geo[k].as<T>();
-  T* stage = L.stage.as<T>();
-  const bool st = int64_t(L.nslots) * 3 * NR * int64_t(sizeof(T)) > kStreamStageBytes;
   unsigned* gcount = reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64);
-  constexpr int TPB = det_threads(NR, int(sizeof(T)));
-  if (mask_in)
-    hipLaunchKernelGGL((k_ebe_det<T, NR, true>), dim3(unsigned(L.npatch)), dim3(TPB), 0, s, m->lconn.as<uint8_t>(),
-                       L.pelem.as<int32_t>(), L.poff.as<int32_t>(), L.pnode.as<int32_t>(), L.pslot.as<int32_t>(),
-                       L.pistart.as<int32_t>(), L.pinc.as<uint16_t>(), gc, static_cast<const T*>(x),
-                       static_cast<T*>(y), stage, int(st), int(bc), int(add), gamma, m->gacc.as<double>(), gcount,
-                       gate);
-  else
-    hipLaunchKernelGGL((k_ebe_det<T, NR, false>), dim3(unsigned(L.npatch)), dim3(TPB), 0, s,
-                       m->lconn.as<uint8_t>(), L.pelem.as<int32_t>(), L.poff.as<int32_t>(), L.pnode.as<int32_t>(),
-                       L.pslot.as<int32_t>(), L.pistart.as<int32_t>(), L.pinc.as<uint16_t>(), gc,
-                       static_cast<const T*>(x), static_cast<T*>(y), stage, int(st), int(bc), int(add), gamma,
-                       m->gacc.as<double>(), gcount, gate);
-  hipError_t e = hipGetLastError();
+  hipLaunchKernelGGL((k_ebe_det<T, NR, MASK, COLOUR>), dim3(unsigned(npatch)), dim3(det_threads(NR, int(sizeof(T)))),
+                     0, s, m->lconn.as<uint8_t>(), L.pelem.as<int32_t>(), L.poff.as<int32_t>(),
+                     COLOUR ? L.cword.as<int32_t>() : L.pnode.as<int32_t>(), L.pslot.as<int32_t>(),
+                     L.pistart.as<int32_t>(), L.pinc.as<uint16_t>(), m->geo[k].as<T>(), static_cast<const T*>(x),
+                     static_cast<T*>(y), L.stage.as<T>(), int(st), int(bc), int(add), gamma, m->gacc.as<double>(),
+                     gcount, gate, plist);
+  return hipGetLastError();
+}
+
+template <typename T, int NR, bool COLOUR>
+hipError_t launch_det_m(const ebe_mesh* m, const int32_t* plist, int64_t npatch, const void* x, void* y, bool st,
+                        bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
+  return mask_in ? launch_det_k<T, NR, true, COLOUR>(m, plist, npatch, x, y, st, bc, add, gate, s, gamma)
+                 : launch_det_k<T, NR, false, COLOUR>(m, plist, npatch, x, y, st, bc, add, gate, s, gamma);
+}
+
+template <typename T, int NR>
+hipError_t launch_det_p(const ebe_mesh* m, bool colour, const void* x, void* y, bool mask_in, bool bc, bool add,
+                        const int* gate, hipStream_t s, double* gamma) {
+  const PatchLevel& L = m->pl[0];
+  if (colour) {  // colours in turn, sums straight into y
+    const int32_t* cp = L.cperm.as<int32_t>();
+    for (size_t c = 0; c + 1 < L.coff.size(); ++c) {
+      const hipError_t e = launch_det_m<T, NR, true>(m, cp + L.coff[c], L.coff[c + 1] - L.coff[c], x, y, false,
+                                                     mask_in, bc, add, gate, s, gamma);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  const bool st = int64_t(L.nslots) * 3 * NR * int64_t(sizeof(T)) > kStreamStageBytes;
+  hipError_t e = launch_det_m<T, NR, false>(m, nullptr, L.npatch, x, y, st, mask_in, bc, add, gate, s, gamma);
   if (e != hipSuccess || L.nshared == 0) return e;
   const int64_t work = L.nshared * (3 * NR / reduce_width<T, NR>());
   hipLaunchKernelGGL((k_reduce_shared<T, NR>), dim3(unsigned((work + 255) / 256)), dim3(256), 0, s,
-                     L.snode.as<int32_t>(), L.soff.as<int32_t>(), stage, int(st), static_cast<T*>(y),
+                     L.snode.as<int32_t>(), L.soff.as<int32_t>(), L.stage.as<T>(), int(st), static_cast<T*>(y),
                      int32_t(L.nshared), int(bc), int(add), gate);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_det(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in, bool bc,
-                      bool add, const int* gate, hipStream_t s, double* gamma) {
-  if (m->pl[0].npatch < 1 || m->pl[0].pinc.bytes() == 0 || !m->geo_ready[dt == EBE_F64 ? 0 : 1])
+hipError_t launch_det(const ebe_mesh* m, ebe_dtype dt, int nrhs, bool colour, const void* x, void* y, bool mask_in,
+                      bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
+  if (m->pl[0].npatch < 1 || m->pl[0].pinc.bytes() == 0 || !m->geo_ready[dt == EBE_F64 ? 0 : 1] ||
+      (colour && m->pl[0].coff.size() < 2))
     return hipErrorInvalidValue;  // tables or geometry not prepared: host bug
   switch (nrhs) {
-#define EBE_CASE(n)                                                                                 \
-  case n:                                                                                           \
-    return dt == EBE_F64 ? launch_det_p<double, n>(m, x, y, mask_in, bc, add, gate, s, gamma)      \
-                         : launch_det_p<float, n>(m, x, y, mask_in, bc, add, gate, s, gamma);
+#define EBE_CASE(n)                                                                                       \
+  case n:                                                                                                 \
+    return dt == EBE_F64 ? launch_det_p<double, n>(m, colour, x, y, mask_in, bc, add, gate, s, gamma)    \
+                         : launch_det_p<float, n>(m, colour, x, y, mask_in, bc, add, gate, s, gamma);
     EBE_CASE(1) EBE_CASE(2) EBE_CASE(3) EBE_CASE(4) EBE_CASE(5) EBE_CASE(6) EBE_CASE(7) EBE_CASE(8)
     EBE_CASE(9) EBE_CASE(10) EBE_CASE(11) EBE_CASE(12) EBE_CASE(13) EBE_CASE(14) EBE_CASE(15) EBE_CASE(16)
 #undef EBE_CASE

@@ -352,9 +352,11 @@ ebe_status ensure_stage(ebe_mesh* m, int nrhs, size_t elem_bytes);
 
 // ---- deterministic product form (ebe_det.hip) -------------------------------
 // y = K x (quadratic level) with no atomics in the sums; needs the geometry
-// cache of dtype dt and the staging buffer (prepare_products)
-hipError_t launch_det(const ebe_mesh* m, ebe_dtype dt, int nrhs, const void* x, void* y, bool mask_in, bool bc,
-                      bool add, const int* gate, hipStream_t s, double* gamma);
+// cache of dtype dt and the staging buffer (prepare_products).  colour: the
+// patches colour by colour with sums straight into y (else staging and the
+// shared-node pass)
+hipError_t launch_det(const ebe_mesh* m, ebe_dtype dt, int nrhs, bool colour, const void* x, void* y, bool mask_in,
+                      bool bc, bool add, const int* gate, hipStream_t s, double* gamma);
 
 // ---- allocation-free product (ebe_kernels.hip) ------------------------------
 // Size of the fixed device array that stages shared-node partial sums for

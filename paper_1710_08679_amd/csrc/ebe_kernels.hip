@@ -702,7 +702,9 @@ hipError_t launch_ebe_form(const ebe_mesh* m, int order, int form, ebe_dtype dt,
        !m->geo_ready[k]) ||
       (form == EBE_FORM_ASSEMBLED && !m->k1.ready[k]))
     return hipErrorInvalidValue;  // staging, geometry or assembled values not prepared, or bad form: host bug
-  if (form == EBE_FORM_DETERMINISTIC) return launch_det(m, dt, nrhs, x, y, mask_in, bc, add, gate, s, gamma);
+  if (form == EBE_FORM_DETERMINISTIC)
+    return launch_det(m, dt, nrhs, m->fvar[order == 2 ? 0 : 1][k][nrhs] == 1 && L.coff.size() > 1, x, y, mask_in, bc,
+                      add, gate, s, gamma);
   return dt == EBE_F64 ? ebe_dispatch<double>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma)
                        : ebe_dispatch<float>(order, form, m, nrhs, x, y, mask_in, bc, add, gate, s, gamma);
 }

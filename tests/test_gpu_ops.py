@@ -35,8 +35,10 @@ FORMS = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_COLOURED
          ebe.FORM_DETERMINISTIC]  # quadratic level
 FORMS1 = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_ASSEMBLED]  # linear level
 # second variants: pipelined and coloured kernels with the geometry read per
-# work-item, gather and staged kernels with the geometry formed from the corners
-FORMS_V = FORMS + [(ebe.FORM_PIPELINED, 1), (ebe.FORM_COLOURED, 1), (ebe.FORM_GATHER, 1), (ebe.FORM_STAGED, 1)]
+# work-item, gather and staged kernels with the geometry formed from the corners,
+# the deterministic form colour by colour
+FORMS_V = FORMS + [(ebe.FORM_PIPELINED, 1), (ebe.FORM_COLOURED, 1), (ebe.FORM_GATHER, 1), (ebe.FORM_STAGED, 1),
+                   (ebe.FORM_DETERMINISTIC, 1)]
 FORMS1_V = FORMS1 + [(ebe.FORM_PIPELINED, 1), (ebe.FORM_GATHER, 1)]
 
 
@@ -260,7 +262,7 @@ def big(gpu_lib):
     return m, ebe.Mesh.from_generated(m), kappa_max(m)
 
 
-@pytest.mark.parametrize("form", FORMS + [(ebe.FORM_GATHER, 1), "tuned"])
+@pytest.mark.parametrize("form", FORMS + [(ebe.FORM_GATHER, 1), (ebe.FORM_DETERMINISTIC, 1), "tuned"])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("nrhs", [1, 16])
 def test_full_size_matvec_sampled_nodes(big, dtype, nrhs, form):
@@ -287,8 +289,9 @@ def test_full_size_matvec_sampled_nodes(big, dtype, nrhs, form):
     assert np.all(err <= tol), float(np.max(err / tol))
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("dtype,nrhs", [(np.float32, 16), (np.float64, 7), (np.float32, 1)])
-def test_deterministic_form_is_bitwise_reproducible(big, dtype, nrhs):
+def test_deterministic_form_is_bitwise_reproducible(big, dtype, nrhs, variant):
     """The deterministic form on the 64^3 workload: repeated products, with
     products of the other forms launched in between (other schedules, other
     cache contents), give the same bits; and they match the oracle on
@@ -297,7 +300,7 @@ def test_deterministic_form_is_bitwise_reproducible(big, dtype, nrhs):
     x = to_dev(meshgen.random_vectors(meshgen.rng_for(2, 40 + nrhs), m.n_nodes, nrhs), dtype)
     outs = []
     for rep in range(4):
-        with forced_form(gm, 0, dtype, nrhs, ebe.FORM_DETERMINISTIC):
+        with forced_form(gm, 0, dtype, nrhs, (ebe.FORM_DETERMINISTIC, variant)):
             outs.append(gm.matvec(x, apply_bc=rep % 2 == 0))
         with forced_form(gm, 0, dtype, nrhs, FORMS[rep % 4]):
             gm.matvec(x)
