@@ -589,7 +589,7 @@ def main():
                       + ("one k_ebe_pipe launch per patch colour" if form == "coloured" else
                          "patch kernel + shared-node pass") + ")",
             "launches_per_product": gm.patch_info(0)["colours"] if form == "coloured" else 2,
-            "ms_per_launch": ms_events,
+            "ms_per_product": ms_events,
             "algorithmic_flops": F, "algorithmic_bytes": B,
             "hbm": {"achieved": B / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": B / t / 1e9 / HBM_PEAK_GBS}}
     if traffic is not None:
