@@ -209,3 +209,25 @@ def test_full_size_curved_matvec_sampled(gpu_lib):
     worst = float(np.max(np.abs(y[nodes] - ref) / tol))
     print(f"[curved 64^3 f32 n=16] {nodes.size} nodes, worst err / bound {worst:.3g}", flush=True)
     assert worst <= 1.0
+
+
+def test_batch_with_a_curved_mesh_is_never_merged(gpu_lib):
+    """A batch of small meshes with merging on: the straight ones form a
+    merged group, the curved one is solved on its own with its own
+    (curved) operator; every result matches the oracle's direct solve."""
+    ms = [meshgen.crust_mesh(3, 3, 2), meshgen.crust_mesh(4, 3, 2),
+          meshgen.curve_edges(meshgen.crust_mesh(4, 4, 2), meshgen.rng_for(87, 0), amp=0.06)]
+    gms, fs, refs = [], [], []
+    for k, m in enumerate(ms):
+        f, _ = meshgen.dislocation_pair_loads(m, meshgen.rng_for(87, 10 + k), nrhs=9)
+        K = fem.assemble(m.xyz, m.conn, m.young, m.poisson)
+        gms.append(ebe.Mesh.from_generated(m, curved=(k == 2)))
+        fs.append(to_dev(f, np.float64))
+        refs.append(solve.sparse_solve(K, f, m.fixed))
+    info = {}
+    us, sts = ebe.batch_solve(gms, fs, tol=1e-9, info=info, merge_elems=150000)
+    print(f"[batch with a curved mesh] {info}", flush=True)
+    assert info["group_of"][2] == -1 and info["group_of"][0] == info["group_of"][1] >= 0
+    for u, r, st in zip(us, refs, sts):
+        assert st["status"] == ebe.OK and st["max_rel_res"] <= 1e-9
+        assert rel_err(u.cpu().numpy(), r) <= 1e-6
