@@ -139,21 +139,23 @@ def solver_block(torch, ebe, meshgen, modes):
     sols = {}
     ref = None
     table = {"mixed_mg3": (ebe.PREC_MG3, ebe.MODE_MIXED), "mixed_mg3_fp16coarse": (ebe.PREC_MG3, ebe.MODE_MIXED),
+             "mixed_mg3_deterministic": (ebe.PREC_MG3, ebe.MODE_MIXED),
              "fp64_mg3": (ebe.PREC_MG3, ebe.MODE_FP64),
              "mixed_mg2": (ebe.PREC_MG2, ebe.MODE_MIXED), "fp64_mg2": (ebe.PREC_MG2, ebe.MODE_FP64),
              "fp64_pcge": (ebe.PREC_PCGE, ebe.MODE_FP64)}
     for name in modes:
         precond, mode = table[name]
         half = int(name.endswith("fp16coarse"))
+        det = int(name.endswith("deterministic"))
         torch.cuda.synchronize()
         tw = time.perf_counter()
-        gm.solve(fd, precond=precond, mode=mode, tol=1e-8, coarse_half=half)  # warm-up: set-ups, workspace
+        gm.solve(fd, precond=precond, mode=mode, tol=1e-8, coarse_half=half, deterministic=det)  # warm-up
         torch.cuda.synchronize()
         t_first = time.perf_counter() - tw
         times, u, st = [], None, None
         for _ in range(3):
             t0 = time.perf_counter()
-            u, st = gm.solve(fd, precond=precond, mode=mode, tol=1e-8, coarse_half=half)
+            u, st = gm.solve(fd, precond=precond, mode=mode, tol=1e-8, coarse_half=half, deterministic=det)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
         dt = sorted(times)[1]
@@ -477,7 +479,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-greens", action="store_true")
     ap.add_argument("--no-curved", action="store_true")
-    ap.add_argument("--solver-modes", default="mixed_mg3,mixed_mg3_fp16coarse,fp64_mg3,mixed_mg2,fp64_mg2,fp64_pcge")
+    ap.add_argument("--solver-modes",
+                    default="mixed_mg3,mixed_mg3_fp16coarse,mixed_mg3_deterministic,fp64_mg3,mixed_mg2,fp64_mg2,"
+                            "fp64_pcge")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-elems", type=int, default=200000)
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle residual threads (0: min(16, cpus))")

@@ -139,6 +139,13 @@ typedef struct {
                            stored in FP16, and level 2 its A2 in FP16 (values scaled by the largest
                            magnitude over 2^14; FP32 arithmetic): a low-precision preconditioner
                            experiment that halves the coarse operators' traffic; 0 (default): off */
+  int32_t deterministic; /* 1: a bit-reproducible solve: the same u and statistics on every run.
+                            The quadratic-level products use EBE_FORM_DETERMINISTIC (with the
+                            mesh's variant for it), the linear level the assembled K1, and every
+                            (p, K p) is summed by a separate pass in a fixed order (the products'
+                            own folds use atomics); about 1.2-1.5x the time of a tuned solve.
+                            Straight-sided meshes only (else EBE_ERR_ARG); ebe_batch_solve then
+                            solves every mesh on its own.  0 (default): off */
 } ebe_pcg_opts;
 
 typedef struct {

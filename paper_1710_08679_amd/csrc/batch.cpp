@@ -402,15 +402,24 @@ ebe_status ebe_batch_solve(ebe_batch* b, const double* const* f, double* const* 
     }
   }
   // jobs: merged groups (index >= 0 into groups) and solo meshes (-1 - mesh), largest first
+  // (deterministic solves run every mesh on its own: the merged systems'
+  // case scaling sums norms with atomics)
   std::vector<int32_t> jobs;
   std::vector<double> work;
-  for (size_t g = 0; g < b->groups.size(); ++g) {
-    jobs.push_back(int32_t(g));
-    work.push_back(double(b->groups[g]->mesh->n_elem) * b->groups[g]->nr);
-  }
-  for (int32_t i : b->solo) {
-    jobs.push_back(-1 - i);
-    work.push_back(double(b->meshes[i]->n_elem) * b->nrhs[i]);
+  if (o.deterministic) {
+    for (size_t i = 0; i < n; ++i) {
+      jobs.push_back(-1 - int32_t(i));
+      work.push_back(double(b->meshes[i]->n_elem) * b->nrhs[i]);
+    }
+  } else {
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+      jobs.push_back(int32_t(g));
+      work.push_back(double(b->groups[g]->mesh->n_elem) * b->groups[g]->nr);
+    }
+    for (int32_t i : b->solo) {
+      jobs.push_back(-1 - i);
+      work.push_back(double(b->meshes[i]->n_elem) * b->nrhs[i]);
+    }
   }
   std::vector<size_t> order(jobs.size());
   std::iota(order.begin(), order.end(), 0);

@@ -140,32 +140,51 @@ uintptr_t addr(const void* p) { return reinterpret_cast<uintptr_t>(p); }
 
 // Algorithm 1(b) on one level: approximately solve A u = r starting from u.
 // The level's operator: EBE products on levels 0 and 1, the assembled A2 on level 2.
+// det (deterministic solves): products whose sums have a fixed order (the
+// deterministic form on the quadratic level, the assembled operators on the
+// coarse levels), and (x, K x) summed by a node-case pass in a fixed order
+// instead of inside the product (whose cross-workgroup fold uses atomics).
 template <typename T>
 hipError_t level_product(const ebe_mesh* m, int level, int nr, const T* x, T* y, const int* gate, hipStream_t s,
-                         double* gamma = nullptr, bool half = false) {
+                         double* gamma = nullptr, bool half = false, bool det = false,
+                         SolverState* st = nullptr) {
   // all solver vectors are kept zero on fixed DOFs, so inputs need no masking
-  if constexpr (sizeof(T) == 4) {
-    if (half && level >= 1) return launch_asm_half(m, level, nr, x, y, false, true, false, gate, s, gamma);
+  double* g = det ? nullptr : gamma;
+  hipError_t e;
+  if (sizeof(T) == 4 && half && level >= 1) {
+    e = launch_asm_half(m, level, nr, reinterpret_cast<const float*>(x), reinterpret_cast<float*>(y), false, true,
+                        false, gate, s, g);
+  } else if (level == 2) {
+    e = launch_level2(m, dtype_of<T>(), nr, x, y, false, true, false, gate, s, g);
+  } else if (det) {
+    e = launch_ebe_form(m, level == 0 ? 2 : 1, level == 0 ? EBE_FORM_DETERMINISTIC : EBE_FORM_ASSEMBLED,
+                        dtype_of<T>(), nr, x, y, false, true, false, gate, s, nullptr);
+  } else {
+    e = launch_ebe(m, level == 0 ? 2 : 1, dtype_of<T>(), nr, x, y, false, true, false, gate, s, g);
   }
-  if (level == 2) return launch_level2(m, dtype_of<T>(), nr, x, y, false, true, false, gate, s, gamma);
-  return launch_ebe(m, level == 0 ? 2 : 1, dtype_of<T>(), nr, x, y, false, true, false, gate, s, gamma);
+  if (e != hipSuccess || !det || !gamma) return e;
+  return sk_dot<T>(m, level, x, y, nr, gamma, gate, *st, s);
 }
 
 template <typename T>
 ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int nr, double eps, int nmax,
-                       bool graphs, bool half, SolverState& st, hipStream_t s) {
+                       bool graphs, bool half, bool det, SolverState& st, hipStream_t s) {
   InnerScalars* din = &st.sc->inner[level];
   half = half && sizeof(T) == 4 && level >= 1;
-  EBE_K(level_product<T>(m, level, nr, u, q, &st.sc->outer_active, s, nullptr, half));
+  EBE_K(level_product<T>(m, level, nr, u, q, &st.sc->outer_active, s, nullptr, half, det, &st));
   EBE_K(sk_inner_init<T>(m, level, r, q, e, nr, eps, nmax, st, s));
   int enq = 0;
   int chunk = level == 0 ? 3 : (level == 1 ? 4 : 8);
   while (enq < nmax - 1) {
     const int k = std::min(chunk, nmax - 1 - enq);
     const void* data = level == 2 ? m->a2.val[sizeof(T) == 8 ? 0 : 1].as<void>() : m->pl[level].stage.as<void>();
-    const uintptr_t form = half ? uintptr_t(64)  // the FP16 assembled operator
-                                : (level == 2 ? uintptr_t(EBE_FORM_ASSEMBLED)
-                                              : product_key(m, level == 0 ? 2 : 1, dtype_of<T>(), nr));
+    const uintptr_t form = (half ? uintptr_t(64)  // the FP16 assembled operator
+                                 : (level == 2 ? uintptr_t(EBE_FORM_ASSEMBLED)
+                                               : (det ? uintptr_t(level == 0 ? EBE_FORM_DETERMINISTIC
+                                                                             : EBE_FORM_ASSEMBLED) |
+                                                            (uintptr_t(m->fvar[0][sizeof(T) == 8 ? 0 : 1][nr]) << 8)
+                                                      : product_key(m, level == 0 ? 2 : 1, dtype_of<T>(), nr)))) |
+                           (det ? uintptr_t(1) << 16 : 0);
     ebe_status rs = enqueue_steps(
         m,
         {1, uintptr_t(level), uintptr_t(k), uintptr_t(nr), sizeof(T), uintptr_t(form), addr(e), addr(p), addr(q),
@@ -175,7 +194,7 @@ ebe_status inner_solve(ebe_mesh* m, int level, T* r, T* u, T* e, T* p, T* q, int
         graphs, s, [&]() -> ebe_status {
           for (int c = 0; c < k; ++c) {
             EBE_K(sk_inner_p<T>(m, level, e, p, q, nr, st, s));
-            EBE_K(level_product<T>(m, level, nr, p, q, &din->active, s, din->gamma, half));
+            EBE_K(level_product<T>(m, level, nr, p, q, &din->active, s, din->gamma, half, det, &st));
             EBE_K(sk_inner_update<T>(m, level, e, u, q, p, nr, eps, nmax, st, s));
           }
           return EBE_OK;
@@ -215,17 +234,17 @@ ebe_status mg_precondition(ebe_mesh* m, int nr, const ebe_pcg_opts& o, const Buf
     EBE_K(launch_restrict_p2(m, dt, nr, u1, u2, s));           // u2 <= P2^T u1
     ebe_status r2s = inner_solve<T>(m, 2, r2, u2, static_cast<T*>(b.e2), static_cast<T*>(b.p2),
                                     static_cast<T*>(b.q2), nr, o.inner_eps[2], o.inner_max[2], o.graphs != 0,
-                                    o.coarse_half != 0, st, s);
+                                    o.coarse_half != 0, o.deterministic != 0, st, s);
     if (r2s != EBE_OK) return r2s;
     EBE_K(launch_prolong_p2(m, dt, nr, u2, u1, s));            // u1 <= P2 u2
   }
   ebe_status rs = inner_solve<T>(m, 1, r1, u1, static_cast<T*>(b.e1), static_cast<T*>(b.p1),
                                  static_cast<T*>(b.q1), nr, o.inner_eps[1], o.inner_max[1], o.graphs != 0,
-                                 o.coarse_half != 0, st, s);
+                                 o.coarse_half != 0, o.deterministic != 0, st, s);
   if (rs != EBE_OK) return rs;
   EBE_K(launch_prolong(m, dt, nr, u1, ub, true, s));           // u_bar <= P1 u1
   rs = inner_solve<T>(m, 0, rb, ub, static_cast<T*>(b.e0), static_cast<T*>(b.p0), static_cast<T*>(b.q0), nr,
-                      o.inner_eps[0], o.inner_max[0], o.graphs != 0, false, st, s);
+                      o.inner_eps[0], o.inner_max[0], o.graphs != 0, false, o.deterministic != 0, st, s);
   if (rs != EBE_OK) return rs;
   EBE_K(sk_outer_z_cast<T>(m, ub, b.r, b.q, nr, st, s));  // z = u_bar: (z,q), (z,r), beta
   EBE_K(sk_outer_p_cast<T>(m, ub, b.p, nr, st, s));       // p <= z + beta p
@@ -238,7 +257,7 @@ ebe_status check_opts(const ebe_pcg_opts& o) {
       o.check_every < 1 || o.inner_max[0] < 1 || o.inner_max[1] < 1 || o.inner_max[2] < 1 ||
       !(o.inner_eps[0] >= 0.0) || !(o.inner_eps[1] >= 0.0) || !(o.inner_eps[2] >= 0.0) ||
       (o.coarse_guess != 0 && o.coarse_guess != 1) || (o.graphs != 0 && o.graphs != 1) ||
-      (o.coarse_half != 0 && o.coarse_half != 1)) {
+      (o.coarse_half != 0 && o.coarse_half != 1) || (o.deterministic != 0 && o.deterministic != 1)) {
     set_error("ebe_pcg_solve: invalid options");
     return EBE_ERR_ARG;
   }
@@ -289,6 +308,11 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   else ebe_pcg_default_opts(&o);
   ebe_status st_ = check_opts(o);
   if (st_ != EBE_OK) return st_;
+  if (o.deterministic && m->curved) {
+    set_error("ebe_pcg_solve: deterministic solves need straight-sided elements (the curved kernel sums with "
+              "atomics)");
+    return EBE_ERR_ARG;
+  }
   // level 2's set-up sums a coarse row in LDS: past its limit, run MG2
   if (o.precond == EBE_PREC_MG3 && m->a2_maxlen > kA2MaxRow) o.precond = EBE_PREC_MG2;
   const int64_t captures0 = m->ws.captures;
@@ -321,7 +345,8 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
     void *x, *y;
     size_t bytes;
   } tunes[3] = {{0, EBE_F64, b.p, b.q, vbytes}, {0, inner_dt, b.p0, b.q0, vbytes}, {1, inner_dt, b.p1, b.q1, v1bytes}};
-  for (int t = 0; t < (mg ? 3 : 1); ++t) {
+  const bool det = o.deterministic != 0;
+  for (int t = 0; t < (mg ? 3 : 1) && !det; ++t) {  // a deterministic solve uses fixed forms
     const Tune& k = tunes[t];
     if (m->form[k.level][k.dt == EBE_F64 ? 0 : 1][nr] != EBE_FORM_AUTO) continue;
     EBE_K(launch_fill_zero(k.x, k.bytes, s));
@@ -330,6 +355,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   }
   for (int t = 0; t < (mg ? 3 : 1); ++t)
     if ((st_ = prepare_products(m, tunes[t].level, tunes[t].dt, nr, s)) != EBE_OK) return st_;
+  if (det && mg && (st_ = ensure_assembled(m, inner_dt, s)) != EBE_OK) return st_;
   if (o.precond == EBE_PREC_MG3 && (st_ = ensure_level2(m, inner_dt, s)) != EBE_OK) return st_;
   if (o.coarse_half && o.mode != EBE_MODE_MIXED) o.coarse_half = 0;  // FP16 coarse operators feed FP32 loops only
   if (mg && o.coarse_half && (st_ = ensure_half(m, 1, s)) != EBE_OK) return st_;
@@ -341,7 +367,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
   if (o.use_x0) EBE_K(sk_mask_u(m, u, nr, st, s));
   else EBE_K(launch_fill_zero(u, vbytes, s));
   // lines 4-5: r <= f - sum_i K_i u_i
-  EBE_K(launch_ebe(m, 2, EBE_F64, nr, u, b.q, false, true, false, nullptr, s));
+  EBE_K(level_product<double>(m, 0, nr, u, b.q, nullptr, s, nullptr, false, det, &st));
   EBE_K(sk_outer_init(m, f, b.q, b.r, nr, o.tol, st, s));
 
   if (!mg) EBE_K(sk_outer_z_bj(m, b.r, b.q, nr, st, s));  // first z = M^-1 r: rho (beta = 0 at iteration 0)
@@ -354,7 +380,7 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
     const int k = std::min(per_check, o.max_outer - enq);
     // q <= K p, gamma <= (p, K p); alpha; r, u updates
     auto product_and_update = [&]() -> ebe_status {
-      EBE_K(launch_ebe(m, 2, EBE_F64, nr, b.p, b.q, false, true, false, &st.sc->outer_active, s, st.sc->gamma));
+      EBE_K(level_product<double>(m, 0, nr, b.p, b.q, &st.sc->outer_active, s, st.sc->gamma, false, det, &st));
       EBE_K(sk_outer_update(m, b.r, u, b.q, b.p, nr, o.tol, o.max_outer, st, s));
       return EBE_OK;
     };
@@ -367,7 +393,11 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
       }
     } else {
       rs = enqueue_steps(m,
-                         {2, uintptr_t(k), uintptr_t(nr), product_key(m, 2, EBE_F64, nr), addr(b.r),
+                         {2, uintptr_t(k), uintptr_t(nr),
+                          det ? (uintptr_t(EBE_FORM_DETERMINISTIC) | (uintptr_t(m->fvar[0][0][nr]) << 8) |
+                                 (uintptr_t(1) << 16))
+                              : product_key(m, 2, EBE_F64, nr),
+                          addr(b.r),
                           addr(b.p), addr(b.q), addr(u), addr(st.sc),
                           addr(st.partials), addr(st.counter), addr(m->pl[0].stage.as<void>()),
                           addr(m->gacc.as<void>()), addr(m->minv64[0].as<void>()), bits_of(o.tol),
@@ -376,8 +406,8 @@ ebe_status ebe_pcg_solve(ebe_mesh* m, int32_t nr, const double* f, double* u, co
                            for (int c = 0; c < k; ++c) {
                              EBE_K(sk_outer_p_bj(m, b.r, b.p, nr, st, s));  // p <= z + beta p, z = M^-1 r
                              // q <= K p, gamma <= (p, K p); alpha; r, u updates; next (z,q), (z,r), beta
-                             EBE_K(launch_ebe(m, 2, EBE_F64, nr, b.p, b.q, false, true, false, &st.sc->outer_active,
-                                              s, st.sc->gamma));
+                             EBE_K(level_product<double>(m, 0, nr, b.p, b.q, &st.sc->outer_active, s,
+                                                         st.sc->gamma, false, det, &st));
                              EBE_K(sk_outer_update_z_bj(m, b.r, u, b.q, b.p, nr, o.tol, o.max_outer, st, s));
                            }
                            return EBE_OK;

@@ -404,6 +404,19 @@ struct BodyInnerUpdate {
   }
 };
 
+// sums (a, b) per case in FP64 (the (p, K p) of a deterministic solve)
+template <typename T>
+struct BodyDot {
+  const T* a;
+  const T* b;
+  int nr;
+  __device__ void operator()(int64_t node, int col, double* acc) const {
+    const int64_t i0 = NC_IDX(node, 0, col);
+    acc[0] += double(a[i0]) * double(b[i0]) + double(a[i0 + nr]) * double(b[i0 + nr]) +
+              double(a[i0 + 2 * nr]) * double(b[i0 + 2 * nr]);
+  }
+};
+
 #undef NC_IDX
 
 // ---------------------------------------------------------------------------
@@ -501,6 +514,16 @@ struct EpiOuterConvBeta {
     return rel;
   }
   __device__ void finish(double worst, int flags) const { conv.finish(worst, flags); }
+};
+
+// gamma[j] = the case's sum (fixed-order partials; no atomics)
+struct EpiSetGamma {
+  double* gamma;
+  __device__ double step(const double* tot, int, int j, int&) const {
+    gamma[j] = tot[j];
+    return 0.0;
+  }
+  __device__ void finish(double, int) const {}
 };
 
 template <typename T>
@@ -651,6 +674,16 @@ hipError_t sk_inner_update(const ebe_mesh* m, int level, T* e, T* u, const T* q,
                             EpiInnerStep<T>{&st.sc->inner[level], eps, nmax}, n, nr, st,
                             &st.sc->inner[level].active, s);
 }
+
+template <typename T>
+hipError_t sk_dot(const ebe_mesh* m, int level, const T* a, const T* b, int nr, double* gamma, const int* gate,
+                  SolverState& st, hipStream_t s) {
+  return run_nodecase<double, 1>(BodyDot<T>{a, b, nr}, EpiSetGamma{gamma}, level_rows(m, level), nr, st, gate, s);
+}
+template hipError_t sk_dot<float>(const ebe_mesh*, int, const float*, const float*, int, double*, const int*,
+                                  SolverState&, hipStream_t);
+template hipError_t sk_dot<double>(const ebe_mesh*, int, const double*, const double*, int, double*, const int*,
+                                   SolverState&, hipStream_t);
 
 #define EBE_INST(T)                                                                                              \
   template hipError_t sk_inner_init<T>(const ebe_mesh*, int, const T*, const T*, T*, int, double, int,            \

@@ -72,5 +72,10 @@ hipError_t sk_inner_p(const ebe_mesh* m, int level, const T* e, T* p, T* q, int 
 template <typename T>
 hipError_t sk_inner_update(const ebe_mesh* m, int level, T* e, T* u, const T* q, const T* p, int nr, double eps,
                            int nmax, SolverState& st, hipStream_t s);
+// gamma[j] = (a_j, b_j) on level `level` (rows of that level), summed in a
+// fixed order; skipped when gate is non-null and *gate == 0
+template <typename T>
+hipError_t sk_dot(const ebe_mesh* m, int level, const T* a, const T* b, int nr, double* gamma, const int* gate,
+                  SolverState& st, hipStream_t s);
 
 }  // namespace ebe

@@ -45,7 +45,7 @@ class PcgOpts(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("inner_eps", ctypes.c_double * 3), ("inner_max", ctypes.c_int32 * 3),
                 ("use_x0", ctypes.c_int32), ("coarse_guess", ctypes.c_int32), ("graphs", ctypes.c_int32),
-                ("coarse_half", ctypes.c_int32)]
+                ("coarse_half", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 class PcgStats(ctypes.Structure):

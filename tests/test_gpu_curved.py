@@ -183,6 +183,9 @@ def test_curved_mesh_refusals(curved):
     with pytest.raises(ebe.EbeError) as ei:
         ebe.Fault(gm, sides, np.array([m.conn[0, 0]], dtype=np.int32), np.ones((1, 1)), np.array([[1.0, 0, 0]]))
     assert ei.value.status == ebe.ERR_ARG and "curved" in str(ei.value)
+    with pytest.raises(ebe.EbeError) as ei:  # the curved kernel sums with LDS atomics
+        gm.solve(to_dev(np.zeros((m.n_nodes, 3, 2)), np.float64), deterministic=1)
+    assert ei.value.status == ebe.ERR_ARG
     ms = gm.autotune(0, torch.float32, 4)
     assert ms[ebe.FORM_GATHER] > 0 and all(ms[f] < 0 for f in (ebe.FORM_STAGED, ebe.FORM_PIPELINED,
                                                                  ebe.FORM_COLOURED, ebe.FORM_DETERMINISTIC))

@@ -82,6 +82,27 @@ def test_crust_mixed_mg2_in_each_product_form(crust, form):
     assert rel_err(u.cpu().numpy(), ud) <= 1e-6
 
 
+@pytest.mark.parametrize("precond,mode,tol,bound", [(ebe.PREC_MG3, ebe.MODE_MIXED, 1e-8, 1e-6),
+                                                    (ebe.PREC_MG2, ebe.MODE_FP64, 1e-13, 1e-10),
+                                                    (ebe.PREC_PCGE, ebe.MODE_FP64, 1e-11, 1e-8)])
+def test_deterministic_solves_are_bitwise_reproducible(crust, precond, mode, tol, bound):
+    """opts.deterministic: two solves (the second on a side stream, with graph
+    capture) give the same bits and the same statistics, and the solution
+    matches the oracle's direct solve."""
+    m, gm, f, K, ud = crust
+    fd = dev(f)
+    u1, st1 = gm.solve(fd, precond=precond, mode=mode, tol=tol, deterministic=1)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        u2, st2 = gm.solve(fd, precond=precond, mode=mode, tol=tol, deterministic=1, stream=side)
+    side.synchronize()
+    print(f"[deterministic precond={precond} mode={mode}] {st1} / {st2}", flush=True)
+    assert st1["status"] == ebe.OK and torch.equal(u1, u2)
+    for k in ("outer_iters", "inner_iters", "max_rel_res"):
+        assert st1[k] == st2[k], k
+    assert rel_err(u1.cpu().numpy(), ud) <= bound
+
+
 @pytest.mark.parametrize("coarse_guess", [0, 1])
 def test_crust_mixed_mg2_within_1e6(crust, coarse_guess):
     m, gm, f, K, ud = crust
