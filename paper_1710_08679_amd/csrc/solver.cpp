@@ -150,20 +150,18 @@ hipError_t level_product(const ebe_mesh* m, int level, int nr, const T* x, T* y,
                          SolverState* st = nullptr) {
   // all solver vectors are kept zero on fixed DOFs, so inputs need no masking
   double* g = det ? nullptr : gamma;
-  hipError_t e;
-  if (sizeof(T) == 4 && half && level >= 1) {
-    e = launch_asm_half(m, level, nr, reinterpret_cast<const float*>(x), reinterpret_cast<float*>(y), false, true,
-                        false, gate, s, g);
-  } else if (level == 2) {
-    e = launch_level2(m, dtype_of<T>(), nr, x, y, false, true, false, gate, s, g);
-  } else if (det) {
-    e = launch_ebe_form(m, level == 0 ? 2 : 1, level == 0 ? EBE_FORM_DETERMINISTIC : EBE_FORM_ASSEMBLED,
-                        dtype_of<T>(), nr, x, y, false, true, false, gate, s, nullptr);
-  } else {
-    e = launch_ebe(m, level == 0 ? 2 : 1, dtype_of<T>(), nr, x, y, false, true, false, gate, s, g);
+  auto then_dot = [&](hipError_t e) -> hipError_t {
+    if (e != hipSuccess || !det || !gamma) return e;
+    return sk_dot<T>(m, level, x, y, nr, gamma, gate, *st, s);
+  };
+  if constexpr (sizeof(T) == 4) {
+    if (half && level >= 1) return then_dot(launch_asm_half(m, level, nr, x, y, false, true, false, gate, s, g));
   }
-  if (e != hipSuccess || !det || !gamma) return e;
-  return sk_dot<T>(m, level, x, y, nr, gamma, gate, *st, s);
+  if (level == 2) return then_dot(launch_level2(m, dtype_of<T>(), nr, x, y, false, true, false, gate, s, g));
+  if (det)
+    return then_dot(launch_ebe_form(m, level == 0 ? 2 : 1, level == 0 ? EBE_FORM_DETERMINISTIC : EBE_FORM_ASSEMBLED,
+                                    dtype_of<T>(), nr, x, y, false, true, false, gate, s, nullptr));
+  return then_dot(launch_ebe(m, level == 0 ? 2 : 1, dtype_of<T>(), nr, x, y, false, true, false, gate, s, g));
 }
 
 template <typename T>
