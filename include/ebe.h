@@ -428,6 +428,10 @@ ebe_status ebe_get_product_form(const ebe_mesh* mesh, int32_t level, ebe_dtype d
  * element).  DETERMINISTIC: 0 = shared nodes' partial sums staged and
  * added by a second pass, 1 = patches colour by colour with their sums added
  * straight into y (the colour order is fixed, so still bit-reproducible).
+ * ASSEMBLED: the tile, cases per work-item and block slots per trip: FP32
+ * 0 = 4 / 4, 1 = 2 / 4, 2 = 8 / 2; FP64 0 = 4 / 1, 1 = 2 / 2, 2 = 1 / 4
+ * (cases per work-item reduced to a divisor of nrhs).  Variant 2 exists for
+ * ASSEMBLED only; the other forms take it as 0.
  * Same result up to rounding; ebe_autotune sets it,
  * ebe_set_product_form resets it to 0; other forms ignore it. */
 ebe_status ebe_set_product_variant(ebe_mesh* mesh, int32_t level, ebe_dtype dtype, int32_t nrhs, int32_t variant);

@@ -48,12 +48,13 @@ ebe_status tune_product(ebe_mesh* m, int level, ebe_dtype dt, int nrhs, const vo
     // the patch kernels come in two variants: pipelined and coloured with
     // the element geometry kept in LDS or read per work-item, gather and
     // staged with the geometry read from the cache or formed from the corner
-    // coordinates, deterministic with staging or colour by colour: measure
-    // both
+    // coordinates, deterministic with staging or colour by colour; the
+    // assembled form comes in three tiles: measure them all
     const bool curved = order == 2 && m->curved;
-    const int nvar = (form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED ||
-                      ((form == EBE_FORM_GATHER || form == EBE_FORM_STAGED) && !curved) ||
-                      (form == EBE_FORM_DETERMINISTIC && m->pl[0].coff.size() > 1))
+    const int nvar = form == EBE_FORM_ASSEMBLED ? 3  // tiles: cases per work-item, slots per trip
+                     : (form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED ||
+                        ((form == EBE_FORM_GATHER || form == EBE_FORM_STAGED) && !curved) ||
+                        (form == EBE_FORM_DETERMINISTIC && m->pl[0].coff.size() > 1))
                          ? 2
                          : 1;
     for (int var = 0; var < nvar && e == hipSuccess; ++var) {
@@ -125,8 +126,8 @@ ebe_status ebe_set_product_form(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_
 
 ebe_status ebe_set_product_variant(ebe_mesh* m, int32_t level, ebe_dtype dt, int32_t nrhs, int32_t variant) {
   if (!valid_args(m, level, dt, nrhs, "ebe_set_product_variant")) return EBE_ERR_ARG;
-  if (variant != 0 && variant != 1) {
-    set_error("ebe_set_product_variant: variant %d is not 0 or 1", variant);
+  if (variant < 0 || variant > 2) {
+    set_error("ebe_set_product_variant: variant %d is not 0, 1 or 2", variant);
     return EBE_ERR_ARG;
   }
   m->fvar[level][dt == EBE_F64 ? 0 : 1][nrhs] = int8_t(variant);

@@ -298,33 +298,41 @@ __attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) 
 #ifndef EBE_ASM_WG_PER_CU
 #define EBE_ASM_WG_PER_CU 8
 #endif
-template <typename T, int NR>
+// Tiles of the assembled product (cases per work-item, slots per trip), one
+// per kernel variant: 0 is the default, 1 and 2 are in the tuner's search.
+constexpr int asm_tile_cpl(bool f32, int v) {
+  return f32 ? (v == 1 ? 2 : (v == 2 ? 8 : EBE_ASM_CPL_F32)) : (v == 1 ? 2 : (v == 2 ? 1 : EBE_ASM_CPL_F64));
+}
+constexpr int asm_tile_unroll(bool f32, int v) {
+  return f32 ? (v == 1 ? 4 : (v == 2 ? 2 : EBE_ASM_UNROLL_F32)) : (v == 1 ? 2 : (v == 2 ? 4 : EBE_ASM_UNROLL_F64));
+}
+template <typename T, int NR, int V = 0>
 constexpr int asm_cpl() {
-  int c = sizeof(T) == 4 ? EBE_ASM_CPL_F32 : EBE_ASM_CPL_F64;
+  int c = asm_tile_cpl(sizeof(T) == 4, V);
   while (c > 1 && NR % c != 0) c /= 2;
   return c;
 }
-template <typename T, int NR>
-constexpr int asm_rows() { return 256 / (NR / asm_cpl<T, NR>()); }
-template <typename T, int NR>
-constexpr int asm_threads() { return asm_rows<T, NR>() * (NR / asm_cpl<T, NR>()); }
+template <typename T, int NR, int V = 0>
+constexpr int asm_rows() { return 256 / (NR / asm_cpl<T, NR, V>()); }
+template <typename T, int NR, int V = 0>
+constexpr int asm_threads() { return asm_rows<T, NR, V>() * (NR / asm_cpl<T, NR, V>()); }
 
 // S: the stored value type (T, or FP16 holding the values divided by vscale,
-// which multiplies each row's sums at the end).
-template <typename T, int NR, typename S = T>
-__global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
+// which multiplies each row's sums at the end).  TV: the tile variant.
+template <typename T, int NR, typename S = T, int TV = 0>
+__global__ __launch_bounds__((asm_threads<T, NR, TV>())) void k_assembled(
     const int32_t* __restrict__ soff, const int32_t* __restrict__ col, const S* __restrict__ val,
     const uint8_t* __restrict__ fix, const T* __restrict__ x, T* __restrict__ y, int64_t nv, int mask_in, int bc,
     int add, double* __restrict__ gamma, double* __restrict__ gslot, unsigned* __restrict__ gcount,
     const int* __restrict__ gate, T vscale = T(1)) {
   constexpr int W = 3 * NR;
-  constexpr int CPL = asm_cpl<T, NR>();
+  constexpr int CPL = asm_cpl<T, NR, TV>();
   constexpr int LPR = NR / CPL;  // work-items per row
-  constexpr int RPB = asm_rows<T, NR>();
+  constexpr int RPB = asm_rows<T, NR, TV>();
   constexpr int VW = CPL * int(sizeof(T)) > 16 ? 16 / int(sizeof(T)) : CPL;  // values per (<= 16-byte) vector
   constexpr int NVEC = CPL / VW;
   constexpr int SR = kSliceRows;
-  constexpr int U = sizeof(T) == 4 ? EBE_ASM_UNROLL_F32 : EBE_ASM_UNROLL_F64;  // slots per trip
+  constexpr int U = asm_tile_unroll(sizeof(T) == 4, TV);  // slots per trip
   using V = VecT<T, VW>;
   __shared__ double gsum[NR];
   if (gate && *gate == 0) return;
@@ -454,7 +462,7 @@ __global__ __launch_bounds__((asm_threads<T, NR>())) void k_assembled(
 #pragma unroll
     for (int t = 0; t < CPL; ++t) atomicAdd(&gsum[j0 + t], en[t]);
     __syncthreads();
-    fold_gamma<NR, (asm_threads<T, NR>())>(gsum, gamma, gslot, gcount);
+    fold_gamma<NR, (asm_threads<T, NR, TV>())>(gsum, gamma, gslot, gcount);
   }
 }
 
@@ -486,16 +494,16 @@ void launch_patch(const ebe_mesh* m, const PatchLevel& L, const void* x, void* y
     launch_patch_m<T, NR, ORDER, STAGE, false, CURVED>(m, L, x, y, stage, stream, bc, add, gate, s, gamma, cache);
 }
 // y = A x for an assembled operator whose row fix bits are `fix`
-template <typename T, int NR>
+template <typename T, int NR, int V = 0>
 hipError_t launch_asm_p(const ebe_mesh* m, const AsmOp& op, const uint8_t* fix, const void* x, void* y,
                         bool mask_in, bool bc, bool add, const int* gate, hipStream_t s, double* gamma) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess || cus < 1)
     cus = 256;
-  constexpr int RPB = asm_rows<T, NR>();
+  constexpr int RPB = asm_rows<T, NR, V>();
   const int64_t grid =
       std::max<int64_t>(1, std::min<int64_t>((op.rows + RPB - 1) / RPB, int64_t(EBE_ASM_WG_PER_CU) * cus));
-  hipLaunchKernelGGL((k_assembled<T, NR>), dim3(unsigned(grid)), dim3(asm_threads<T, NR>()), 0, s,
+  hipLaunchKernelGGL((k_assembled<T, NR, T, V>), dim3(unsigned(grid)), dim3(asm_threads<T, NR, V>()), 0, s,
                      op.soff.as<int32_t>(), op.col.as<int32_t>(), op.val[sizeof(T) == 8 ? 0 : 1].as<T>(), fix,
                      static_cast<const T*>(x), static_cast<T*>(y), op.rows, int(mask_in), int(bc), int(add), gamma,
                      m->gacc.as<double>(), reinterpret_cast<unsigned*>(m->gacc.as<char>() + kGammaBytes - 64),
@@ -524,8 +532,13 @@ hipError_t ebe_dispatch_p(int order, int form, const ebe_mesh* m, const void* x,
                           bool add, const int* gate, hipStream_t s, double* gamma) {
   const PatchLevel& L = m->pl[order == 2 ? 0 : 1];
   T* stage = L.stage.as<T>();
-  if (form == EBE_FORM_ASSEMBLED)  // linear level only (checked by the caller)
-    return launch_asm_p<T, NR>(m, m->k1, m->fix.as<uint8_t>(), x, y, mask_in, bc, add, gate, s, gamma);
+  if (form == EBE_FORM_ASSEMBLED) {  // linear level only (checked by the caller); tile variant 0..2
+    const int var = m->fvar[1][sizeof(T) == 8 ? 0 : 1][NR];
+    const uint8_t* fx = m->fix.as<uint8_t>();
+    if (var == 1) return launch_asm_p<T, NR, 1>(m, m->k1, fx, x, y, mask_in, bc, add, gate, s, gamma);
+    if (var == 2) return launch_asm_p<T, NR, 2>(m, m->k1, fx, x, y, mask_in, bc, add, gate, s, gamma);
+    return launch_asm_p<T, NR>(m, m->k1, fx, x, y, mask_in, bc, add, gate, s, gamma);
+  }
   if (form == EBE_FORM_PIPELINED || form == EBE_FORM_COLOURED) {
     const bool colour = form == EBE_FORM_COLOURED;
     const int var = m->fvar[order == 2 ? 0 : 1][sizeof(T) == 8 ? 0 : 1][NR];

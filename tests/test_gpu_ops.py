@@ -36,10 +36,10 @@ FORMS = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_COLOURED
 FORMS1 = [ebe.FORM_GATHER, ebe.FORM_STAGED, ebe.FORM_PIPELINED, ebe.FORM_ASSEMBLED]  # linear level
 # second variants: pipelined and coloured kernels with the geometry read per
 # work-item, gather and staged kernels with the geometry formed from the corners,
-# the deterministic form colour by colour
+# the deterministic form colour by colour, the assembled form in its other tiles
 FORMS_V = FORMS + [(ebe.FORM_PIPELINED, 1), (ebe.FORM_COLOURED, 1), (ebe.FORM_GATHER, 1), (ebe.FORM_STAGED, 1),
                    (ebe.FORM_DETERMINISTIC, 1)]
-FORMS1_V = FORMS1 + [(ebe.FORM_PIPELINED, 1), (ebe.FORM_GATHER, 1)]
+FORMS1_V = FORMS1 + [(ebe.FORM_PIPELINED, 1), (ebe.FORM_GATHER, 1), (ebe.FORM_ASSEMBLED, 1), (ebe.FORM_ASSEMBLED, 2)]
 
 
 class forced_form:
