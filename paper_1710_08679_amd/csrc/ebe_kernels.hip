@@ -50,7 +50,7 @@ namespace {
 // q = K p without a separate inner-product pass.
 template <typename T, int NR, int ORDER, bool STAGE, bool MASK, bool CURVED>
 __global__ __launch_bounds__(threads_for(NR, ORDER, int(sizeof(T)), STAGE))
-__attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE)))) void k_ebe_patch(
+__attribute__((amdgpu_waves_per_eu(patch_waves_per_simd<T>(NR, ORDER, STAGE, CURVED)))) void k_ebe_patch(
     const int32_t* __restrict__ conn, const uint8_t* __restrict__ lconn, const int32_t* __restrict__ pelem,
     const int32_t* __restrict__ poff, const int32_t* __restrict__ pnode, const int32_t* __restrict__ pslot,
     const double4* __restrict__ xv, const typename Pair<T>::type* __restrict__ lame, const T* __restrict__ x,

@@ -88,7 +88,12 @@ constexpr int threads_for(int nr, int order, int value_bytes, bool stage) {
 // room for (160 KiB per CU, 4 SIMDs); the kernel asks the compiler for no
 // more registers than that occupancy allows, but never for fewer than the
 // element arithmetic needs without spilling: 128 (FP32, and the linear
-// element) or 256 (quadratic FP64).
+// element) or 256 (quadratic FP64).  Exception: straight quadratic FP64
+// patches of at most 4 cases take three wavefronts per SIMD (168 registers,
+// at most 32 bytes of spills per work-item): their small workgroups are
+// bound by the latency of each patch's chain of loads, not by the
+// arithmetic (gather form on the 64^3 cube, one case: 0.172 -> 0.151 ms,
+// two cases: 0.287 -> 0.257 ms).
 template <typename T>
 constexpr int patch_lds_bytes(int nr, int order, bool stage) {
   const int maxn = order == 2 ? kPatchNodes : kLinPatchCorners;
@@ -98,11 +103,11 @@ constexpr int patch_lds_bytes(int nr, int order, bool stage) {
          8 * maxn + 8 * nr + 16;
 }
 template <typename T>
-constexpr int patch_waves_per_simd(int nr, int order, bool stage) {
+constexpr int patch_waves_per_simd(int nr, int order, bool stage, bool curved = false) {
   const int lds = (patch_lds_bytes<T>(nr, order, stage) + 511) / 512 * 512;  // allocation granule
   const int wg = 163840 / lds;
   const int w = (wg > 0 ? wg : 1) * (threads_for(nr, order, int(sizeof(T)), stage) / 64) / 4;
-  const int most = (sizeof(T) == 8 && order == 2) ? 2 : 4;
+  const int most = (sizeof(T) == 8 && order == 2) ? (nr <= 4 && !curved ? 3 : 2) : 4;
   return w > most ? most : (w < 1 ? 1 : w);
 }
 
