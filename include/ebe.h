@@ -399,7 +399,8 @@ ebe_status ebe_invert_lcurve(int32_t n_obs, int32_t n_basis, const double* G_dev
 
 /* Time every product form of y = K x (level 0: quadratic mesh, level 1:
  * linear mesh) for (dtype, nrhs) on this mesh, and for GATHER, STAGED,
- * PIPELINED and COLOURED every kernel variant (ebe_set_product_variant), and keep the
+ * PIPELINED, COLOURED, DETERMINISTIC and ASSEMBLED every kernel variant
+ * (ebe_set_product_variant), and keep the
  * fastest for every later product with these
  * parameters (Section 4 tunes its kernels' parameters by hand; here the
  * search is measured on the mesh); ms_out[EBE_NUM_FORMS] (or NULL) receives
