@@ -335,10 +335,11 @@ __attribute__((amdgpu_waves_per_eu(pipe_waves_per_simd<T>(NR, ORDER, GEO, NP))))
       // patch's stores (64^3 cube, 16 cases: 0.685 -> 0.669 ms FP32, 1.385 ->
       // 1.321 ms FP64).  The other forms read y only for y += K x and keep
       // one read per row piece, which measured faster for them; the
-      // geometry-in-LDS variant has no registers to spare for it.  The
-      // coloured form writes y with streaming (non-temporal) stores: a
-      // product's y is larger than the last-level cache at 16 cases, and
-      // keeping x there instead measured 2% faster (FP32 and FP64).
+      // geometry-in-LDS variant has no registers to spare for it.  y is
+      // written with streaming (non-temporal) stores: a product's y is
+      // larger than the last-level cache at 16 cases, and keeping x there
+      // instead measured faster (FP32 16 cases, bench.py's timing: coloured
+      // 0.667-0.680 -> 0.651-0.669 ms, pipelined 0.703-0.706 -> 0.687-0.689).
       constexpr bool kReadFirst = COLOUR && !GEO;
       V old[kReadFirst ? KIT : 1];
 #pragma unroll
@@ -377,16 +378,14 @@ __attribute__((amdgpu_waves_per_eu(pipe_waves_per_simd<T>(NR, ORDER, GEO, NP))))
                 else o = *yp;
 #pragma unroll
                 for (int t = 0; t < VEC; ++t) o.v[t] += v.v[t];
-                if constexpr (COLOUR) store_stream<T, VEC>(reinterpret_cast<T*>(yp), o);
-                else *yp = o;
+                store_stream<T, VEC>(reinterpret_cast<T*>(yp), o);
               }
             } else {
               if (fixed) {
 #pragma unroll
                 for (int t = 0; t < VEC; ++t) v.v[t] = T(0);
               }
-              if constexpr (COLOUR) store_stream<T, VEC>(reinterpret_cast<T*>(yp), v);
-              else *yp = v;
+              store_stream<T, VEC>(reinterpret_cast<T*>(yp), v);
             }
           }
         }
