@@ -66,7 +66,7 @@ def curved(gpu_lib):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("nrhs", [1, 4, 7, 16])
+@pytest.mark.parametrize("nrhs", [1, 2, 4, 7, 16])
 def test_curved_matvec_matches_oracle(curved, dtype, nrhs):
     m, gm, K, absK, kap = curved
     x = meshgen.random_vectors(meshgen.rng_for(79, nrhs), m.n_nodes, nrhs).astype(dtype).astype(np.float64)
