@@ -77,6 +77,21 @@ def test_matvec_matches_oracle(small, dtype, nrhs, form):
 
 @pytest.mark.parametrize("form", FORMS_V)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("nrhs", [5, 6, 8, 10, 11, 12, 13, 14, 15])
+def test_matvec_other_case_counts(small, dtype, nrhs, form):
+    """The case counts the test above leaves out: each is its own kernel
+    instantiation, with its own pass widths and vector widths."""
+    m, gm, K, _, kap = small
+    x = meshgen.rng_for(86, nrhs).standard_normal((m.n_nodes, 3, nrhs)).astype(dtype)
+    with forced_form(gm, 0, dtype, nrhs, form):
+        y = gm.matvec(to_dev(x, dtype), apply_bc=True).cpu().numpy().astype(np.float64)
+    xr = x.astype(np.float64)
+    assert_close_bound(y, fem.matvec_bc(K, xr, m.fixed), abs(K), xr, dtype, kap,
+                       f"P K P x {dtype.__name__} n={nrhs} form={form}")
+
+
+@pytest.mark.parametrize("form", FORMS_V)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_matvec_with_dirichlet_projection(small, dtype, form):
     m, gm, K, _, kap = small
     x = meshgen.rng_for(81, 0).standard_normal((m.n_nodes, 3, 5)).astype(dtype)
