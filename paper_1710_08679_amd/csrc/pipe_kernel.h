@@ -329,7 +329,8 @@ __attribute__((amdgpu_waves_per_eu(pipe_waves_per_simd<T>(NR, ORDER, GEO, NP))))
         if (pass == NP - 1 && pn < stop) fetch_late();
       }
       // E. write back this pass, zeroing F behind it.  Coloured form with
-      // the geometry read per work-item: the rows that are read, added to
+      // the geometry read per work-item, at 8 or more cases (at 4, FP64, it
+      // measured 15% slower): the rows that are read, added to
       // and written back (nodes an earlier colour wrote, or y += K x) are all
       // read before the first store, so the reads do not wait for this
       // patch's stores (64^3 cube, 16 cases: 0.685 -> 0.669 ms FP32, 1.385 ->
@@ -340,7 +341,7 @@ __attribute__((amdgpu_waves_per_eu(pipe_waves_per_simd<T>(NR, ORDER, GEO, NP))))
       // larger than the last-level cache at 16 cases, and keeping x there
       // instead measured faster (FP32 16 cases, bench.py's timing: coloured
       // 0.667-0.680 -> 0.651-0.669 ms, pipelined 0.703-0.706 -> 0.687-0.689).
-      constexpr bool kReadFirst = COLOUR && !GEO;
+      constexpr bool kReadFirst = COLOUR && !GEO && NR >= 8;
       V old[kReadFirst ? KIT : 1];
 #pragma unroll
       for (int k = 0; k < (kReadFirst ? KIT : 0); ++k) {
